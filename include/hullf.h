@@ -1,0 +1,175 @@
+/*
+ * hullf.h -- C ABI of the MI355X (gfx950) octagon filter and convex hull.
+ *
+ * Method: Carrasco, Ferrada, Navarro, Hitschfeld, "An Evaluation of GPU
+ * Filters for Accelerating the 2D Convex Hull" (arXiv 2303.10581),
+ * Algorithm 1: findingPolygon (Sec. 3.1), buildingFilter (Sec. 3.2),
+ * compactingFilteredPoints (Sec. 3.2, Sec. 4.1.1), convexHull_algorithm
+ * (Sec. 3.3).
+ *
+ * Conventions shared by every entry point
+ *  - Points are FP32 (x, y) pairs stored as an array of hullf_pt (8 bytes
+ *    each, x first).  Device arrays must be at least 8-byte aligned; 16-byte
+ *    alignment enables the vectorised loads.
+ *  - "d_" arguments are device pointers, "h_" arguments host pointers.  The
+ *    caller owns every input and output buffer; the library never frees or
+ *    keeps caller memory beyond the call (the batched graph cache keeps the
+ *    pointer values, see hull_filter_batched).
+ *  - "stream" is a hipStream_t (NULL = the default stream).  Asynchronous
+ *    calls only enqueue work; synchronous ones return after the stream has
+ *    drained up to their last operation.
+ *  - A context serialises its own scratch memory: calls that share one
+ *    context must be issued from one host thread and on one stream (or be
+ *    ordered by the caller).  Different contexts are independent.
+ *  - Errors come back as hullf_status; nothing aborts or throws.  After
+ *    HULLF_EDEVICE the context stays usable if the device still is.
+ *  - n counts points.  n must be below 2^32 (indices are uint32).
+ *
+ * Extremes (Sec. 3.1).  E0..E7 are, counter-clockwise from the right-most
+ * point: max x, max fl32(x+y), max y, max fl32(y-x), min x, min fl32(x+y),
+ * min y, max fl32(x-y).  The corner keys are the Manhattan distance to the
+ * bounding-box corner up to a constant.  Ties go to the lowest index, and
+ * -0 equals +0.
+ *
+ * Inside test (Sec. 3.2).  For each edge (a, b) = (E_j, E_j+1) whose end
+ * points differ, with binary64 operations and no fused multiply-add:
+ *   ex=bx-ax ey=by-ay qx=px-ax qy=py-ay l=ex*qy r=ey*qx det=l-r
+ *   bnd=(3+16e)e*(|l|+|r|), e=2^-53;  strictly inside iff det > bnd.
+ * A point is discarded iff it is strictly inside every such edge (and one
+ * exists).  Every other point survives, so points on or within rounding
+ * distance of the boundary are kept: the filter never drops a hull vertex.
+ *
+ * Hull (Sec. 3.3).  Strict vertices (no collinear or repeated points), the
+ * lowest index per repeated coordinate, counter-clockwise, starting at the
+ * lexicographically smallest (x, y), no closing repeat.  One distinct point
+ * gives one vertex; collinear points give the two end points.
+ */
+#ifndef HULLF_H
+#define HULLF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    float x, y;
+} hullf_pt;
+
+typedef struct hullf_ctx *hullf_ctx_t;
+
+typedef enum {
+    HULLF_OK = 0,
+    HULLF_EINVAL = 1,      /* bad argument: null pointer, n >= 2^32, misaligned */
+    HULLF_ENONFINITE = 2,  /* an input coordinate is NaN or infinite */
+    HULLF_ECAPACITY = 3,   /* output capacity too small; the count is still written */
+    HULLF_ENOMEM = 4,      /* device or host allocation failed */
+    HULLF_EDEVICE = 5      /* a HIP runtime call failed */
+} hullf_status;
+
+/* Written to *d_count by the asynchronous calls when an input coordinate is
+ * not finite (they cannot return HULLF_ENONFINITE without a host sync). */
+#define HULLF_COUNT_NONFINITE UINT64_MAX
+/* Written to a batched count when d_off is not a valid offset array
+ * (d_off[0] != 0, decreasing, or d_off[S] != n_total). */
+#define HULLF_COUNT_BAD_OFFSETS (UINT64_MAX - 1)
+/* Written when the device reduction produced no vertex for a direction
+ * (an internal error; never expected). */
+#define HULLF_COUNT_INTERNAL (UINT64_MAX - 2)
+
+/* Create a context on HIP device `device`; it owns the scratch memory
+ * (look-back tile status, reduction slots, octagon record, survivor staging)
+ * and the tuned launch shapes.  *out is set only on HULLF_OK. */
+hullf_status hullf_create(int device, hullf_ctx_t *out);
+
+/* Release the context and its device memory.  NULL is ignored. */
+void hullf_destroy(hullf_ctx_t ctx);
+
+/* Static string for a status code. */
+const char *hullf_status_str(hullf_status s);
+
+/* Step findingPolygon of Algorithm 1 (Sec. 3.1), synchronous.
+ * d_pts: n >= 1 device points.  idx_out: host array of 8 indices E0..E7.
+ * Returns HULLF_ENONFINITE if a coordinate is not finite, HULLF_EINVAL for
+ * n == 0. */
+hullf_status hullf_octagon(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
+                           uint32_t idx_out[8], void *stream);
+
+/* Steps findingPolygon, buildingFilter and compactingFilteredPoints of
+ * Algorithm 1 (Sec. 3.1, 3.2, 4.1.1), asynchronous on `stream`.
+ * d_surv: device array receiving the ascending indices of the surviving
+ * points; at most `cap` entries are written (cap >= n always suffices).
+ * d_count: one device uint64 receiving the number of survivors (also when it
+ * exceeds cap), or HULLF_COUNT_NONFINITE.  n == 0 writes 0. */
+hullf_status hull_filter(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
+                         uint32_t *d_surv, uint64_t cap, uint64_t *d_count,
+                         void *stream);
+
+/* Algorithm 1 end to end, synchronous: hull_filter, then the monotone-chain
+ * hull (Sec. 3.3) of the survivors on the host.
+ * h_hull: host array receiving the counter-clockwise vertex indices (into
+ * d_pts) with capacity `cap`; *h_count receives the vertex count.  Returns
+ * HULLF_ECAPACITY (with *h_count set) if cap is too small. */
+hullf_status convex_hull(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
+                         uint32_t *h_hull, uint64_t cap, uint64_t *h_count,
+                         void *stream);
+
+/* Debug export of the bit vector of Sec. 3.2 (one byte per point, 1 =
+ * survives), asynchronous.  d_flags: n device bytes.  If a coordinate is not
+ * finite every flag is set to 2. */
+hullf_status hullf_flags(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
+                         uint8_t *d_flags, void *stream);
+
+/* Many independent point sets in one persistent launch (Algorithm 1 per
+ * set), asynchronous, replayed from a cached HIP graph.
+ * d_pts: all sets back to back; d_off: S+1 device uint64 CSR offsets
+ * (set s is d_pts[d_off[s] .. d_off[s+1])), d_off[0] == 0 and
+ * d_off[S] == n_total (host value, the caller sized d_pts with it).
+ * d_surv: n_total device uint32; the survivors of set s are written as
+ * set-local ascending indices at d_surv + d_off[s].
+ * d_counts: S device uint64, survivors per set (HULLF_COUNT_NONFINITE for a
+ * set with a non-finite coordinate).  Sets may be empty.
+ * The graph cache is keyed by the argument values; a new key captures a new
+ * graph. */
+hullf_status hull_filter_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
+                                 const uint64_t *d_off, uint32_t S,
+                                 uint64_t n_total, uint32_t *d_surv,
+                                 uint64_t *d_counts, void *stream);
+
+/* Same work as hull_filter_batched, launched directly (no graph), with an
+ * explicit launch shape.  block in {256, 512}, ppt (points per thread per
+ * tile) in {8, 16, 32}; 0 picks the tuned or default value. */
+hullf_status hull_filter_batched_shape(hullf_ctx_t ctx, const hullf_pt *d_pts,
+                                       const uint64_t *d_off, uint32_t S,
+                                       uint64_t n_total, uint32_t *d_surv,
+                                       uint64_t *d_counts, int block, int ppt,
+                                       void *stream);
+
+/* Autotuner: time every supported (block, ppt) shape of the batched kernel
+ * on the given batch (`reps` launches each, after one warm-up), keep the
+ * fastest in the context for later batched calls, and report it.
+ * best_block / best_ppt / best_ms may be NULL.  Synchronous. */
+hullf_status hullf_autotune_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
+                                    const uint64_t *d_off, uint32_t S,
+                                    uint64_t n_total, uint32_t *d_surv,
+                                    uint64_t *d_counts, int reps,
+                                    int *best_block, int *best_ppt,
+                                    float *best_ms, void *stream);
+
+/* Per-kernel device timing.  When enabled, every kernel the library
+ * launches is bracketed by HIP events on its stream.  hullf_timing_read
+ * waits for those events and returns, per kernel kind, the number of
+ * launches and their summed duration in milliseconds, then clears them.
+ * kinds: 0 = extremes reduction, 1 = inside test + compaction,
+ * 2 = batched persistent kernel.  Arrays hold at least 3 entries. */
+hullf_status hullf_timing_enable(hullf_ctx_t ctx, int enable);
+hullf_status hullf_timing_read(hullf_ctx_t ctx, uint64_t *launches,
+                               double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HULLF_H */

@@ -1,0 +1,22 @@
+// Host monotone-chain hull (Sec. 3.3) used by convex_hull().
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace hullf {
+
+struct HostPt {
+    float x, y;
+    uint32_t i;
+};
+
+// Strict counter-clockwise hull of p (reordered in place) starting at the
+// lexicographically smallest point; the lowest index is kept per repeated
+// coordinate pair.
+void monotone_chain(std::vector<HostPt>& p, std::vector<uint32_t>& out);
+
+// Exact sign of (a-o) x (b-o) for FP32 points.
+int orient_sign(float ox, float oy, float ax, float ay, float bx, float by);
+
+}  // namespace hullf

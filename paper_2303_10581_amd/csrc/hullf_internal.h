@@ -1,0 +1,107 @@
+// Internal interface between the HIP kernels (hullf_kernels.hip) and the
+// host runtime (hullf_runtime.cpp).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hullf {
+
+// Octagon record computed on the device from the eight extremes (Sec. 3.1)
+// and read by every inside-test kernel (Sec. 3.2).
+//
+// Edges: the non-degenerate directed edges (E_j, E_j+1) in binary64
+// (vertex a, difference b-a); unused slots repeat edge 0 so that loops can
+// always run over 8 entries.
+// Prefilter (fast == 1): for each edge, FP32 coefficients of the edge line
+// scaled by a power of two s_e so that the FP32 evaluation
+//   d_e = fma(A, y - cy, fma(NB, x - cx, C0))
+// is within 0.5 of s_e times the exact edge value (see setup_octagon).
+// Quick-accept box (bxl < x < bxh, byl < y < byh): every point inside it is
+// discarded by the binary64 rule; empty when bxl > bxh.
+struct alignas(16) Octagon {
+    uint32_t idx[8];
+    int32_t status;   // 0 ok, 1 non-finite input, 3 internal error (no candidate)
+    int32_t mode;     // 0 keep every point (fewer than 3 distinct vertices), 1 test
+    int32_t fast;     // FP32 prefilter usable
+    int32_t m;        // number of non-degenerate edges
+    float bxl, bxh, byl, byh;
+    float cx, cy, pad0, pad1;
+    float A[8], NB[8], C0[8];
+    double ax[8], ay[8], ex[8], ey[8];
+};
+
+// Cross-block reduction state of one point set.  key[j] holds the packed
+// (ordered key, ~index) maximum of direction j; the last block to finish
+// (counted in `done`) builds the octagon and resets the record.
+struct alignas(16) ReduceSlots {
+    unsigned long long key[8];
+    uint32_t nonfinite;
+    uint32_t done;
+    uint32_t ticket;   // tile ticket of the inside-test/compaction kernel
+    uint32_t ready;    // batched kernel: octagon of this set published
+};
+
+// Per-set bookkeeping of the batched persistent kernel.
+struct alignas(16) SetInfo {
+    uint64_t begin;        // first point of the set
+    uint64_t n;            // points in the set
+    uint32_t r_tiles;      // reduction tiles
+    uint32_t f_tiles;      // inside-test/compaction tiles
+    uint32_t r_tile0;      // reduction tiles of all earlier sets
+    uint32_t f_tile0;      // compaction tiles of all earlier sets (status array offset)
+    uint32_t r_done;       // reduction tiles finished
+    uint32_t pad;
+};
+
+// Batched work list: segment k covers tickets [start[k], start[k+1]) and is
+// either the reduction tiles or the compaction tiles of one set.
+struct BatchPlan {
+    uint32_t* seg_start;   // 2S+1
+    uint32_t* seg_code;    // 2S: set index << 1 | (1 = compaction)
+};
+
+constexpr uint64_t kFlagA = 1ull << 62;
+constexpr uint64_t kFlagP = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr uint64_t kCountNonFinite = ~0ull;
+constexpr uint64_t kCountBadOffsets = ~0ull - 1;
+constexpr uint64_t kCountInternal = ~0ull - 2;
+
+struct Shape {
+    int block;
+    int ppt;
+};
+
+// Launchers (all asynchronous on `stream`; return the launch error).
+hipError_t launch_init_slots(ReduceSlots* slots, uint32_t count, hipStream_t stream);
+hipError_t launch_reduce(const float2* pts, uint64_t n, ReduceSlots* slots, Octagon* oct,
+                         uint64_t* tile_status, uint32_t num_tiles, int grid, hipStream_t stream);
+hipError_t launch_filter(const float2* pts, uint64_t n, const Octagon* oct, ReduceSlots* slots,
+                         uint64_t* tile_status, uint32_t num_tiles, uint32_t* surv, uint64_t cap,
+                         uint64_t* count, Shape shape, int grid, hipStream_t stream);
+hipError_t launch_flags(const float2* pts, uint64_t n, const Octagon* oct, uint8_t* flags,
+                        int grid, hipStream_t stream);
+hipError_t launch_write_count(uint64_t* count, uint64_t value, hipStream_t stream);
+hipError_t launch_gather(const float2* pts, const uint32_t* surv, const uint64_t* count,
+                         uint64_t cap, uint64_t n, float2* out, int grid, hipStream_t stream);
+
+uint32_t filter_tile_points(Shape shape);
+uint32_t reduce_chunk_points();
+bool shape_supported(Shape shape);
+
+// Batched: plan construction (one block) and the persistent kernel.
+hipError_t launch_batch_plan(const uint64_t* off, uint32_t S, SetInfo* sets, ReduceSlots* slots,
+                             uint32_t* seg_start, uint32_t* seg_code, uint32_t* ticket,
+                             uint32_t* total_tickets, uint64_t* tile_status, uint32_t max_tiles,
+                             uint64_t lag_points, uint64_t n_total, uint64_t* counts, Shape shape,
+                             hipStream_t stream);
+uint64_t batch_max_tiles(uint64_t n_total, uint32_t S, Shape shape);
+hipError_t launch_batch_persistent(const float2* pts, uint32_t S, const SetInfo* sets,
+                                   ReduceSlots* slots, Octagon* octs, const uint32_t* seg_start,
+                                   const uint32_t* seg_code, uint32_t* ticket,
+                                   const uint32_t* total_tickets, uint64_t* tile_status,
+                                   uint32_t* surv, uint64_t* counts, Shape shape, int grid,
+                                   hipStream_t stream);
+
+}  // namespace hullf

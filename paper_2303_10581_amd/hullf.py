@@ -1,0 +1,216 @@
+"""Python binding of libhullf.so (C ABI in include/hullf.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels (and, for convex_hull, its host monotone chain).  PyTorch provides
+device memory and streams.  There is no fallback: if the library is missing,
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhullf.so")
+
+OK, EINVAL, ENONFINITE, ECAPACITY, ENOMEM, EDEVICE = range(6)
+COUNT_NONFINITE = (1 << 64) - 1
+COUNT_BAD_OFFSETS = (1 << 64) - 2
+
+_lib = None
+
+
+class HullfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {_load().hullf_status_str(status).decode()} (status {status})")
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2303_10581_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, U64, U32, I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    st = ctypes.c_int
+    sig = {
+        "hullf_create": ([I, ctypes.POINTER(P)], st),
+        "hullf_destroy": ([P], None),
+        "hullf_status_str": ([st], ctypes.c_char_p),
+        "hullf_octagon": ([P, P, U64, P, P], st),
+        "hull_filter": ([P, P, U64, P, U64, P, P], st),
+        "convex_hull": ([P, P, U64, P, U64, P, P], st),
+        "hullf_flags": ([P, P, U64, P, P], st),
+        "hull_filter_batched": ([P, P, P, U32, U64, P, P, P], st),
+        "hull_filter_batched_shape": ([P, P, P, U32, U64, P, P, I, I, P], st),
+        "hullf_autotune_batched": ([P, P, P, U32, U64, P, P, I, P, P, P, P], st),
+        "hullf_timing_enable": ([P, I], st),
+        "hullf_timing_read": ([P, P, P], st),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise HullfError(status, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _points(pts):
+    torch = _torch()
+    if not isinstance(pts, torch.Tensor) or not pts.is_cuda:
+        raise TypeError("points must be a CUDA tensor")
+    if pts.dtype != torch.float32 or pts.dim() != 2 or pts.shape[1] != 2 or not pts.is_contiguous():
+        raise TypeError("points must be a contiguous float32 tensor of shape (n, 2)")
+    return pts
+
+
+class Context:
+    """Owns a hullf context (scratch memory, tuned shapes, graph cache)."""
+
+    def __init__(self, device: int = 0):
+        lib = _load()
+        h = ctypes.c_void_p()
+        _check(lib.hullf_create(int(device), ctypes.byref(h)), "hullf_create")
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if self.handle:
+            _load().hullf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- steps ---------------------------------------------------------------
+    def octagon(self, pts, stream=None) -> np.ndarray:
+        """Indices E0..E7 of the octagon vertices (synchronous)."""
+        pts = _points(pts)
+        out = np.zeros(8, dtype=np.uint32)
+        _check(_load().hullf_octagon(self.handle, pts.data_ptr(), pts.shape[0], out.ctypes.data,
+                                     _stream(stream)), "hullf_octagon")
+        return out
+
+    def hull_filter(self, pts, surv=None, count=None, cap=None, stream=None):
+        """Enqueue the filter; returns (surv uint32[cap], count uint64[1]) device tensors."""
+        torch = _torch()
+        pts = _points(pts)
+        n = pts.shape[0]
+        if surv is None:
+            surv = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+        if count is None:
+            count = torch.empty(1, dtype=torch.int64, device=pts.device)
+        if cap is None:
+            cap = surv.numel()
+        _check(_load().hull_filter(self.handle, pts.data_ptr(), n, surv.data_ptr(), int(cap),
+                                   count.data_ptr(), _stream(stream)), "hull_filter")
+        return surv, count
+
+    def survivors(self, pts, stream=None):
+        """Ascending survivor indices as an int32 device tensor (synchronises)."""
+        surv, count = self.hull_filter(pts, stream=stream)
+        c = int(count.item()) & ((1 << 64) - 1)
+        if c == COUNT_NONFINITE:
+            raise HullfError(ENONFINITE, "hull_filter")
+        return surv[:c]
+
+    def flags(self, pts, stream=None):
+        """One byte per point: 1 survives, 0 discarded, 2 non-finite input."""
+        torch = _torch()
+        pts = _points(pts)
+        out = torch.empty(pts.shape[0], dtype=torch.uint8, device=pts.device)
+        _check(_load().hullf_flags(self.handle, pts.data_ptr(), pts.shape[0], out.data_ptr(),
+                                   _stream(stream)), "hullf_flags")
+        return out
+
+    def convex_hull(self, pts, stream=None) -> np.ndarray:
+        """Counter-clockwise hull vertex indices (synchronous)."""
+        pts = _points(pts)
+        n = pts.shape[0]
+        cap = max(n, 1)
+        out = np.zeros(cap, dtype=np.uint32)
+        h = ctypes.c_uint64(0)
+        _check(_load().convex_hull(self.handle, pts.data_ptr(), n, out.ctypes.data, cap,
+                                   ctypes.byref(h), _stream(stream)), "convex_hull")
+        return out[:h.value].copy()
+
+    # -- batched -------------------------------------------------------------
+    def hull_filter_batched(self, pts, off, n_total=None, surv=None, counts=None, stream=None,
+                            block=None, ppt=None):
+        """Enqueue the batched filter.  off: uint64/int64 device tensor (S+1).
+        Returns (surv int32[n_total], counts int64[S]); survivors of set s are
+        set-local indices at surv[off[s]:off[s]+counts[s]].  With block/ppt
+        given, launches that shape directly instead of the cached graph."""
+        torch = _torch()
+        pts = _points(pts)
+        S = off.numel() - 1
+        if n_total is None:
+            n_total = pts.shape[0]
+        if surv is None:
+            surv = torch.empty(max(n_total, 1), dtype=torch.int32, device=pts.device)
+        if counts is None:
+            counts = torch.empty(max(S, 1), dtype=torch.int64, device=pts.device)
+        lib = _load()
+        if block is None and ppt is None:
+            st = lib.hull_filter_batched(self.handle, pts.data_ptr(), off.data_ptr(), S, int(n_total),
+                                         surv.data_ptr(), counts.data_ptr(), _stream(stream))
+        else:
+            st = lib.hull_filter_batched_shape(self.handle, pts.data_ptr(), off.data_ptr(), S,
+                                               int(n_total), surv.data_ptr(), counts.data_ptr(),
+                                               int(block or 0), int(ppt or 0), _stream(stream))
+        _check(st, "hull_filter_batched")
+        return surv, counts
+
+    def autotune_batched(self, pts, off, surv, counts, reps: int = 3, stream=None):
+        """Pick the fastest (block, ppt) for the batched kernel; returns
+        (block, ppt, ms)."""
+        pts = _points(pts)
+        S = off.numel() - 1
+        b, p, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_float(0)
+        _check(_load().hullf_autotune_batched(self.handle, pts.data_ptr(), off.data_ptr(), S,
+                                              pts.shape[0], surv.data_ptr(), counts.data_ptr(), reps,
+                                              ctypes.byref(b), ctypes.byref(p), ctypes.byref(ms),
+                                              _stream(stream)), "hullf_autotune_batched")
+        return b.value, p.value, ms.value
+
+    # -- timing --------------------------------------------------------------
+    def timing(self, enable: bool):
+        _check(_load().hullf_timing_enable(self.handle, 1 if enable else 0), "hullf_timing_enable")
+
+    def timing_read(self):
+        """{kind: (launches, total_ms)} for kinds reduce, filter, batched."""
+        launches = (ctypes.c_uint64 * 3)()
+        ms = (ctypes.c_double * 3)()
+        _check(_load().hullf_timing_read(self.handle, launches, ms), "hullf_timing_read")
+        return {k: (launches[i], ms[i]) for i, k in enumerate(("reduce", "filter", "batched"))}
+
+
+def exported_symbols():
+    """Names of the C-ABI functions the binding expects."""
+    return ["hullf_create", "hullf_destroy", "hullf_status_str", "hullf_octagon", "hull_filter",
+            "convex_hull", "hullf_flags", "hull_filter_batched", "hull_filter_batched_shape",
+            "hullf_autotune_batched", "hullf_timing_enable", "hullf_timing_read"]

@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer/index results are compared bit for bit: the eight octagon vertex
+indices, the ascending survivor index list and its count, and the
+counter-clockwise hull index list.  Sizes span many tiles and ragged tails;
+the full-size cases use the shapes the benchmark times."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_10581_amd import hullf, workloads
+from tests import cases
+from tests.gpu_common import ctx, say, survivors_np, torch_dev, upload  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_all(ctx, dev, xy, name, hull=True, offset=0):
+    say(f"[gpu] {name}: n={xy.shape[0]} offset={offset}")
+    t = upload(xy, dev, offset)
+    want_idx = oracle.extremes(xy)
+    assert ctx.octagon(t).tolist() == want_idx.tolist(), name
+    want = oracle.survivors(xy)
+    got = survivors_np(ctx, t)
+    assert got.shape == want.shape, (name, got.shape, want.shape)
+    assert np.array_equal(got, want), name
+    flags = ctx.flags(t).cpu().numpy()
+    assert np.array_equal(np.flatnonzero(flags == 1).astype(np.uint32), want), name
+    if hull:
+        h = ctx.convex_hull(t)
+        assert np.array_equal(h, oracle.hull(xy, want)), name
+
+
+@pytest.mark.parametrize("name,xy,case", cases.golden_cases(), ids=lambda v: v if isinstance(v, str) else "")
+def test_golden(ctx, torch_dev, name, xy, case):
+    t = upload(xy, torch_dev)
+    assert ctx.octagon(t).tolist() == case["extremes"]
+    assert survivors_np(ctx, t).tolist() == case["survivors"]
+    if "hull" in case:
+        assert ctx.convex_hull(t).tolist() == case["hull"]
+
+
+@pytest.mark.parametrize("kind", ["normal", "circle", "displaced", "circle_jitter", "normal_far",
+                                  "displaced_huge", "displaced_tiny", "subnormal", "grid",
+                                  "collinear_h", "collinear_diag", "all_equal"])
+def test_named_sets(ctx, torch_dev, kind):
+    # 200003 points: ~49 compaction tiles of 4096 and a ragged tail
+    xy = cases.named_sets(200003, 17)[kind]
+    _check_all(ctx, torch_dev, xy, kind)
+
+
+@pytest.mark.parametrize("kind", ["normal", "displaced", "circle_jitter", "normal_far",
+                                  "displaced_huge", "displaced_tiny", "subnormal"])
+def test_near_edge_adversarial(ctx, torch_dev, kind):
+    base = cases.named_sets(50000, 23)[kind]
+    xy = cases.with_near_edge_points(base, oracle.extremes, per_edge=4000, seed=9)
+    _check_all(ctx, torch_dev, xy, "near-edge " + kind)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 63, 64, 65, 4095, 4096, 4097, 8191, 12289])
+def test_small_and_ragged_sizes(ctx, torch_dev, n):
+    for kind in ("normal", "circle"):
+        xy = workloads.by_kind(kind, n, 100 + n)
+        _check_all(ctx, torch_dev, xy, f"{kind} n={n}")
+
+
+def test_misaligned_pointer(ctx, torch_dev):
+    xy = workloads.displaced(100001, 5)
+    _check_all(ctx, torch_dev, xy, "displaced misaligned", offset=1)
+
+
+def test_empty_input(ctx, torch_dev):
+    import torch
+    t = torch.zeros((0, 2), dtype=torch.float32, device=torch_dev)
+    surv, count = ctx.hull_filter(t)
+    assert int(count.item()) == 0
+    assert ctx.convex_hull(t).size == 0
+    with pytest.raises(hullf.HullfError) as e:
+        ctx.octagon(t)
+    assert e.value.status == hullf.EINVAL
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+@pytest.mark.parametrize("where", [0, 12345, 99999])
+def test_nonfinite(ctx, torch_dev, bad, where):
+    xy = workloads.normal(100000, 3)
+    xy[where, where % 2] = bad
+    t = upload(xy, torch_dev)
+    say(f"[gpu] nonfinite {bad} at {where}")
+    surv, count = ctx.hull_filter(t)
+    assert (int(count.item()) & ((1 << 64) - 1)) == hullf.COUNT_NONFINITE
+    with pytest.raises(hullf.HullfError) as e:
+        ctx.convex_hull(t)
+    assert e.value.status == hullf.ENONFINITE
+    with pytest.raises(hullf.HullfError) as e:
+        ctx.octagon(t)
+    assert e.value.status == hullf.ENONFINITE
+    assert (ctx.flags(t).cpu().numpy() == 2).all()
+    # the context stays usable
+    ok = workloads.normal(1000, 4)
+    assert np.array_equal(survivors_np(ctx, upload(ok, torch_dev)), oracle.survivors(ok))
+
+
+def test_overflowing_keys_are_legal(ctx, torch_dev):
+    # x + y overflows to +-inf for finite inputs: a legal key, not an error
+    xy = workloads.normal(5000, 8) * np.float32(3e38 / 6)
+    xy[10] = [3.0e38, 3.0e38]
+    xy[11] = [-3.0e38, -3.0e38]
+    _check_all(ctx, torch_dev, xy.astype(np.float32), "overflowing keys")
+
+
+def test_capacity_smaller_than_count(ctx, torch_dev):
+    import torch
+    xy = workloads.circle(50000, 6)
+    want = oracle.survivors(xy)
+    t = upload(xy, torch_dev)
+    cap = 1000
+    surv = torch.full((cap + 16,), -1, dtype=torch.int32, device=torch_dev)
+    _, count = ctx.hull_filter(t, surv=surv, cap=cap)
+    assert int(count.item()) == want.size
+    got = surv.cpu().numpy()
+    assert np.array_equal(got[:cap].astype(np.uint32), want[:cap])
+    assert (got[cap:] == -1).all()
+    out_cap = 3
+    with pytest.raises(hullf.HullfError) as e:
+        import ctypes
+        buf = np.zeros(out_cap, np.uint32)
+        h = ctypes.c_uint64(0)
+        st = hullf._load().convex_hull(ctx.handle, t.data_ptr(), t.shape[0], buf.ctypes.data, out_cap,
+                                        ctypes.byref(h), hullf._stream(None))
+        assert h.value == oracle.hull(xy, want).size
+        hullf._check(st, "convex_hull")
+    assert e.value.status == hullf.ECAPACITY
+
+
+def test_repeated_calls_same_context(ctx, torch_dev):
+    # the reduction slots and look-back state are reset between calls
+    for seed in range(4):
+        for kind in ("normal", "circle", "displaced"):
+            xy = workloads.by_kind(kind, 30011 + 977 * seed, seed)
+            t = upload(xy, torch_dev)
+            assert np.array_equal(survivors_np(ctx, t), oracle.survivors(xy)), (kind, seed)
+
+
+def test_config_small_normal_1e6(ctx, torch_dev):
+    xy = workloads.normal(1_000_000, 1)
+    _check_all(ctx, torch_dev, xy, "normal 1e6 seed 1")
+
+
+@pytest.mark.parametrize("kind,seed", [("normal", 2), ("circle", 3), ("displaced", 4)])
+def test_full_size_1e8(ctx, torch_dev, kind, seed):
+    n = 100_000_000
+    say(f"[gpu] full size {kind} n={n} seed={seed}")
+    xy = workloads.by_kind(kind, n, seed)
+    t = upload(xy, torch_dev)
+    assert ctx.octagon(t).tolist() == oracle.extremes(xy).tolist()
+    want = oracle.survivors(xy)
+    got = survivors_np(ctx, t)
+    assert got.size == want.size and np.array_equal(got, want)
+    if kind == "normal":
+        assert np.array_equal(ctx.convex_hull(t), oracle.hull(xy, want))
+    del t
+
+
+def test_full_size_5e8_circle_jitter(ctx, torch_dev):
+    n = 500_000_000
+    say(f"[gpu] full size circle_jitter n={n} seed=5")
+    xy = workloads.circle_jitter(n, 5, 0.01)
+    t = upload(xy, torch_dev)
+    want = oracle.survivors(xy)
+    got = survivors_np(ctx, t)
+    assert got.size == want.size and np.array_equal(got, want)
+    del t
