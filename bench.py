@@ -1,0 +1,362 @@
+#!/usr/bin/env python3
+"""Benchmark of the octagon filter (Algorithm 1, steps findingPolygon +
+buildingFilter + compactingFilteredPoints) on one MI355X.
+
+Workload (one step): the three 1e8-point FP32 sets of the paper's study
+cases, already resident in HBM -- N(0,1) normal (seed 2), unit circle
+(seed 3), circle with radius 1 + U[-0.05, 0.05] (seed 4).  A step runs
+hull_filter on each set (2 kernels per set: extremes reduction, inside
+test + compaction).  value = points filtered per second over the timed
+steps (Gpoints/s).
+
+Printed: ONE JSON line with the metric, the roofline of the dominant kernel
+(measured live with HIP events on the launch stream), the CPU oracle timed on
+a bounded sample on this host, end-to-end hull times (host finishing
+included) and the batched-launch comparison.
+
+Extra modes:
+  --profile-pass     a short run for rocprofv3 (also a 1 GB copy kernel for
+                     counter calibration)
+  --parse-pmc DIR    read rocprofv3 --pmc output(s) and print per-kernel
+                     FETCH_SIZE / WRITE_SIZE bytes per dispatch
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "filtered Gpoints/s + % HBM peak; batched hulls/s vs per-set launch; p50/p99"
+HBM_PEAK_GBS = 8000.0
+N_SET = 100_000_000
+SETS = (("normal", 2), ("circle", 3), ("displaced", 4))
+KERNEL_SRC = os.path.join(ROOT, "paper_2303_10581_amd", "csrc", "hullf_kernels.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def make_sets():
+    from paper_2303_10581_amd import workloads
+    out = []
+    for kind, seed in SETS:
+        t0 = time.time()
+        xy = workloads.by_kind(kind, N_SET, seed)
+        log(f"[bench] generated {kind} n={N_SET} seed={seed} in {time.time() - t0:.1f}s")
+        out.append((kind, seed, xy))
+    return out
+
+
+def algorithmic_bytes(n: int, survivors: int):
+    """Bytes the method must move: reduction reads 8 B/pt; the fused inside
+    test + compaction reads 8 B/pt and writes 4 B per survivor."""
+    return {"reduce": 8 * n, "filter": 8 * n + 4 * survivors}
+
+
+def cpu_baseline(sets, budget_s: float = 15.0):
+    """The oracle (single-threaded C) on a bounded prefix of each set."""
+    import oracle
+    oracle.build()
+    probe = sets[0][2][:1_000_000]
+    t0 = time.perf_counter()
+    oracle.survivors(probe)
+    rate = probe.shape[0] / max(time.perf_counter() - t0, 1e-6)
+    m = int(min(N_SET, max(1_000_000, budget_s * rate / len(sets))))
+    pts = 0
+    t0 = time.perf_counter()
+    for _, _, xy in sets:
+        oracle.survivors(xy[:m])
+        pts += m
+    dt = time.perf_counter() - t0
+    return {"value": pts / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m} points of each of the 3 sets ({pts} points, {dt:.1f} s, single thread)"}
+
+
+def stored_traffic():
+    """Measured HBM bytes per dispatch (rocprofv3 FETCH_SIZE/WRITE_SIZE scaled
+    by a copy-kernel calibration), or None if absent or taken on other code."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha") != kernel_hash():
+        return None
+    return d
+
+
+def run_bench(args):
+    import torch
+    from paper_2303_10581_amd import hullf
+
+    dev = torch.device("cuda:0")
+    sets = make_sets()
+    ctx = hullf.Context(0)
+    stream = torch.cuda.current_stream()
+    dpts, surv, cnt = [], [], []
+    for kind, seed, xy in sets:
+        dpts.append(torch.from_numpy(xy).to(dev))
+        surv.append(torch.empty(N_SET, dtype=torch.int32, device=dev))
+        cnt.append(torch.empty(1, dtype=torch.int64, device=dev))
+    torch.cuda.synchronize()
+
+    def step():
+        for i in range(len(sets)):
+            ctx.hull_filter(dpts[i], surv=surv[i], count=cnt[i], stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    survivors = [int(c.item()) for c in cnt]
+
+    ctx.timing(True)
+    ctx.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = ctx.timing_read()
+    ctx.timing(False)
+
+    # per-pass, per-set breakdown (one instrumented pass per set)
+    per_set = {}
+    for i, (kind, _, _) in enumerate(sets):
+        ctx.timing(True)
+        ctx.timing_read()
+        for _ in range(5):
+            ctx.hull_filter(dpts[i], surv=surv[i], count=cnt[i], stream=stream)
+        r = ctx.timing_read()
+        ctx.timing(False)
+        ab = algorithmic_bytes(N_SET, survivors[i])
+        red_ms = r["reduce"][1] / r["reduce"][0]
+        fil_ms = r["filter"][1] / r["filter"][0]
+        per_set[kind] = {
+            "survivors": survivors[i],
+            "reduce_us": round(red_ms * 1e3, 2),
+            "filter_us": round(fil_ms * 1e3, 2),
+            "reduce_GBs": round(ab["reduce"] / red_ms / 1e6, 1),
+            "filter_GBs": round(ab["filter"] / fil_ms / 1e6, 1),
+            "Gpoints_s": round(N_SET / (red_ms + fil_ms) / 1e6, 1),
+            "hbm_frac": round((ab["reduce"] + ab["filter"]) / (red_ms + fil_ms) / 1e6 / HBM_PEAK_GBS, 3),
+        }
+
+    total_pts = N_SET * len(sets) * args.steps
+    value = total_pts / elapsed / 1e9
+    ms_per_step = elapsed * 1e3 / args.steps
+
+    # dominant kernel: the kind with the larger summed device time
+    dom = max(("reduce", "filter"), key=lambda k: kt[k][1])
+    bytes_per_step = sum(algorithmic_bytes(N_SET, s)[dom] for s in survivors)
+    launches, total_ms = kt[dom]
+    per_launch_bytes = bytes_per_step / len(sets)
+    avg_ms = total_ms / launches
+    achieved = per_launch_bytes / avg_ms / 1e6
+    traffic = None
+    st = stored_traffic()
+    if st and dom in st.get("bytes_per_dispatch", {}):
+        traffic = st["bytes_per_dispatch"][dom]
+    all_bytes = sum(sum(algorithmic_bytes(N_SET, s).values()) for s in survivors)
+    step_hbm_frac = all_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "configs[1]: 3 single sets of 1e8 FP32 points -- normal N(0,1) seed 2, "
+                        "circle r=1 seed 3, displaced r=1+U[-0.05,0.05] seed 4; hull_filter per set",
+            "points_per_step": N_SET * len(sets),
+            "filter_shape": {"block": 256, "ppt": 16},
+        },
+        "hbm_frac_step": round(step_hbm_frac, 3),
+        "roofline": {
+            "kernel": "k_filter" if dom == "filter" else "k_reduce",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 3),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": int(per_launch_bytes),
+            "avg_launch_us": round(avg_ms * 1e3, 2),
+        },
+        "passes": per_set,
+    }
+
+    if not args.no_e2e:
+        e2e = {}
+        for i, (kind, _, _) in enumerate(sets):
+            t0 = time.perf_counter()
+            h = ctx.convex_hull(dpts[i])
+            e2e[kind] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "hull_vertices": int(h.size)}
+        result["e2e_hull"] = e2e
+
+    if not args.no_batched:
+        result["batched"] = bench_batched(ctx, dev)
+
+    ctx.close()
+    del dpts, surv
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle")
+        result["cpu_baseline"] = cpu_baseline(sets)
+    return result
+
+
+def bench_batched(ctx, dev):
+    """configs[3]: 4096 sets, log-uniform sizes in [100, 1e6]; one persistent
+    launch (HIP graph) against 4096 plain hull_filter launches."""
+    import torch
+    from paper_2303_10581_amd import workloads
+    t0 = time.time()
+    pts, off, kinds = workloads.batch(S=4096, seed=6)
+    log(f"[bench] generated batch S=4096 n={pts.shape[0]} in {time.time() - t0:.1f}s")
+    S = off.size - 1
+    tp = torch.from_numpy(pts).to(dev)
+    to = torch.from_numpy(off.astype(np.int64)).to(dev)
+    surv = torch.empty(pts.shape[0], dtype=torch.int32, device=dev)
+    counts = torch.empty(S, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    ctx.hull_filter_batched(tp, to, surv=surv, counts=counts, stream=stream)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.hull_filter_batched(tp, to, surv=surv, counts=counts, stream=stream)
+    torch.cuda.synchronize()
+    b_ms = (time.perf_counter() - t0) * 1e3 / reps
+    # plain per-set launches on the same GPU
+    offs = off.tolist()
+    views = [tp[offs[s]:offs[s + 1]] for s in range(S)]
+    c1 = torch.empty(S, dtype=torch.int64, device=dev)
+    for s in range(S):
+        ctx.hull_filter(views[s], surv=surv[offs[s]:], count=c1[s:s + 1], cap=offs[s + 1] - offs[s],
+                        stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(S):
+        ctx.hull_filter(views[s], surv=surv[offs[s]:], count=c1[s:s + 1], cap=offs[s + 1] - offs[s],
+                        stream=stream)
+    torch.cuda.synchronize()
+    p_ms = (time.perf_counter() - t0) * 1e3
+    same = bool(torch.equal(counts, c1))
+    n = int(pts.shape[0])
+    return {
+        "workload": "configs[3]: 4096 sets, sizes log-uniform [1e2, 1e6], kinds uniform, seed 6",
+        "points": n,
+        "batched_ms": round(b_ms, 3),
+        "batched_hulls_per_s": round(S / (b_ms / 1e3), 1),
+        "batched_Gpoints_s": round(n / b_ms / 1e6, 1),
+        "per_set_launch_ms": round(p_ms, 3),
+        "per_set_hulls_per_s": round(S / (p_ms / 1e3), 1),
+        "speedup": round(p_ms / b_ms, 2),
+        "counts_match": same,
+    }
+
+
+def profile_pass(args):
+    """Short run for rocprofv3: a 1 GB copy (counter calibration), then a few
+    filter steps on the three sets."""
+    import torch
+    from paper_2303_10581_amd import hullf
+    dev = torch.device("cuda:0")
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    ctx = hullf.Context(0)
+    for kind, seed, xy in make_sets():
+        t = torch.from_numpy(xy).to(dev)
+        s = torch.empty(N_SET, dtype=torch.int32, device=dev)
+        c = torch.empty(1, dtype=torch.int64, device=dev)
+        for _ in range(args.steps):
+            ctx.hull_filter(t, surv=s, count=c)
+        torch.cuda.synchronize()
+        log(f"[profile] {kind}: survivors {int(c.item())}")
+        del t, s
+    ctx.close()
+
+
+def parse_pmc(directory):
+    """Print FETCH_SIZE / WRITE_SIZE (bytes) per kernel dispatch from
+    rocprofv3 counter_collection CSV files under `directory`."""
+    rows = []
+    for path in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    out = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        cname = r.get("Counter_Name", "")
+        val = float(r.get("Counter_Value", "nan"))
+        key = (r.get("Dispatch_Id", ""), name)
+        out.setdefault(key, {})[cname] = val
+    for (disp, name), ctrs in sorted(out.items(), key=lambda kv: int(kv[0][0] or 0)):
+        short = name.split("(")[0][:60]
+        print(json.dumps({"dispatch": disp, "kernel": short,
+                          **{k: v * 1024.0 for k, v in ctrs.items()}}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-e2e", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--parse-pmc", default=None)
+    args = ap.parse_args()
+    if args.parse_pmc:
+        parse_pmc(args.parse_pmc)
+        return 0
+    ws = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or ws != 1:
+        print("bench.py measures one GPU only: the filter path is built and measured on a single "
+              "MI355X (multi-GPU sharding is a design note, not part of this build). "
+              "Run with --gpus 1.", file=sys.stderr)
+        return 2
+    if args.profile_pass:
+        profile_pass(args)
+        return 0
+    res = run_bench(args)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

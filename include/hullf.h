@@ -163,7 +163,8 @@ hullf_status hullf_autotune_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
  * waits for those events and returns, per kernel kind, the number of
  * launches and their summed duration in milliseconds, then clears them.
  * kinds: 0 = extremes reduction, 1 = inside test + compaction,
- * 2 = batched persistent kernel.  Arrays hold at least 3 entries. */
+ * 2 = batched launch (plan + persistent kernel), 3 = octagon set-up (merge
+ * of the reduction's per-block records).  Arrays hold at least 4 entries. */
 hullf_status hullf_timing_enable(hullf_ctx_t ctx, int enable);
 hullf_status hullf_timing_read(hullf_ctx_t ctx, uint64_t *launches,
                                double *total_ms);

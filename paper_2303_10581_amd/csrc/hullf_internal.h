@@ -31,34 +31,32 @@ struct alignas(16) Octagon {
     double ax[8], ay[8], ex[8], ey[8];
 };
 
-// Cross-block reduction state of one point set.  key[j] holds the packed
-// (ordered key, ~index) maximum of direction j; the last block to finish
-// (counted in `done`) builds the octagon and resets the record.
+// Device state of one single-set call: the compaction tile ticket (reset by
+// the reduction launch).  The remaining fields are kept zero.
 struct alignas(16) ReduceSlots {
     unsigned long long key[8];
     uint32_t nonfinite;
     uint32_t done;
-    uint32_t ticket;   // tile ticket of the inside-test/compaction kernel
-    uint32_t ready;    // batched kernel: octagon of this set published
+    uint32_t ticket;
+    uint32_t ready;
 };
 
-// Per-set bookkeeping of the batched persistent kernel.
+// Per-set bookkeeping of the batched launch (written by the plan kernel).
 struct alignas(16) SetInfo {
     uint64_t begin;        // first point of the set
     uint64_t n;            // points in the set
     uint32_t r_tiles;      // reduction tiles
     uint32_t f_tiles;      // inside-test/compaction tiles
-    uint32_t r_tile0;      // reduction tiles of all earlier sets
+    uint32_t r_tile0;      // reduction tiles of all earlier sets (partial record offset)
     uint32_t f_tile0;      // compaction tiles of all earlier sets (status array offset)
-    uint32_t r_done;       // reduction tiles finished
-    uint32_t pad;
 };
 
-// Batched work list: segment k covers tickets [start[k], start[k+1]) and is
-// either the reduction tiles or the compaction tiles of one set.
-struct BatchPlan {
-    uint32_t* seg_start;   // 2S+1
-    uint32_t* seg_code;    // 2S: set index << 1 | (1 = compaction)
+// Batch-wide totals and the compaction ticket (device).
+struct alignas(16) BatchTotals {
+    uint32_t r_tiles;
+    uint32_t f_tiles;
+    uint32_t ticket;
+    uint32_t pad;
 };
 
 constexpr uint64_t kFlagA = 1ull << 62;
@@ -73,10 +71,17 @@ struct Shape {
     int ppt;
 };
 
+
 // Launchers (all asynchronous on `stream`; return the launch error).
 hipError_t launch_init_slots(ReduceSlots* slots, uint32_t count, hipStream_t stream);
-hipError_t launch_reduce(const float2* pts, uint64_t n, ReduceSlots* slots, Octagon* oct,
+// Extremes of one set in two launches: launch_reduce writes 9 * grid
+// uint64 partial records to `part` (and clears the compaction state);
+// launch_setup merges them and writes the octagon.
+hipError_t launch_reduce(const float2* pts, uint64_t n, ReduceSlots* slots, unsigned long long* part,
                          uint64_t* tile_status, uint32_t num_tiles, int grid, hipStream_t stream);
+hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsigned long long* part,
+                        uint32_t nblocks, hipStream_t stream);
+constexpr int kReduceMaxGrid = 4096;
 hipError_t launch_filter(const float2* pts, uint64_t n, const Octagon* oct, ReduceSlots* slots,
                          uint64_t* tile_status, uint32_t num_tiles, uint32_t* surv, uint64_t cap,
                          uint64_t* count, Shape shape, int grid, hipStream_t stream);
@@ -90,18 +95,13 @@ uint32_t filter_tile_points(Shape shape);
 uint32_t reduce_chunk_points();
 bool shape_supported(Shape shape);
 
-// Batched: plan construction (one block) and the persistent kernel.
-hipError_t launch_batch_plan(const uint64_t* off, uint32_t S, SetInfo* sets, ReduceSlots* slots,
-                             uint32_t* seg_start, uint32_t* seg_code, uint32_t* ticket,
-                             uint32_t* total_tickets, uint64_t* tile_status, uint32_t max_tiles,
-                             uint64_t lag_points, uint64_t n_total, uint64_t* counts, Shape shape,
-                             hipStream_t stream);
+// Batched: plan, reduction, octagon set-up and compaction (four launches).
+// part: 9 * max_rtiles uint64 scratch; tile_status: max_ftiles words.
+hipError_t launch_batch(const float2* pts, const uint64_t* off, uint32_t S, uint64_t n_total, SetInfo* sets,
+                        BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles, Octagon* octs,
+                        uint64_t* tile_status, uint32_t max_ftiles, uint32_t* surv, uint64_t* counts,
+                        Shape shape, int cus, hipStream_t stream);
 uint64_t batch_max_tiles(uint64_t n_total, uint32_t S, Shape shape);
-hipError_t launch_batch_persistent(const float2* pts, uint32_t S, const SetInfo* sets,
-                                   ReduceSlots* slots, Octagon* octs, const uint32_t* seg_start,
-                                   const uint32_t* seg_code, uint32_t* ticket,
-                                   const uint32_t* total_tickets, uint64_t* tile_status,
-                                   uint32_t* surv, uint64_t* counts, Shape shape, int grid,
-                                   hipStream_t stream);
+uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S);
 
 }  // namespace hullf

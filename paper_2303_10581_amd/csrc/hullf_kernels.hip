@@ -16,6 +16,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include "hullf_internal.h"
 
 namespace hullf {
@@ -25,6 +27,7 @@ namespace {
 // Shewchuk (1997) for a 2x2 determinant of differences.
 constexpr double kBoundC = 0x1.8000000000004p-52;
 constexpr float kInfF = __builtin_huge_valf();
+constexpr int kLB = 8;   // look-back groups of 64 predecessors per round
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -88,13 +91,31 @@ __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Buffer resource (V#) over `bytes` bytes at a wave-uniform base: raw
+// buffer, stride 0, gfx9-family format word.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+constexpr int kAuxNT = 2;   // non-temporal (streaming) cache policy
+
+// Streaming load of the point pair at byte offset voff + soff of a buffer:
+// the per-lane part (voff) is one 32-bit VGPR, the per-slot part (soff) a
+// scalar, so a tile needs no 64-bit per-lane addresses.
+// VEC4: one 16-byte load (base and offsets 16-byte aligned); otherwise two
+// 8-byte loads (base only 8-byte aligned).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 template <bool VEC4>
-__device__ __forceinline__ float4 load_pair(const float2* __restrict__ pts, uint64_t g) {
+__device__ __forceinline__ float4 load_pair_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     if constexpr (VEC4) {
-        return *reinterpret_cast<const float4*>(pts + g);
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, kAuxNT);
+        return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
     } else {
-        float2 a = pts[g], b = pts[g + 1];
-        return make_float4(a.x, a.y, b.x, b.y);
+        const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, kAuxNT);
+        const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(voff + 8u), (int)soff, kAuxNT);
+        return make_float4(__uint_as_float(a.x), __uint_as_float(a.y), __uint_as_float(b.x), __uint_as_float(b.y));
     }
 }
 
@@ -132,27 +153,20 @@ __device__ __forceinline__ float key_of(int j, float x, float y) {
     }
 }
 
-template <int N>
-__device__ __forceinline__ float tree_max(const float (&v)[N]) {
-    float r[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) r[i] = v[i];
-#pragma unroll
-    for (int w = 1; w < N; w *= 2)
-#pragma unroll
-        for (int i = 0; i + w < N; i += 2 * w) r[i] = fmaxf(r[i], r[i + w]);
-    return r[0];
+// IEEE-754 2019 maximum/minimum (NaN-propagating) lower to gfx950's
+// v_maximum3_f32 / v_minimum3_f32 without operand canonicalisation.  NaN
+// inputs are detected separately, so their propagation is harmless.
+__device__ __forceinline__ float max3f(float a, float b, float c) {
+    return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
 }
-template <int N>
-__device__ __forceinline__ float tree_min(const float (&v)[N]) {
-    float r[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) r[i] = v[i];
-#pragma unroll
-    for (int w = 1; w < N; w *= 2)
-#pragma unroll
-        for (int i = 0; i + w < N; i += 2 * w) r[i] = fminf(r[i], r[i + w]);
-    return r[0];
+__device__ __forceinline__ float min3f(float a, float b, float c) {
+    return __builtin_elementwise_minimum(__builtin_elementwise_minimum(a, b), c);
+}
+__device__ __forceinline__ float max8(const float* v) {
+    return max3f(max3f(v[0], v[1], v[2]), max3f(v[3], v[4], v[5]), __builtin_elementwise_maximum(v[6], v[7]));
+}
+__device__ __forceinline__ float min8(const float* v) {
+    return min3f(min3f(v[0], v[1], v[2]), min3f(v[3], v[4], v[5]), __builtin_elementwise_minimum(v[6], v[7]));
 }
 
 struct BlockExtremes {
@@ -165,7 +179,7 @@ struct BlockExtremes {
 // CH = BLOCK*G*2 points starting at the pair-aligned base al <= lo.  The
 // block result is left in `res` (valid in every thread after return).
 template <int BLOCK, int G, bool VEC4>
-__device__ void reduce_points(const float2* __restrict__ pts, uint64_t lo, uint64_t hi, uint64_t al,
+__device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, uint64_t lo, uint64_t hi, uint64_t al,
                               uint32_t c0, uint32_t cstep, uint32_t nch, BlockExtremes& res) {
     constexpr uint32_t CH = BLOCK * G * 2;
     constexpr int NW = BLOCK / 64;
@@ -182,10 +196,12 @@ __device__ void reduce_points(const float2* __restrict__ pts, uint64_t lo, uint6
     for (uint32_t c = c0; c < nch; c += cstep) {
         const uint64_t cb = al + (uint64_t)c * CH;
         if (cb >= lo && cb + CH <= hi) {
+            static_assert(G == 4, "the hot loop folds 8 points per group");
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + cb, CH * 8u);
             float4 q[G];
 #pragma unroll
-            for (int k = 0; k < G; ++k) q[k] = load_pair<VEC4>(pts, cb + 2ull * (k * BLOCK + t));
-            float xs[2 * G], ys[2 * G], ss[2 * G], ds[2 * G];
+            for (int k = 0; k < G; ++k) q[k] = load_pair_buf<VEC4>(rs, 16u * t, 16u * k * BLOCK);
+            float xs[8], ys[8], ss[8], ds[8];
 #pragma unroll
             for (int k = 0; k < G; ++k) {
                 xs[2 * k] = q[k].x;
@@ -194,14 +210,14 @@ __device__ void reduce_points(const float2* __restrict__ pts, uint64_t lo, uint6
                 ys[2 * k + 1] = q[k].w;
             }
 #pragma unroll
-            for (int i = 0; i < 2 * G; ++i) {
+            for (int i = 0; i < 8; ++i) {
                 ss[i] = xs[i] + ys[i];
                 ds[i] = xs[i] - ys[i];
             }
 #pragma unroll
-            for (int i = 0; i < 2 * G; i += 2) bad |= __builtin_isunordered(ss[i], ss[i + 1]);
-            const float m0 = tree_max(xs), m1 = tree_max(ss), m2 = tree_max(ys), m3 = tree_min(ds);
-            const float m4 = tree_min(xs), m5 = tree_min(ss), m6 = tree_min(ys), m7 = tree_max(ds);
+            for (int i = 0; i < 8; i += 2) bad |= __builtin_isunordered(ss[i], ss[i + 1]);
+            const float m0 = max8(xs), m1 = max8(ss), m2 = max8(ys), m3 = min8(ds);
+            const float m4 = min8(xs), m5 = min8(ss), m6 = min8(ys), m7 = max8(ds);
             if (m0 > v[0]) { v[0] = m0; grp[0] = c; }
             if (m1 > v[1]) { v[1] = m1; grp[1] = c; }
             if (m2 > v[2]) { v[2] = m2; grp[2] = c; }
@@ -288,14 +304,6 @@ __device__ void reduce_points(const float2* __restrict__ pts, uint64_t lo, uint6
     __syncthreads();
 }
 
-// Merge a block result into the set's slots (thread 0 only).
-__device__ __forceinline__ void publish_extremes(const BlockExtremes& r, ReduceSlots* slots) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-        if (r.idx[j] != 0xFFFFFFFFu) atomicMax(&slots->key[j], pack_key(r.key[j], r.idx[j]));
-    if (r.bad) atomicOr(&slots->nonfinite, 1u);
-}
-
 // ---------------------------------------------------------------------------
 // Octagon set-up (Sec. 3.1 -> Sec. 3.2), one thread, after all blocks of a
 // set have published.
@@ -321,143 +329,136 @@ __device__ __forceinline__ void publish_extremes(const BlockExtremes& r, ReduceS
 // 2^-48 M = 32 e M on every edge.  Edge values are affine, so every point of
 // the box then has D > 27 e M > 7.01 e M and the rule discards it.
 
-__device__ void setup_octagon(const float2* __restrict__ pts, uint64_t lo, uint64_t n,
-                              ReduceSlots* slots, Octagon* o) {
+// Executed by all 64 lanes of one wave; lane l works on vertex/edge l & 7,
+// and lanes 0..31 check one (edge, box corner) pair each.
+// `p` is the merged packed key of direction lane & 7 (0 if none), `nf` the
+// merged NaN flag.
+// Returns the status it wrote (0 ok, 1 non-finite, 3 internal), uniform.
+__device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uint64_t lo, uint64_t n,
+                                             unsigned long long p, uint32_t nf, Octagon* o) {
 #pragma clang fp contract(off)
-    float vx[8], vy[8];
-    uint32_t id[8];
-    bool missing = false;
-    for (int j = 0; j < 8; ++j) {
-        const unsigned long long p =
-            __hip_atomic_load(&slots->key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        id[j] = unpack_idx(p);
-        missing |= (p == 0ull) || ((uint64_t)id[j] >= n);
-        o->idx[j] = id[j];
+    const uint32_t lane = lane_id();
+    const int j = (int)(lane & 7u);
+    const uint32_t id = unpack_idx(p);
+    const bool miss = (p == 0ull) || ((uint64_t)id >= n);
+    if (lane < 8) o->idx[j] = id;
+    if (lane == 0) {
+        o->mode = 0;
+        o->fast = 0;
+        o->m = 0;
+        o->bxl = kInfF;
+        o->bxh = -kInfF;
+        o->byl = kInfF;
+        o->byh = -kInfF;
     }
-    o->mode = 0;
-    o->fast = 0;
-    o->m = 0;
-    o->bxl = kInfF;
-    o->bxh = -kInfF;
-    o->byl = kInfF;
-    o->byh = -kInfF;
-    if (missing) {   // no candidate for some direction: never expected
-        o->status = 3;
-        return;
+    if (__ballot(miss) != 0ull) {   // no candidate for some direction: never expected
+        if (lane == 0) o->status = 3;
+        return 3;
     }
-    for (int j = 0; j < 8; ++j) {
-        const float2 q = pts[lo + id[j]];
-        vx[j] = q.x;
-        vy[j] = q.y;
-    }
-    const uint32_t nf = __hip_atomic_load(&slots->nonfinite, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const bool bad = nf || !isfinite(vx[0]) || !isfinite(vx[4]) || !isfinite(vy[2]) || !isfinite(vy[6]);
-    o->status = bad ? 1 : 0;
-    if (bad) return;
+    const float2 q = pts[lo + id];
+    const float vx = q.x, vy = q.y;
+    // bounding box: E0 max x, E4 min x, E2 max y, E6 min y
+    const float xmax = __shfl(vx, 0, 64), xmin = __shfl(vx, 4, 64);
+    const float ymax = __shfl(vy, 2, 64), ymin = __shfl(vy, 6, 64);
+    const bool bad = nf || !isfinite(xmax) || !isfinite(xmin) || !isfinite(ymax) || !isfinite(ymin);
+    if (lane == 0) o->status = bad ? 1 : 0;
+    if (bad) return 1;
 
-    // distinct vertices
-    int distinct = 0;
-    for (int j = 0; j < 8; ++j) {
-        bool seen = false;
-        for (int k = 0; k < j; ++k) seen |= (vx[k] == vx[j] && vy[k] == vy[j]);
-        distinct += seen ? 0 : 1;
+    const float nx = __shfl(vx, (j + 1) & 7, 64), ny = __shfl(vy, (j + 1) & 7, 64);
+    const bool deg = (vx == nx) && (vy == ny);
+    bool first = true;   // first vertex with these coordinates
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float kx = __shfl(vx, k, 64), ky = __shfl(vy, k, 64);
+        if (k < j && kx == vx && ky == vy) first = false;
     }
-    // non-degenerate edges, binary64
-    double ax[8], ay[8], ex[8], ey[8];
-    int m = 0;
-    for (int j = 0; j < 8; ++j) {
-        const int k = (j + 1) & 7;
-        if (vx[j] == vx[k] && vy[j] == vy[k]) continue;
-        ax[m] = vx[j];
-        ay[m] = vy[j];
-        ex[m] = (double)vx[k] - (double)vx[j];
-        ey[m] = (double)vy[k] - (double)vy[j];
-        ++m;
-    }
-    o->m = m;
+    const int distinct = __popcll(__ballot(lane < 8 && first));
+    const unsigned long long ndm = __ballot(lane < 8 && !deg) & 0xFFull;
+    const int m = __popcll(ndm);
+    if (lane == 0) o->m = m;
     // Fewer than three distinct vertices: no point can be strictly inside
     // every edge (the rule is sound and the polygon has no interior).
-    if (distinct < 3 || m == 0) return;
-    for (int e = m; e < 8; ++e) {
-        ax[e] = ax[0];
-        ay[e] = ay[0];
-        ex[e] = ex[0];
-        ey[e] = ey[0];
-    }
-    for (int e = 0; e < 8; ++e) {
-        o->ax[e] = ax[e];
-        o->ay[e] = ay[e];
-        o->ex[e] = ex[e];
-        o->ey[e] = ey[e];
-    }
-    o->mode = 1;
+    if (distinct < 3 || m == 0) return 0;
 
-    // bounding box (E4, E0 give x; E6, E2 give y)
-    const float xmin = vx[4], xmax = vx[0], ymin = vy[6], ymax = vy[2];
+    // edge slot j: the j-th non-degenerate edge, or the first one as padding
+    int src = __ffsll((long long)ndm) - 1;
+    {
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((ndm >> k) & 1ull) {
+                if (cnt == j) src = k;
+                ++cnt;
+            }
+    }
+    const float sax = __shfl(vx, src, 64), say = __shfl(vy, src, 64);
+    const float sbx = __shfl(nx, src, 64), sby = __shfl(ny, src, 64);
+    const double ax = sax, ay = say;
+    const double ex = (double)sbx - ax, ey = (double)sby - ay;
+    if (lane < 8) {
+        o->ax[j] = ax;
+        o->ay[j] = ay;
+        o->ex[j] = ex;
+        o->ey[j] = ey;
+    }
+
     const double up = 1.0 + 0x1p-40;
     const double W = ((double)xmax - (double)xmin) * (1.0 + 0x1p-50);
     const double H = ((double)ymax - (double)ymin) * (1.0 + 0x1p-50);
     const float cx = (float)(0.5 * (double)xmin + 0.5 * (double)xmax);
     const float cy = (float)(0.5 * (double)ymin + 0.5 * (double)ymax);
-    o->cx = cx;
-    o->cy = cy;
-    double M[8];
-    bool fast = isfinite(W) && isfinite(H);
-    for (int e = 0; e < 8; ++e) {
-        M[e] = (fabs(ex[e]) * H + fabs(ey[e]) * W) * up;
-        if (!(M[e] > 0.0) || !isfinite(M[e])) {
-            fast = false;
-            M[e] = 0.0;
-            continue;
-        }
-        int E;
-        (void)frexp(M[e] * 0x1p-20, &E);   // 16 u M = m 2^E, m in [0.5, 1)
-        const double s = ldexp(1.0, -E);
-        const double a = s * ex[e];
-        const double nb = -s * ey[e];
-        const double k = ex[e] * ((double)cy - ay[e]) - ey[e] * ((double)cx - ax[e]);
-        const double c0 = s * k;
-        if (!(fabs(a) <= 0x1p100 && fabs(nb) <= 0x1p100 && fabs(c0) <= 0x1p100)) fast = false;
-        o->A[e] = (float)a;
-        o->NB[e] = (float)nb;
-        o->C0[e] = (float)c0;
+    const double M = (fabs(ex) * H + fabs(ey) * W) * up;
+    bool ok = isfinite(W) && isfinite(H) && (M > 0.0) && isfinite(M);
+    int E = 0;
+    (void)frexp(ok ? M * 0x1p-20 : 1.0, &E);   // 16 u M = f 2^E, f in [0.5, 1)
+    const double sc = ldexp(1.0, -E);
+    const double a = sc * ex;
+    const double nb = -sc * ey;
+    const double kk = ex * ((double)cy - ay) - ey * ((double)cx - ax);
+    const double c0 = sc * kk;
+    ok = ok && fabs(a) <= 0x1p100 && fabs(nb) <= 0x1p100 && fabs(c0) <= 0x1p100;
+    if (lane < 8) {
+        o->A[j] = (float)a;
+        o->NB[j] = (float)nb;
+        o->C0[j] = (float)c0;
     }
-    o->fast = fast ? 1 : 0;
+    const bool fast = __ballot(lane < 8 && !ok) == 0ull;
 
-    // quick-accept box
-    float XL = fmaxf(vx[3], vx[5]), XH = fminf(vx[1], vx[7]);
-    float YL = fmaxf(vy[5], vy[7]), YH = fminf(vy[1], vy[3]);
-    bool ok = fast && XL < XH && YL < YH;
-    for (int it = 0; ok && it < 8; ++it) {
-        bool pass = true;
-        for (int c = 0; c < 4 && pass; ++c) {
-            const double qx = (c & 1) ? (double)XH : (double)XL;
-            const double qy = (c & 2) ? (double)YH : (double)YL;
-            for (int e = 0; e < 8; ++e) {
-                const double D = ex[e] * (qy - ay[e]) - ey[e] * (qx - ax[e]);
-                if (!(D > 0x1p-48 * M[e])) {
-                    pass = false;
-                    break;
-                }
-            }
-        }
-        if (pass) break;
+    // quick-accept box: candidate from the corner vertices, shrunk towards
+    // the centre until all four corners pass every edge
+    float XL = fmaxf(__shfl(vx, 3, 64), __shfl(vx, 5, 64)), XH = fminf(__shfl(vx, 1, 64), __shfl(vx, 7, 64));
+    float YL = fmaxf(__shfl(vy, 5, 64), __shfl(vy, 7, 64)), YH = fminf(__shfl(vy, 1, 64), __shfl(vy, 3, 64));
+    bool boxok = fast && XL < XH && YL < YH;
+    const int corner = (int)((lane >> 3) & 3u);
+    for (int it = 0; boxok && it < 8; ++it) {
+        const double qx = (corner & 1) ? (double)XH : (double)XL;
+        const double qy = (corner & 2) ? (double)YH : (double)YL;
+        const double D = ex * (qy - ay) - ey * (qx - ax);
+        const bool pass = (lane >= 32) || (D > 0x1p-48 * M);
+        if (__ballot(!pass) == 0ull) break;
         if (it == 7) {
-            ok = false;
+            boxok = false;
             break;
         }
         XL = (float)((double)cx + 0.75 * ((double)XL - (double)cx));
         XH = (float)((double)cx + 0.75 * ((double)XH - (double)cx));
         YL = (float)((double)cy + 0.75 * ((double)YL - (double)cy));
         YH = (float)((double)cy + 0.75 * ((double)YH - (double)cy));
-        ok = XL < XH && YL < YH;
+        boxok = XL < XH && YL < YH;
     }
-    if (ok) {
-        o->bxl = XL;
-        o->bxh = XH;
-        o->byl = YL;
-        o->byh = YH;
+    if (lane == 0) {
+        o->cx = cx;
+        o->cy = cy;
+        o->fast = fast ? 1 : 0;
+        if (boxok) {
+            o->bxl = XL;
+            o->bxh = XH;
+            o->byl = YL;
+            o->byh = YH;
+        }
+        o->mode = 1;
     }
+    return 0;
 }
 
 __device__ __forceinline__ void reset_slots(ReduceSlots* s) {
@@ -475,7 +476,8 @@ __device__ __forceinline__ bool contract_inside(const Octagon* __restrict__ o, f
 #pragma clang fp contract(off)
     const double x = px, y = py;
     bool in = true;
-#pragma unroll
+    // one edge at a time: this is the rare path, keep its registers few
+#pragma unroll 1
     for (int e = 0; e < 8; ++e) {
         const double qx = x - o->ax[e];
         const double qy = y - o->ay[e];
@@ -488,16 +490,22 @@ __device__ __forceinline__ bool contract_inside(const Octagon* __restrict__ o, f
     return in;
 }
 
+// Minimum over the edges of the scaled FP32 edge values (fast == 1).
+__device__ __forceinline__ float edge_min(const Octagon* __restrict__ o, float x, float y) {
+    const float qx = x - o->cx, qy = y - o->cy;
+    float d[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = fmaf(o->A[e], qy, fmaf(o->NB[e], qx, o->C0[e]));
+    return min8(d);
+}
+
 // 1 = the point survives.  Decision-equivalent to the binary64 rule.
 __device__ __forceinline__ bool keep_point(const Octagon* __restrict__ o, float x, float y) {
     if (o->mode == 0) return true;
     const bool inbox = (o->bxl < x) & (x < o->bxh) & (o->byl < y) & (y < o->byh);
     if (inbox) return false;
     if (o->fast) {
-        const float qx = x - o->cx, qy = y - o->cy;
-        float mn = kInfF;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) mn = fminf(mn, fmaf(o->A[e], qy, fmaf(o->NB[e], qx, o->C0[e])));
+        const float mn = edge_min(o, x, y);
         if (mn < -1.0f) return true;
         if (mn > 2.0f) return false;
     }
@@ -505,115 +513,252 @@ __device__ __forceinline__ bool keep_point(const Octagon* __restrict__ o, float 
 }
 
 // ---------------------------------------------------------------------------
-// Sec. 4.1.1: compaction of one tile with decoupled look-back
+// Sec. 4.1.1: compaction with decoupled look-back, in phases
 // ---------------------------------------------------------------------------
-// Tile `tile` of a set covers points [al + tile*T, al + (tile+1)*T) clipped
-// to [lo, hi).  Survivors are written as indices relative to lo, ascending,
-// at out + (prefix), entries >= cap dropped.  status: the set's tile status
-// words (flag in bits 62-63: 0 not ready, 1 aggregate, 2 inclusive prefix).
-// `count` (if non-null, for the set's last tile) receives the total.
+// Geometry: a tile is SUB sub-tiles of ST = BLOCK*PPT points; pair slot j of
+// thread t in a sub-tile with base sb covers points sb + 2*(j*BLOCK + t) +
+// {0, 1}.  Survivor order inside a tile is (sub-tile, j, wave, lane, point),
+// which is ascending point order.  A tile's survivor count is the sum of
+// NS = SUB*NP*NW wave-segment counts kept in LDS.
+//
+// Tile status words (one per tile of a set): flag in bits 62-63 (0 not
+// ready, 1 aggregate, 2 inclusive prefix), count in the low bits; flag and
+// value share one 64-bit word, so relaxed agent-scope atomics suffice.
 
+// Load one sub-tile; returns the validity mask (bit 2j+h).
 template <int BLOCK, int PPT, bool VEC4>
-__device__ void filter_tile(const float2* __restrict__ pts, uint64_t lo, uint64_t hi, uint64_t al,
-                            uint32_t tile, const Octagon* __restrict__ o, uint64_t* status,
-                            uint32_t* __restrict__ out, uint64_t cap, uint64_t* count) {
+__device__ __forceinline__ uint32_t load_sub(const float2* __restrict__ pts, uint64_t lo, uint64_t hi,
+                                             uint64_t sb, float4 (&q)[PPT / 2]) {
     constexpr int NP = PPT / 2;
-    constexpr int NW = BLOCK / 64;
-    constexpr int NS = NP * NW;   // wave segments per tile, in index order (j, wave)
-    constexpr uint32_t T = BLOCK * PPT;
-    static_assert(NS <= 128, "tile shape");
-    __shared__ uint32_t sh_off[NS];
-    __shared__ uint64_t sh_excl;
-
-    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-    const uint64_t tb = al + (uint64_t)tile * T;
-    const bool full = (tb >= lo) && (tb + T <= hi);
-
-    uint32_t k0m = 0, k1m = 0;
-    uint32_t rank[NP];
+    constexpr uint32_t ST = BLOCK * PPT;
+    const uint32_t t = threadIdx.x;
+    if (sb >= lo && sb + ST <= hi) {
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + sb, ST * 8u);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) q[j] = load_pair_buf<VEC4>(rs, 16u * t, 16u * j * BLOCK);
+        return (NP >= 16) ? 0xFFFFFFFFu : ((1u << (2 * NP)) - 1u);
+    }
+    uint32_t validm = 0;
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-        const uint64_t g = tb + 2ull * (j * BLOCK + t);
-        float4 q;
-        bool v0 = true, v1 = true;
-        if (full) q = load_pair<VEC4>(pts, g);
-        else q = load_pair_checked(pts, g, lo, hi, v0, v1);
-        const bool k0 = v0 && keep_point(o, q.x, q.y);
-        const bool k1 = v1 && keep_point(o, q.z, q.w);
-        const unsigned long long b0 = __ballot(k0), b1 = __ballot(k1);
-        rank[j] = rank_below(b0) + rank_below(b1);
-        if (lane == 0) sh_off[j * NW + wave] = (uint32_t)(__popcll(b0) + __popcll(b1));
-        k0m |= (k0 ? 1u : 0u) << j;
-        k1m |= (k1 ? 1u : 0u) << j;
+        bool v0, v1;
+        q[j] = load_pair_checked(pts, sb + 2ull * (j * BLOCK + t), lo, hi, v0, v1);
+        validm |= (v0 ? 1u : 0u) << (2 * j);
+        validm |= (v1 ? 1u : 0u) << (2 * j + 1);
     }
-    __syncthreads();
+    return validm;
+}
 
-    if (wave == 0) {
-        // exclusive scan of the NS segment counts (two per lane at most)
-        uint32_t a = (lane < NS) ? sh_off[lane] : 0u;
-        uint32_t b = (lane + 64 < NS) ? sh_off[lane + 64] : 0u;
-        uint32_t ia = a;
+// Inside test of one loaded sub-tile; returns the keep mask (bit 2j+h).
+// Points in the uncertain band are re-read by index and take the binary64
+// rule itself.
+template <int BLOCK, int PPT>
+__device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, const float2* __restrict__ pts,
+                                                 uint64_t sb, const float4 (&q)[PPT / 2], uint32_t validm) {
+    constexpr int NP = PPT / 2;
+    const uint32_t t = threadIdx.x;
+    if (o->mode == 0) return validm;
+    uint32_t keepm = 0, pendm = 0;
+    const float bxl = o->bxl, bxh = o->bxh, byl = o->byl, byh = o->byh;
+    const bool fast = o->fast != 0;
 #pragma unroll
-        for (int o2 = 1; o2 < 64; o2 <<= 1) {
-            const uint32_t u = (uint32_t)__shfl_up((int)ia, o2, 64);
-            if ((int)lane >= o2) ia += u;
+    for (int j = 0; j < NP; ++j) {
+        const bool ok0 = (validm >> (2 * j)) & 1u, ok1 = (validm >> (2 * j + 1)) & 1u;
+        const bool in0 = (bxl < q[j].x) & (q[j].x < bxh) & (byl < q[j].y) & (q[j].y < byh);
+        const bool in1 = (bxl < q[j].z) & (q[j].z < bxh) & (byl < q[j].w) & (q[j].w < byh);
+        const bool need0 = ok0 & !in0, need1 = ok1 & !in1;
+        // wave-uniform branch: skipped when every point of the pair slot is
+        // inside the quick-accept box (most of a normal cloud)
+        if (__ballot(need0 | need1) != 0ull) {
+            uint32_t k2 = 0, p2 = 0;
+            if (fast) {
+                const float mn0 = edge_min(o, q[j].x, q[j].y);
+                const float mn1 = edge_min(o, q[j].z, q[j].w);
+                k2 = (need0 & (mn0 < -1.0f) ? 1u : 0u) | (need1 & (mn1 < -1.0f) ? 2u : 0u);
+                p2 = (need0 & !(mn0 < -1.0f) & !(mn0 > 2.0f) ? 1u : 0u) |
+                     (need1 & !(mn1 < -1.0f) & !(mn1 > 2.0f) ? 2u : 0u);
+            } else {
+                p2 = (need0 ? 1u : 0u) | (need1 ? 2u : 0u);
+            }
+            keepm |= k2 << (2 * j);
+            pendm |= p2 << (2 * j);
         }
-        const uint32_t tot_a = (uint32_t)__shfl((int)ia, 63, 64);
-        uint32_t ib = b;
-#pragma unroll
-        for (int o2 = 1; o2 < 64; o2 <<= 1) {
-            const uint32_t u = (uint32_t)__shfl_up((int)ib, o2, 64);
-            if ((int)lane >= o2) ib += u;
+    }
+    // uncertain band: one point per lane per round (rare)
+    const float2* __restrict__ tp = pts + sb;
+    while (__ballot(pendm != 0u) != 0ull) {
+        if (pendm) {
+            const int b = __ffs(pendm) - 1;
+            pendm &= pendm - 1u;
+            const float2 pt = *reinterpret_cast<const float2*>(
+                reinterpret_cast<const char*>(tp) + 16u * ((uint32_t)(b >> 1) * BLOCK + t) + 8u * (uint32_t)(b & 1));
+            // an opaque copy of the pointer keeps the compiler from hoisting
+            // the binary64 edge data into registers on the hot path
+            const Octagon* oo = o;
+            asm volatile("" : "+s"(oo));
+            if (!contract_inside(oo, pt.x, pt.y)) keepm |= 1u << b;
         }
-        const uint32_t tot_b = (uint32_t)__shfl((int)ib, 63, 64);
-        if (lane < NS) sh_off[lane] = ia - a;
-        if (lane + 64 < NS) sh_off[lane + 64] = tot_a + ib - b;
-        const uint64_t agg = (uint64_t)tot_a + tot_b;
+    }
+    return keepm;
+}
 
-        // decoupled look-back
-        uint64_t excl = 0;
-        if (tile == 0) {
-            if (lane == 0) status_store(&status[0], kFlagP | agg);
-        } else {
-            if (lane == 0) status_store(&status[tile], kFlagA | agg);
-            int64_t look = (int64_t)tile - 1;
-            for (;;) {
-                const int64_t idx = look - (int64_t)lane;
-                const uint64_t s = (idx >= 0) ? status_load(&status[idx]) : kFlagP;
-                const uint32_t flag = (uint32_t)(s >> 62);
+// Wave-segment survivor counts of one sub-tile into cnt[j*NW + wave].
+template <int BLOCK, int PPT>
+__device__ __forceinline__ void count_sub(uint32_t keepm, uint32_t* cnt) {
+    constexpr int NP = PPT / 2;
+    constexpr int NW = BLOCK / 64;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const unsigned long long b0 = __ballot((keepm >> (2 * j)) & 1u);
+        const unsigned long long b1 = __ballot((keepm >> (2 * j + 1)) & 1u);
+        if (lane == 0) cnt[j * NW + wave] = (uint32_t)(__popcll(b0) + __popcll(b1));
+    }
+}
+
+// Wave 0: exclusive scan of the NS segment counts in place, then the
+// tile's decoupled look-back.  Writes the tile's exclusive prefix to *excl_out
+// and, for the last tile, the set's total to *count.
+template <int NS>
+__device__ __forceinline__ void scan_lookback(uint32_t* cnt, uint32_t tile, uint64_t* status,
+                                              uint64_t* excl_out, uint64_t* count) {
+    static_assert(NS <= 512, "at most 8 segments per lane");
+    constexpr int PER = (NS + 63) / 64;
+    const uint32_t lane = lane_id();
+    uint32_t v[PER];
+    uint32_t local = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const uint32_t e = lane * PER + i;
+        v[i] = (e < NS) ? cnt[e] : 0u;
+        local += v[i];
+    }
+    uint32_t incl = local;
+#pragma unroll
+    for (int o2 = 1; o2 < 64; o2 <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)incl, o2, 64);
+        if ((int)lane >= o2) incl += u;
+    }
+    const uint64_t agg = (uint32_t)__shfl((int)incl, 63, 64);
+    uint32_t run = incl - local;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const uint32_t e = lane * PER + i;
+        if (e < NS) cnt[e] = run;
+        run += v[i];
+    }
+
+    uint64_t excl = 0;
+    if (tile == 0) {
+        if (lane == 0) status_store(&status[0], kFlagP | agg);
+    } else {
+        if (lane == 0) status_store(&status[tile], kFlagA | agg);
+        // Rounds read `chunks` groups of 64 consecutive predecessors
+        // (group k holds tiles look-64k-lane): one group first, all kLB
+        // groups once no inclusive prefix is within reach.
+        int64_t look = (int64_t)tile - 1;
+        int chunks = 1;
+        for (;;) {
+            uint64_t w[kLB];
+#pragma unroll
+            for (int k = 0; k < kLB; ++k) {
+                w[k] = kFlagP;
+                if (k < chunks) {
+                    const int64_t top = look - 64 * k;   // uniform
+                    const uint32_t lim = top < 0 ? 0u : (top >= 63 ? 64u : (uint32_t)top + 1u);
+                    if (lane < lim) {
+                        const uint64_t* b = status + (top - 63);
+                        w[k] = status_load(reinterpret_cast<const uint64_t*>(
+                            reinterpret_cast<const char*>(b) + 8u * (63u - lane)));
+                    }
+                }
+            }
+            int k = 0;
+            bool found = false, stalled = false;
+            uint64_t sum = 0;
+#pragma unroll
+            for (; k < kLB; ++k) {
+                if (k >= chunks) break;
+                const uint32_t flag = (uint32_t)(w[k] >> 62);
                 const unsigned long long pm = __ballot(flag == 2u);
                 const unsigned long long xm = __ballot(flag == 0u);
                 const int first_p = pm ? (__ffsll((long long)pm) - 1) : 64;
                 const unsigned long long need = (first_p >= 63) ? ~0ull : ((2ull << first_p) - 1ull);
                 if (xm & need) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+                    stalled = true;
+                    break;
                 }
-                const uint64_t part = ((int)lane <= first_p) ? (s & kValMask) : 0ull;
-                excl += wave_sum_u64(part);
-                if (first_p < 64) break;
-                look -= 64;
+                sum += wave_sum_u64(((int)lane <= first_p) ? (w[k] & kValMask) : 0ull);
+                if (first_p < 64) {
+                    found = true;
+                    break;
+                }
             }
-            if (lane == 0) status_store(&status[tile], kFlagP | (excl + agg));
+            excl += sum;
+            if (found) break;
+            look -= 64 * k;   // groups before k held aggregates only
+            if (stalled) __builtin_amdgcn_s_sleep(1);
+            else chunks = kLB;
         }
-        if (lane == 0) {
-            sh_excl = excl;
-            if (count) *count = excl + agg;
-        }
+        if (lane == 0) status_store(&status[tile], kFlagP | (excl + agg));
     }
-    __syncthreads();
+    if (lane == 0) {
+        *excl_out = excl;
+        if (count) *count = excl + agg;
+    }
+}
 
-    const uint64_t excl = sh_excl;
+// Write the survivors of one sub-tile: positions excl + off[j*NW + wave] +
+// rank (off is relative to the tile's first survivor, so it can reach the
+// tile size `span`), values = point index relative to lo; entries at or
+// beyond cap are dropped.  vbase = (sub-tile base - lo) mod 2^32.
+template <int BLOCK, int PPT>
+__device__ __forceinline__ void write_sub(uint32_t keepm, const uint32_t* off, uint64_t excl,
+                                          uint32_t vbase, uint32_t* __restrict__ out, uint64_t cap,
+                                          uint32_t span) {
+    constexpr int NP = PPT / 2;
+    constexpr int NW = BLOCK / 64;
+    if (__ballot(keepm != 0u) == 0ull) return;
+    const uint32_t t = threadIdx.x, wave = t >> 6;
+    const uint64_t room = (cap > excl) ? cap - excl : 0ull;
+    const uint32_t capr = room > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)room;
+    const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + excl, 4u * (capr < span ? capr : span));
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-        const bool k0 = (k0m >> j) & 1u, k1 = (k1m >> j) & 1u;
-        if (!(k0 | k1)) continue;
-        const uint64_t g = tb + 2ull * (j * BLOCK + t);
-        const uint64_t pos = excl + sh_off[j * NW + wave] + rank[j];
-        if (k0 && pos < cap) __builtin_nontemporal_store((uint32_t)(g - lo), out + pos);
-        const uint64_t pos1 = pos + (k0 ? 1u : 0u);
-        if (k1 && pos1 < cap) __builtin_nontemporal_store((uint32_t)(g + 1 - lo), out + pos1);
+        const unsigned long long b0 = __ballot((keepm >> (2 * j)) & 1u);
+        const unsigned long long b1 = __ballot((keepm >> (2 * j + 1)) & 1u);
+        if ((b0 | b1) == 0ull) continue;
+        const bool k0 = (keepm >> (2 * j)) & 1u, k1 = (keepm >> (2 * j + 1)) & 1u;
+        const uint32_t idx = vbase + 2u * (j * BLOCK + t);
+        const uint32_t pos = off[j * NW + wave] + rank_below(b0) + rank_below(b1);
+        if (k0 && pos < capr) __builtin_amdgcn_raw_buffer_store_b32(idx, ro, (int)(4u * pos), 0, kAuxNT);
+        const uint32_t pos1 = pos + (k0 ? 1u : 0u);
+        if (k1 && pos1 < capr) __builtin_amdgcn_raw_buffer_store_b32(idx + 1u, ro, (int)(4u * pos1), 0, kAuxNT);
     }
+}
+
+// One whole tile (SUB = 1), not pipelined: used by the batched kernel.
+template <int BLOCK, int PPT, bool VEC4>
+__device__ __forceinline__ void filter_tile(const float2* __restrict__ pts, uint64_t lo, uint64_t hi, uint64_t al,
+                                            uint32_t tile, const Octagon* __restrict__ o, uint64_t* status,
+                                            uint32_t* __restrict__ out, uint64_t cap, uint64_t* count) {
+    constexpr int NP = PPT / 2;
+    constexpr int NW = BLOCK / 64;
+    constexpr int NS = NP * NW;
+    constexpr uint32_t T = BLOCK * PPT;
+    __shared__ uint32_t sh_cnt[NS];
+    __shared__ uint64_t sh_excl;
+    const uint64_t tb = al + (uint64_t)tile * T;
+    float4 q[NP];
+    const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, tb, q);
+    const uint32_t keepm = classify_sub<BLOCK, PPT>(o, pts, tb, q, validm);
+    count_sub<BLOCK, PPT>(keepm, sh_cnt);
+    __syncthreads();
+    if ((threadIdx.x >> 6) == 0) scan_lookback<NS>(sh_cnt, tile, status, &sh_excl, count);
+    __syncthreads();
+    const uint64_t excl = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_excl >> 32)) << 32) |
+                          __builtin_amdgcn_readfirstlane((uint32_t)sh_excl);
+    write_sub<BLOCK, PPT>(keepm, sh_cnt, excl, (uint32_t)(tb - lo), out, cap, T);
     __syncthreads();
 }
 
@@ -622,7 +767,7 @@ __device__ void filter_tile(const float2* __restrict__ pts, uint64_t lo, uint64_
 // ---------------------------------------------------------------------------
 
 constexpr int kRBlock = 256;
-constexpr int kRG = 8;   // pairs per thread per chunk: 16 points
+constexpr int kRG = 4;   // pairs per thread per chunk: 8 points
 
 __global__ void k_init_slots(ReduceSlots* s, uint32_t count) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -633,10 +778,16 @@ __global__ void k_init_slots(ReduceSlots* s, uint32_t count) {
     }
 }
 
+// One point set, pass 1.  Every block writes its packed candidates to its
+// own partial record with plain stores.  There is deliberately no
+// cross-block fence or completion counter here: on this multi-XCD device an
+// agent-scope release writes back the XCD's L2, and one per block costs more
+// than the whole streaming pass.  k_setup (next launch on the stream) merges
+// the records; the kernel boundary makes them visible.
 template <bool VEC4>
-__global__ __launch_bounds__(kRBlock) void k_reduce(const float2* __restrict__ pts, uint64_t n,
-                                                    ReduceSlots* slots, Octagon* oct,
-                                                    uint64_t* tile_status, uint32_t num_tiles) {
+__global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_reduce(
+    const float2* __restrict__ pts, uint64_t n, ReduceSlots* slots,
+    unsigned long long* __restrict__ part, uint64_t* tile_status, uint32_t num_tiles) {
     // clear the look-back state of the compaction kernel that follows
     for (uint64_t i = (uint64_t)blockIdx.x * kRBlock + threadIdx.x; i < num_tiles;
          i += (uint64_t)gridDim.x * kRBlock)
@@ -645,43 +796,116 @@ __global__ __launch_bounds__(kRBlock) void k_reduce(const float2* __restrict__ p
 
     constexpr uint32_t CH = kRBlock * kRG * 2;
     const uint32_t nch = (uint32_t)((n + CH - 1) / CH);
-    __shared__ int sh_last;
     BlockExtremes r;
     reduce_points<kRBlock, kRG, VEC4>(pts, 0, n, 0, blockIdx.x, gridDim.x, nch, r);
-    if (threadIdx.x == 0) {
-        publish_extremes(r, slots);
-        __threadfence();
-        const uint32_t prev = atomicAdd(&slots->done, 1u);
-        sh_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (sh_last && threadIdx.x == 0) {
-        __threadfence();
-        setup_octagon(pts, 0, n, slots, oct);
-        reset_slots(slots);
-        __threadfence();
+    if (threadIdx.x < 9) {
+        const int j = threadIdx.x;
+        unsigned long long v;
+        if (j < 8) v = (r.idx[j] != 0xFFFFFFFFu) ? pack_key(r.key[j], r.idx[j]) : 0ull;
+        else v = r.bad ? 1ull : 0ull;
+        part[(uint64_t)blockIdx.x * 9 + j] = v;
     }
 }
 
+// One point set, pass 2 (one block of 256 threads): merge the `nblocks`
+// partial records (max per direction, OR of the NaN flags), then build the
+// octagon with wave 0.
+__global__ __launch_bounds__(256) void k_setup(const float2* __restrict__ pts, uint64_t n, Octagon* oct,
+                                               const unsigned long long* __restrict__ part,
+                                               uint32_t nblocks) {
+    __shared__ unsigned long long sh_m[9][4];
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+    unsigned long long m[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) m[j] = 0ull;
+    for (uint32_t b = t; b < nblocks; b += 256) {
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const unsigned long long v = part[(uint64_t)b * 9 + j];
+            m[j] = (j == 8) ? (m[j] | v) : max(m[j], v);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        unsigned long long v = m[j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, 64);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, 64);
+            const unsigned long long u = ((unsigned long long)hi << 32) | lo;
+            v = (j == 8) ? (v | u) : max(v, u);
+        }
+        if (lane == 0) sh_m[j][wave] = v;
+    }
+    __syncthreads();
+    if (t < 64) {
+        const uint32_t j = lane & 7u;
+        unsigned long long key = 0ull, nf = 0ull;
+        for (int w = 0; w < 4; ++w) {
+            key = max(key, sh_m[j][w]);
+            nf |= sh_m[8][w];
+        }
+        (void)setup_octagon(pts, 0, n, key, (uint32_t)nf, oct);
+    }
+}
+
+// One point set, inside test + compaction.  Persistent blocks take tiles
+// (SUB sub-tiles each) from an atomic ticket; the next tile's ticket is
+// taken and its first sub-tile's loads issued before this tile's look-back,
+// so the look-back wait overlaps memory traffic.
 template <int BLOCK, int PPT, bool VEC4>
-__global__ __launch_bounds__(BLOCK) void k_filter(const float2* __restrict__ pts, uint64_t n,
-                                                  const Octagon* __restrict__ oct, ReduceSlots* slots,
-                                                  uint64_t* tile_status, uint32_t num_tiles,
-                                                  uint32_t* __restrict__ surv, uint64_t cap,
-                                                  uint64_t* count) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_filter(
+    const float2* __restrict__ pts, uint64_t n, const Octagon* __restrict__ oct, ReduceSlots* slots,
+    uint64_t* tile_status, uint32_t num_tiles, uint32_t* __restrict__ surv, uint64_t cap, uint64_t* count) {
+    constexpr int NP = PPT / 2;
+    constexpr int NW = BLOCK / 64;
+    constexpr int SUB = 64 / PPT;   // the keep bits of a whole tile fit one 64-bit mask
+    constexpr int NSS = NP * NW;    // segments per sub-tile
+    constexpr uint32_t ST = BLOCK * PPT;
+    constexpr uint32_t T = ST * SUB;
     if (oct->status != 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
             *count = (oct->status == 1) ? kCountNonFinite : kCountInternal;
         return;
     }
-    __shared__ uint32_t sh_tile;
-    for (;;) {
-        if (threadIdx.x == 0) sh_tile = atomicAdd(&slots->ticket, 1u);
+    __shared__ uint32_t sh_cnt[SUB * NSS];
+    __shared__ uint64_t sh_excl;
+    __shared__ uint32_t sh_tk;
+    const uint32_t wave = threadIdx.x >> 6;
+
+    if (threadIdx.x == 0) sh_tk = atomicAdd(&slots->ticket, 1u);
+    __syncthreads();
+    uint32_t tile = __builtin_amdgcn_readfirstlane(sh_tk);
+    float4 q[NP];
+    uint32_t validm = 0;
+    if (tile < num_tiles) validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, (uint64_t)tile * T, q);
+    while (tile < num_tiles) {
+        const uint64_t tb = (uint64_t)tile * T;
+        uint64_t keep = 0;   // PPT bits per sub-tile
+#pragma unroll 1
+        for (int sidx = 0; sidx < SUB; ++sidx) {
+            const uint64_t sb = tb + (uint64_t)sidx * ST;
+            if (sidx > 0) validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q);
+            const uint32_t k = classify_sub<BLOCK, PPT>(oct, pts, sb, q, validm);
+            count_sub<BLOCK, PPT>(k, &sh_cnt[sidx * NSS]);
+            keep |= (uint64_t)k << (sidx * PPT);
+        }
+        if (threadIdx.x == 0) sh_tk = atomicAdd(&slots->ticket, 1u);
         __syncthreads();
-        const uint32_t tile = sh_tile;
-        if (tile >= num_tiles) break;
-        filter_tile<BLOCK, PPT, VEC4>(pts, 0, n, 0, tile, oct, tile_status, surv, cap,
-                                      tile == num_tiles - 1 ? count : nullptr);
+        const uint32_t next = __builtin_amdgcn_readfirstlane(sh_tk);
+        if (next < num_tiles) validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, (uint64_t)next * T, q);
+        if (wave == 0)
+            scan_lookback<SUB * NSS>(sh_cnt, tile, tile_status, &sh_excl, tile == num_tiles - 1 ? count : nullptr);
+        __syncthreads();
+        const uint64_t excl = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_excl >> 32)) << 32) |
+                              __builtin_amdgcn_readfirstlane((uint32_t)sh_excl);
+#pragma unroll 1
+        for (int sidx = 0; sidx < SUB; ++sidx) {
+            const uint32_t k = (uint32_t)(keep >> (sidx * PPT)) & (PPT >= 32 ? 0xFFFFFFFFu : ((1u << PPT) - 1u));
+            write_sub<BLOCK, PPT>(k, &sh_cnt[sidx * NSS], excl, (uint32_t)(tb + (uint64_t)sidx * ST), surv, cap, T);
+        }
+        __syncthreads();
+        tile = next;
     }
 }
 
@@ -714,28 +938,29 @@ __global__ __launch_bounds__(256) void k_gather(const float2* __restrict__ pts,
 }
 
 // ---------------------------------------------------------------------------
-// kernels: many sets, one persistent launch
+// kernels: many sets in one graph of four launches
 // ---------------------------------------------------------------------------
-// Work list.  Set s has r_tiles reduction tiles (kRBlock*kRG*2 points each)
-// and f_tiles compaction tiles.  The list interleaves them so that the
-// compaction of set s comes after the reduction tiles of the sets that end
-// within `lag` points after it: its reduction has long finished when its
-// compaction tiles are handed out (few waits), and its points are still in
-// the last-level cache when they are read the second time.
-//   segment order: R(0), F(s : j(s) = 0), R(1), F(s : j(s) = 1), ...
-//   j(s) = max(s, first set j with off[j+1] >= off[s+1] + lag), at most S-1
-// Tickets are taken from one atomic counter; a ticket's segment is found by
-// binary search.  A compaction tile spins until its set's octagon is
-// published; this cannot deadlock because every reduction tile of that set
-// holds an earlier ticket and never waits.
+// Sets are CSR ranges of one point array.  Launch 1 (plan, one block) cuts
+// every set into reduction tiles of kBatchRT points and compaction tiles of
+// BLOCK*PPT points (both aligned to the pair grid of the array) and computes
+// their prefix counts.  Launch 2 streams all reduction tiles and writes one
+// partial record per tile; launch 3 merges each set's records and builds its
+// octagon (one wave per set); launch 4 runs the inside test + compaction on
+// all compaction tiles from one ticket counter, with a decoupled look-back
+// per set.  Cross-block results only flow across launch boundaries, so no
+// kernel needs a device-wide fence.
 
-__device__ __forceinline__ uint32_t first_set_reaching(const uint64_t* off, uint32_t S, uint64_t target) {
-    // smallest j in [0, S) with off[j+1] >= target, or S-1
+constexpr uint32_t kBatchRChunks = 4;
+constexpr uint32_t kBatchRT = kRBlock * kRG * 2 * kBatchRChunks;   // reduction tile (points)
+
+// Last set s with start[s] <= k (start non-decreasing, start[0] == 0).
+__device__ __forceinline__ uint32_t set_of(const SetInfo* __restrict__ sets, uint32_t S, uint32_t k, bool f) {
     uint32_t lo = 0, hi = S - 1;
     while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (off[mid + 1] >= target) hi = mid;
-        else lo = mid + 1;
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        const uint32_t st = f ? sets[mid].f_tile0 : sets[mid].r_tile0;
+        if (st <= k) lo = mid;
+        else hi = mid - 1;
     }
     return lo;
 }
@@ -760,150 +985,151 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
     return r;
 }
 
-template <int BLOCK, int PPT>
 __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict__ off, uint32_t S,
-                                                     SetInfo* sets, ReduceSlots* slots,
-                                                     uint32_t* seg_start, uint32_t* seg_code,
-                                                     uint32_t* ticket, uint32_t* total,
-                                                     uint64_t* tile_status, uint32_t max_tiles,
-                                                     uint64_t lag, uint64_t n_total, uint64_t* counts) {
-    // one block of 1024 threads
-    constexpr uint32_t RT = BLOCK * kRG * 2;   // reduction tile = one chunk
-    constexpr uint32_t FT = BLOCK * PPT;       // compaction tile
+                                                     SetInfo* sets, BatchTotals* tot, uint64_t* counts,
+                                                     uint64_t* tile_status, uint32_t max_ftiles,
+                                                     uint32_t max_rtiles, uint64_t n_total, uint32_t ft) {
     __shared__ uint32_t sh_scan[1024];
     __shared__ uint32_t sh_carry[2];
     const uint32_t t = threadIdx.x;
-    if (t == 0) {
-        *ticket = 0u;
-        sh_carry[0] = sh_carry[1] = 0u;
-    }
+    if (t == 0) sh_carry[0] = sh_carry[1] = 0u;
     // offsets must start at 0, end at n_total and never decrease
     int bad = 0;
     for (uint32_t s = t; s < S; s += 1024) bad |= (off[s + 1] < off[s]) ? 1 : 0;
     if (t == 0) bad |= (off[0] != 0ull || off[S] != n_total) ? 1 : 0;
     bad = __syncthreads_or(bad);
     if (bad) {
-        for (uint32_t s = t; s < S; s += 1024) counts[s] = kCountBadOffsets;
-        if (t == 0) *total = 0u;
+        // every set empty for the later launches, every count flagged
+        for (uint32_t s = t; s < S; s += 1024) {
+            counts[s] = kCountBadOffsets;
+            sets[s].begin = 0ull;
+            sets[s].n = 0ull;
+            sets[s].r_tiles = 0u;
+            sets[s].f_tiles = 0u;
+            sets[s].r_tile0 = 0u;
+            sets[s].f_tile0 = 0u;
+        }
+        if (t == 0) {
+            tot->r_tiles = 0u;
+            tot->f_tiles = 0u;
+            tot->ticket = 0u;
+        }
         return;
     }
-    // tile counts and their prefixes
     for (uint32_t base = 0; base < S; base += 1024) {
         const uint32_t s = base + t;
-        uint32_t rt = 0, ft = 0;
+        uint32_t rt = 0, fc = 0;
         uint64_t b = 0, n = 0;
         if (s < S) {
             b = off[s];
             n = off[s + 1] - b;
             const uint64_t al = b & ~1ull;
-            rt = n ? (uint32_t)((b + n - al + RT - 1) / RT) : 0u;
-            ft = n ? (uint32_t)((b + n - al + FT - 1) / FT) : 0u;
+            rt = n ? (uint32_t)((b + n - al + kBatchRT - 1) / kBatchRT) : 0u;
+            fc = n ? (uint32_t)((b + n - al + ft - 1) / ft) : 0u;
         }
         const uint32_t r0 = block_exclusive_scan(rt, sh_scan, &sh_carry[0]);
-        const uint32_t f0 = block_exclusive_scan(ft, sh_scan, &sh_carry[1]);
+        const uint32_t f0 = block_exclusive_scan(fc, sh_scan, &sh_carry[1]);
         if (s < S) {
             sets[s].begin = b;
             sets[s].n = n;
             sets[s].r_tiles = rt;
-            sets[s].f_tiles = ft;
+            sets[s].f_tiles = fc;
             sets[s].r_tile0 = r0;
             sets[s].f_tile0 = f0;
-            sets[s].r_done = 0u;
-            reset_slots(&slots[s]);
-            slots[s].ready = 0u;
             if (n == 0) counts[s] = 0ull;
         }
     }
     const uint32_t rtiles = sh_carry[0], ftiles = sh_carry[1];
-    for (uint32_t i = t; i < ftiles && i < max_tiles; i += 1024) tile_status[i] = 0ull;
-    __syncthreads();
-    // segments (see the work-list comment above)
-    for (uint32_t s = t; s < S; s += 1024) {
-        const uint32_t js = max(s, first_set_reaching(off, S, off[s + 1] + lag));
-        uint32_t lo_i = 0, hi_i = S;   // m(s): first s' with j(s') >= s
-        while (lo_i < hi_i) {
-            const uint32_t mid = (lo_i + hi_i) >> 1;
-            if (max(mid, first_set_reaching(off, S, off[mid + 1] + lag)) >= s) hi_i = mid;
-            else lo_i = mid + 1;
-        }
-        const uint32_t ms = lo_i;
-        const uint32_t sumF_lt_ms = (ms < S) ? sets[ms].f_tile0 : ftiles;
-        const uint32_t iR = s + ms, iF = js + 1 + s;
-        seg_start[iR] = sets[s].r_tile0 + sumF_lt_ms;
-        seg_code[iR] = s << 1;
-        seg_start[iF] = sets[js].r_tile0 + sets[js].r_tiles + sets[s].f_tile0;
-        seg_code[iF] = (s << 1) | 1u;
-    }
+    const bool fits = ftiles <= max_ftiles && rtiles <= max_rtiles;
+    for (uint32_t i = t; i < ftiles && i < max_ftiles; i += 1024) tile_status[i] = 0ull;
     if (t == 0) {
-        seg_start[2 * S] = rtiles + ftiles;
-        *total = (ftiles <= max_tiles) ? rtiles + ftiles : 0u;
+        tot->r_tiles = fits ? rtiles : 0u;
+        tot->f_tiles = fits ? ftiles : 0u;
+        tot->ticket = 0u;
+    }
+}
+
+template <bool VEC4>
+__global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_batch_reduce(
+    const float2* __restrict__ pts, uint32_t S, const SetInfo* __restrict__ sets,
+    const BatchTotals* __restrict__ tot, unsigned long long* __restrict__ part) {
+    const uint32_t rtiles = tot->r_tiles;
+    for (uint32_t r = blockIdx.x; r < rtiles; r += gridDim.x) {
+        const uint32_t s = set_of(sets, S, r, false);
+        const uint64_t b = sets[s].begin, n = sets[s].n;
+        const uint64_t tb = (b & ~1ull) + (uint64_t)(r - sets[s].r_tile0) * kBatchRT;
+        BlockExtremes res;
+        reduce_points<kRBlock, kRG, VEC4>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, res);
+        if (threadIdx.x < 9) {
+            const int j = threadIdx.x;
+            unsigned long long v;
+            if (j < 8) v = (res.idx[j] != 0xFFFFFFFFu) ? pack_key(res.key[j], res.idx[j]) : 0ull;
+            else v = res.bad ? 1ull : 0ull;
+            part[(uint64_t)r * 9 + j] = v;
+        }
+    }
+}
+
+// One wave per set: merge the set's partial records, build its octagon.
+__global__ __launch_bounds__(256) void k_batch_setup(const float2* __restrict__ pts, uint32_t S,
+                                                     const SetInfo* __restrict__ sets,
+                                                     const unsigned long long* __restrict__ part,
+                                                     Octagon* octs, uint64_t* counts) {
+    const uint32_t lane = lane_id();
+    const uint32_t nwaves = gridDim.x * 4;
+    for (uint32_t s = blockIdx.x * 4 + (threadIdx.x >> 6); s < S; s += nwaves) {
+        const uint64_t n = sets[s].n;
+        if (n == 0) continue;
+        const uint32_t r0 = sets[s].r_tile0, rt = sets[s].r_tiles;
+        unsigned long long m[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) m[j] = 0ull;
+        for (uint32_t r = lane; r < rt; r += 64) {
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+                const unsigned long long v = part[(uint64_t)(r0 + r) * 9 + j];
+                m[j] = (j == 8) ? (m[j] | v) : max(m[j], v);
+            }
+        }
+        unsigned long long mine = 0ull, nf = 0ull;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            unsigned long long v = m[j];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, 64);
+                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, 64);
+                const unsigned long long u = ((unsigned long long)hi << 32) | lo;
+                v = (j == 8) ? (v | u) : max(v, u);
+            }
+            if (j == (int)(lane & 7u)) mine = v;
+            if (j == 8) nf = v;
+        }
+        const int st = setup_octagon(pts, sets[s].begin, n, mine, (uint32_t)nf, &octs[s]);
+        if (lane == 0 && st != 0) counts[s] = (st == 1) ? kCountNonFinite : kCountInternal;
     }
 }
 
 template <int BLOCK, int PPT, bool VEC4>
-__global__ __launch_bounds__(BLOCK) void k_batch(const float2* __restrict__ pts, uint32_t S,
-                                                 SetInfo* sets, ReduceSlots* slots, Octagon* octs,
-                                                 const uint32_t* __restrict__ seg_start,
-                                                 const uint32_t* __restrict__ seg_code,
-                                                 uint32_t* ticket, const uint32_t* total_p,
-                                                 uint64_t* tile_status, uint32_t* __restrict__ surv,
-                                                 uint64_t* counts) {
-    constexpr uint32_t RT = BLOCK * kRG * 2;   // reduction tile = one chunk
-    __shared__ uint32_t sh_ticket;
-    __shared__ int sh_last;
-    const uint32_t total = *total_p;
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_batch_filter(
+    const float2* __restrict__ pts, uint32_t S, const SetInfo* __restrict__ sets,
+    const Octagon* __restrict__ octs, BatchTotals* tot, uint64_t* tile_status, uint32_t* __restrict__ surv,
+    uint64_t* counts) {
+    __shared__ uint32_t sh_tk;
+    const uint32_t ftiles = tot->f_tiles;
     for (;;) {
-        if (threadIdx.x == 0) sh_ticket = atomicAdd(ticket, 1u);
+        if (threadIdx.x == 0) sh_tk = atomicAdd(&tot->ticket, 1u);
         __syncthreads();
-        const uint32_t tk = sh_ticket;
-        if (tk >= total) break;
-        // segment of this ticket: last k with seg_start[k] <= tk
-        uint32_t lo = 0, hi = 2 * S - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (seg_start[mid] <= tk) lo = mid;
-            else hi = mid - 1;
-        }
-        const uint32_t code = seg_code[lo];
-        const uint32_t s = code >> 1;
-        const uint32_t local = tk - seg_start[lo];
+        const uint32_t tk = __builtin_amdgcn_readfirstlane(sh_tk);
+        if (tk >= ftiles) break;
+        const uint32_t s = set_of(sets, S, tk, true);
+        const uint32_t local = tk - sets[s].f_tile0;
         const uint64_t b = sets[s].begin, n = sets[s].n;
-        const uint64_t al = b & ~1ull;
-        if ((code & 1u) == 0u) {
-            // reduction tile `local`: points [al + local*RT, +RT) of the set
-            const uint64_t tb = al + (uint64_t)local * RT;
-            BlockExtremes r;
-            reduce_points<BLOCK, kRG, VEC4>(pts, b, b + n, tb, 0u, 1u, 1u, r);
-            if (threadIdx.x == 0) {
-                publish_extremes(r, &slots[s]);
-                __threadfence();
-                const uint32_t prev = atomicAdd(&sets[s].r_done, 1u);
-                sh_last = (prev == sets[s].r_tiles - 1);
-            }
-            __syncthreads();
-            if (sh_last && threadIdx.x == 0) {
-                __threadfence();
-                setup_octagon(pts, b, n, &slots[s], &octs[s]);
-                reset_slots(&slots[s]);
-                __threadfence();
-                __hip_atomic_store(&slots[s].ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                if (octs[s].status != 0)
-                    counts[s] = (octs[s].status == 1) ? kCountNonFinite : kCountInternal;
-            }
-            __syncthreads();
+        const Octagon* o = &octs[s];
+        if (o->status == 0) {
+            filter_tile<BLOCK, PPT, VEC4>(pts, b, b + n, b & ~1ull, local, o, tile_status + sets[s].f_tile0,
+                                          surv + b, n, local == sets[s].f_tiles - 1 ? &counts[s] : nullptr);
         } else {
-            // compaction tile `local` of set s: wait for its octagon
-            if (threadIdx.x == 0) {
-                while (__hip_atomic_load(&slots[s].ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-                    __builtin_amdgcn_s_sleep(2);
-            }
-            __syncthreads();
-            const Octagon* o = &octs[s];
-            if (o->status == 0) {
-                filter_tile<BLOCK, PPT, VEC4>(pts, b, b + n, al, local, o,
-                                              tile_status + sets[s].f_tile0,
-                                              surv + b, n, local == sets[s].f_tiles - 1 ? &counts[s] : nullptr);
-            }
             __syncthreads();
         }
     }
@@ -923,28 +1149,15 @@ hipError_t launch_filter_t(const float2* pts, uint64_t n, const Octagon* oct, Re
 }
 
 template <int BLOCK, int PPT>
-hipError_t launch_batch_t(const float2* pts, uint32_t S, const SetInfo* sets, ReduceSlots* slots,
-                          Octagon* octs, const uint32_t* seg_start, const uint32_t* seg_code,
-                          uint32_t* ticket, const uint32_t* total, uint64_t* tile_status,
-                          uint32_t* surv, uint64_t* counts, bool vec4, int grid, hipStream_t stream) {
-    SetInfo* ms = const_cast<SetInfo*>(sets);
+hipError_t launch_batch_filter_t(const float2* pts, uint32_t S, const SetInfo* sets, const Octagon* octs,
+                                 BatchTotals* tot, uint64_t* tile_status, uint32_t* surv, uint64_t* counts,
+                                 bool vec4, int grid, hipStream_t stream) {
     if (vec4)
-        hipLaunchKernelGGL((k_batch<BLOCK, PPT, true>), dim3(grid), dim3(BLOCK), 0, stream, pts, S, ms,
-                           slots, octs, seg_start, seg_code, ticket, total, tile_status, surv, counts);
+        hipLaunchKernelGGL((k_batch_filter<BLOCK, PPT, true>), dim3(grid), dim3(BLOCK), 0, stream, pts, S,
+                           sets, octs, tot, tile_status, surv, counts);
     else
-        hipLaunchKernelGGL((k_batch<BLOCK, PPT, false>), dim3(grid), dim3(BLOCK), 0, stream, pts, S, ms,
-                           slots, octs, seg_start, seg_code, ticket, total, tile_status, surv, counts);
-    return hipGetLastError();
-}
-
-template <int BLOCK, int PPT>
-hipError_t launch_plan_t(const uint64_t* off, uint32_t S, SetInfo* sets, ReduceSlots* slots,
-                         uint32_t* seg_start, uint32_t* seg_code, uint32_t* ticket, uint32_t* total,
-                         uint64_t* tile_status, uint32_t max_tiles, uint64_t lag, uint64_t n_total,
-                         uint64_t* counts, hipStream_t stream) {
-    hipLaunchKernelGGL((k_batch_plan<BLOCK, PPT>), dim3(1), dim3(1024), 0, stream, off, S, sets, slots,
-                       seg_start, seg_code, ticket, total, tile_status, max_tiles, lag, n_total,
-                       counts);
+        hipLaunchKernelGGL((k_batch_filter<BLOCK, PPT, false>), dim3(grid), dim3(BLOCK), 0, stream, pts, S,
+                           sets, octs, tot, tile_status, surv, counts);
     return hipGetLastError();
 }
 
@@ -958,7 +1171,7 @@ bool is_vec4(const float2* p) { return ((uintptr_t)p & 15u) == 0u; }
 
 uint32_t reduce_chunk_points() { return kRBlock * kRG * 2; }
 
-uint32_t filter_tile_points(Shape s) { return (uint32_t)(s.block * s.ppt); }
+uint32_t filter_tile_points(Shape s) { return (uint32_t)(s.block * 64); }   // 64/ppt sub-tiles
 
 bool shape_supported(Shape s) {
     return (s.block == 256 || s.block == 512) && (s.ppt == 8 || s.ppt == 16 || s.ppt == 32);
@@ -970,14 +1183,20 @@ hipError_t launch_init_slots(ReduceSlots* slots, uint32_t count, hipStream_t str
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const float2* pts, uint64_t n, ReduceSlots* slots, Octagon* oct,
+hipError_t launch_reduce(const float2* pts, uint64_t n, ReduceSlots* slots, unsigned long long* part,
                          uint64_t* tile_status, uint32_t num_tiles, int grid, hipStream_t stream) {
     if (is_vec4(pts))
-        hipLaunchKernelGGL(k_reduce<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, slots, oct,
+        hipLaunchKernelGGL(k_reduce<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, slots, part,
                            tile_status, num_tiles);
     else
-        hipLaunchKernelGGL(k_reduce<false>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, slots, oct,
+        hipLaunchKernelGGL(k_reduce<false>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, slots, part,
                            tile_status, num_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsigned long long* part,
+                        uint32_t nblocks, hipStream_t stream) {
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, stream, pts, n, oct, part, nblocks);
     return hipGetLastError();
 }
 
@@ -1019,31 +1238,34 @@ uint64_t batch_max_tiles(uint64_t n_total, uint32_t S, Shape shape) {
     return n_total / (uint64_t)(shape.block * shape.ppt) + 2ull * S + 1ull;
 }
 
-hipError_t launch_batch_plan(const uint64_t* off, uint32_t S, SetInfo* sets, ReduceSlots* slots,
-                             uint32_t* seg_start, uint32_t* seg_code, uint32_t* ticket,
-                             uint32_t* total_tickets, uint64_t* tile_status, uint32_t max_tiles,
-                             uint64_t lag_points, uint64_t n_total, uint64_t* counts, Shape shape,
-                             hipStream_t stream) {
-#define X(B, P)                                                                                  \
-    if (shape.block == B && shape.ppt == P)                                                      \
-        return launch_plan_t<B, P>(off, S, sets, slots, seg_start, seg_code, ticket, total_tickets, \
-                                   tile_status, max_tiles, lag_points, n_total, counts, stream);
-    HULLF_SHAPES(X)
-#undef X
-    return hipErrorInvalidValue;
-}
+uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S) { return n_total / kBatchRT + 2ull * S + 1ull; }
 
-hipError_t launch_batch_persistent(const float2* pts, uint32_t S, const SetInfo* sets,
-                                   ReduceSlots* slots, Octagon* octs, const uint32_t* seg_start,
-                                   const uint32_t* seg_code, uint32_t* ticket,
-                                   const uint32_t* total_tickets, uint64_t* tile_status,
-                                   uint32_t* surv, uint64_t* counts, Shape shape, int grid,
-                                   hipStream_t stream) {
+hipError_t launch_batch(const float2* pts, const uint64_t* off, uint32_t S, uint64_t n_total, SetInfo* sets,
+                        BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles, Octagon* octs,
+                        uint64_t* tile_status, uint32_t max_ftiles, uint32_t* surv, uint64_t* counts,
+                        Shape shape, int cus, hipStream_t stream) {
+    if (!shape_supported(shape)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts, tile_status,
+                       max_ftiles, max_rtiles, n_total, (uint32_t)(shape.block * shape.ppt));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const bool v = is_vec4(pts);
-#define X(B, P)                                                                                     \
-    if (shape.block == B && shape.ppt == P)                                                         \
-        return launch_batch_t<B, P>(pts, S, sets, slots, octs, seg_start, seg_code, ticket,          \
-                                    total_tickets, tile_status, surv, counts, v, grid, stream);
+    const int rgrid = cus * 8;
+    if (v)
+        hipLaunchKernelGGL(k_batch_reduce<true>, dim3(rgrid), dim3(kRBlock), 0, stream, pts, S, sets, tot, part);
+    else
+        hipLaunchKernelGGL(k_batch_reduce<false>, dim3(rgrid), dim3(kRBlock), 0, stream, pts, S, sets, tot, part);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint32_t sblocks = (uint32_t)std::min<uint64_t>((S + 3) / 4, (uint64_t)cus * 8);
+    hipLaunchKernelGGL(k_batch_setup, dim3(sblocks), dim3(256), 0, stream, pts, S, sets, part, octs, counts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int fgrid = cus * (shape.block >= 512 ? 3 : 6);
+#define X(B, P)                                                                                          \
+    if (shape.block == B && shape.ppt == P)                                                              \
+        return launch_batch_filter_t<B, P>(pts, S, sets, octs, tot, tile_status, surv, counts, v, fgrid, \
+                                           stream);
     HULLF_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -17,7 +18,7 @@ using namespace hullf;
 
 namespace {
 
-constexpr int kKinds = 3;   // 0 reduce, 1 filter, 2 batched
+constexpr int kKinds = 4;   // 0 reduce, 1 filter, 2 batched, 3 octagon set-up
 
 struct GraphEntry {
     const void* pts;
@@ -44,6 +45,7 @@ struct hullf_ctx {
     // one point set
     ReduceSlots* slots = nullptr;
     Octagon* oct = nullptr;
+    unsigned long long* part = nullptr;   // 9 * kReduceMaxGrid
     uint64_t* status = nullptr;
     uint64_t status_cap = 0;
     uint64_t* count = nullptr;
@@ -57,27 +59,25 @@ struct hullf_ctx {
     uint64_t h_xy_cap = 0;
     uint64_t* h_count = nullptr;
     Octagon* h_oct = nullptr;
-    Shape filter_shape{256, 16};
+    Shape filter_shape{512, 16};
     // batched
     uint32_t b_sets_cap = 0;
     SetInfo* b_sets = nullptr;
-    ReduceSlots* b_slots = nullptr;
     Octagon* b_octs = nullptr;
-    uint32_t* b_seg_start = nullptr;
-    uint32_t* b_seg_code = nullptr;
-    uint32_t* b_ticket = nullptr;   // [0] ticket, [1] total tickets
+    BatchTotals* b_tot = nullptr;
+    unsigned long long* b_part = nullptr;
+    uint64_t b_part_cap = 0;   // records (9 words each)
     uint64_t* b_status = nullptr;
     uint64_t b_status_cap = 0;
     Shape batch_shape{256, 16};
-    uint64_t batch_lag = 16ull << 20;
     hipStream_t capture = nullptr;
     std::vector<GraphEntry> graphs;
     // timing
     bool timing = false;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
-    uint64_t launches[kKinds] = {0, 0, 0};
-    double total_ms[kKinds] = {0, 0, 0};
+    uint64_t launches[kKinds] = {0, 0, 0, 0};
+    double total_ms[kKinds] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -174,7 +174,8 @@ hipError_t timed(hullf_ctx* c, int kind, hipStream_t s, F launch) {
 int reduce_grid(const hullf_ctx* c, uint64_t n) {
     const uint64_t ch = reduce_chunk_points();
     const uint64_t nch = (n + ch - 1) / ch;
-    return (int)std::max<uint64_t>(1, std::min<uint64_t>(nch, (uint64_t)c->cus * 8));
+    const uint64_t g = std::min<uint64_t>((uint64_t)c->cus * 8, (uint64_t)kReduceMaxGrid);
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(nch, g));
 }
 
 bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0u; }
@@ -196,8 +197,9 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
     CHECK_HIP(grow_device(&c->status, &c->status_cap, tiles, s));
     const int rg = reduce_grid(c, n);
     CHECK_HIP(timed(c, 0, s, [&] {
-        return launch_reduce(pts, n, c->slots, c->oct, c->status, (uint32_t)tiles, rg, s);
+        return launch_reduce(pts, n, c->slots, c->part, c->status, (uint32_t)tiles, rg, s);
     }));
+    CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
     const int per_cu = c->filter_shape.block >= 512 ? 4 : 8;
     const int fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)c->cus * per_cu));
     CHECK_HIP(timed(c, 1, s, [&] {
@@ -212,30 +214,27 @@ hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, Shape shap
     if (S > c->b_sets_cap) {
         CHECK_HIP(hipStreamSynchronize(s));
         (void)hipFree(c->b_sets);
-        (void)hipFree(c->b_slots);
         (void)hipFree(c->b_octs);
-        (void)hipFree(c->b_seg_start);
-        (void)hipFree(c->b_seg_code);
         c->b_sets = nullptr;
-        c->b_slots = nullptr;
         c->b_octs = nullptr;
-        c->b_seg_start = nullptr;
-        c->b_seg_code = nullptr;
         c->b_sets_cap = 0;
         const uint32_t cap = std::max<uint32_t>(S, 64);
         CHECK_HIP(hipMalloc((void**)&c->b_sets, cap * sizeof(SetInfo)));
-        CHECK_HIP(hipMalloc((void**)&c->b_slots, cap * sizeof(ReduceSlots)));
         CHECK_HIP(hipMalloc((void**)&c->b_octs, cap * sizeof(Octagon)));
-        CHECK_HIP(hipMalloc((void**)&c->b_seg_start, (2ull * cap + 1) * sizeof(uint32_t)));
-        CHECK_HIP(hipMalloc((void**)&c->b_seg_code, 2ull * cap * sizeof(uint32_t)));
-        CHECK_HIP(launch_init_slots(c->b_slots, cap, s));
         c->b_sets_cap = cap;
         realloc = true;
     }
-    const uint64_t tiles = batch_max_tiles(n_total, S, shape);
-    if (tiles > 0xFFFFFFFFull) return HULLF_EINVAL;
-    if (tiles > c->b_status_cap || !c->b_status) {
-        CHECK_HIP(grow_device(&c->b_status, &c->b_status_cap, tiles, s));
+    const uint64_t ftiles = batch_max_tiles(n_total, S, shape);
+    const uint64_t rtiles = batch_max_rtiles(n_total, S);
+    if (ftiles > 0xFFFFFFFFull || rtiles > 0xFFFFFFFFull) return HULLF_EINVAL;
+    if (ftiles > c->b_status_cap || !c->b_status) {
+        CHECK_HIP(grow_device(&c->b_status, &c->b_status_cap, ftiles, s));
+        realloc = true;
+    }
+    if (rtiles > c->b_part_cap || !c->b_part) {
+        uint64_t words = c->b_part_cap * 9;
+        CHECK_HIP(grow_device(&c->b_part, &words, rtiles * 9, s));
+        c->b_part_cap = words / 9;
         realloc = true;
     }
     if (realloc) drop_graphs(c);
@@ -246,13 +245,10 @@ hullf_status enqueue_batched(hullf_ctx* c, const hullf_pt* d_pts, const uint64_t
                              uint64_t n_total, uint32_t* d_surv, uint64_t* d_counts, Shape shape,
                              hipStream_t s) {
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
-    CHECK_HIP(launch_batch_plan(d_off, S, c->b_sets, c->b_slots, c->b_seg_start, c->b_seg_code,
-                                &c->b_ticket[0], &c->b_ticket[1], c->b_status,
-                                (uint32_t)c->b_status_cap, c->batch_lag, n_total, d_counts, shape, s));
-    const int per_cu = shape.block >= 512 ? 4 : 8;
-    CHECK_HIP(launch_batch_persistent(pts, S, c->b_sets, c->b_slots, c->b_octs, c->b_seg_start,
-                                      c->b_seg_code, &c->b_ticket[0], &c->b_ticket[1], c->b_status,
-                                      d_surv, d_counts, shape, c->cus * per_cu, s));
+    CHECK_HIP(launch_batch(pts, d_off, S, n_total, c->b_sets, c->b_tot, c->b_part,
+                           (uint32_t)std::min<uint64_t>(c->b_part_cap, 0xFFFFFFFFull), c->b_octs, c->b_status,
+                           (uint32_t)std::min<uint64_t>(c->b_status_cap, 0xFFFFFFFFull), d_surv, d_counts,
+                           shape, c->cus, s));
     return HULLF_OK;
 }
 
@@ -294,12 +290,16 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cus = cus;
-    if (const char* e = std::getenv("HULLF_BATCH_LAG")) c->batch_lag = std::strtoull(e, nullptr, 10);
+    if (const char* e = std::getenv("HULLF_FILTER_SHAPE")) {   // "block,ppt"
+        Shape sh{0, 0};
+        if (std::sscanf(e, "%d,%d", &sh.block, &sh.ppt) == 2 && shape_supported(sh)) c->filter_shape = sh;
+    }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc((void**)&c->slots, sizeof(ReduceSlots));
     if (e == hipSuccess) e = hipMalloc((void**)&c->oct, sizeof(Octagon));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->part, 9ull * kReduceMaxGrid * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&c->count, sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->b_ticket, 2 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->b_tot, sizeof(BatchTotals));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_count, sizeof(uint64_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_oct, sizeof(Octagon), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
@@ -323,8 +323,8 @@ void hullf_destroy(hullf_ctx_t c) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
-    void* dev[] = {c->slots, c->oct, c->status, c->count, c->surv, c->gather, c->b_sets, c->b_slots,
-                   c->b_octs, c->b_seg_start, c->b_seg_code, c->b_ticket, c->b_status};
+    void* dev[] = {c->slots, c->oct, c->part, c->status, c->count, c->surv, c->gather,
+                   c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_status};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* host[] = {c->h_surv, c->h_xy, c->h_count, c->h_oct};
@@ -340,7 +340,9 @@ hullf_status hullf_octagon(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uin
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
-    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->slots, c->oct, nullptr, 0, reduce_grid(c, n), s); }));
+    const int rg = reduce_grid(c, n);
+    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->slots, c->part, nullptr, 0, rg, s); }));
+    CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
     CHECK_HIP(hipMemcpyAsync(c->h_oct, c->oct, sizeof(Octagon), hipMemcpyDeviceToHost, s));
     CHECK_HIP(hipStreamSynchronize(s));
     if (c->h_oct->status == 1) return HULLF_ENONFINITE;
@@ -369,7 +371,9 @@ hullf_status hullf_flags(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint8
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
-    CHECK_HIP(launch_reduce(pts, n, c->slots, c->oct, nullptr, 0, reduce_grid(c, n), s));
+    const int rg = reduce_grid(c, n);
+    CHECK_HIP(launch_reduce(pts, n, c->slots, c->part, nullptr, 0, rg, s));
+    CHECK_HIP(launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s));
     const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, (uint64_t)c->cus * 16));
     CHECK_HIP(launch_flags(pts, n, c->oct, d_flags, grid, s));
     return HULLF_OK;

@@ -202,11 +202,11 @@ class Context:
         _check(_load().hullf_timing_enable(self.handle, 1 if enable else 0), "hullf_timing_enable")
 
     def timing_read(self):
-        """{kind: (launches, total_ms)} for kinds reduce, filter, batched."""
-        launches = (ctypes.c_uint64 * 3)()
-        ms = (ctypes.c_double * 3)()
+        """{kind: (launches, total_ms)} for kinds reduce, filter, batched, setup."""
+        launches = (ctypes.c_uint64 * 4)()
+        ms = (ctypes.c_double * 4)()
         _check(_load().hullf_timing_read(self.handle, launches, ms), "hullf_timing_read")
-        return {k: (launches[i], ms[i]) for i, k in enumerate(("reduce", "filter", "batched"))}
+        return {k: (launches[i], ms[i]) for i, k in enumerate(("reduce", "filter", "batched", "setup"))}
 
 
 def exported_symbols():
