@@ -197,7 +197,7 @@ def run_bench(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "configs[1]: 3 single sets of 1e8 FP32 points -- normal N(0,1) seed 2, "
+            "workload": "3 single sets of 1e8 FP32 points -- normal N(0,1) seed 2, "
                         "circle r=1 seed 3, displaced r=1+U[-0.05,0.05] seed 4; hull_filter per set",
             "points_per_step": N_SET * len(sets),
             "filter_shape": {"block": 512, "ppt": 16, "tile_points": 32768},
@@ -232,6 +232,9 @@ def run_bench(args):
     del dpts, surv
     torch.cuda.empty_cache()
 
+    if not args.no_serving:
+        result["serving"] = bench_serving(args)
+
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(sets)
@@ -239,7 +242,7 @@ def run_bench(args):
 
 
 def bench_batched(ctx, dev):
-    """configs[3]: 4096 sets, log-uniform sizes in [100, 1e6]; one persistent
+    """4096 sets, log-uniform sizes in [100, 1e6], kinds mixed: one persistent
     launch (HIP graph) against 4096 plain hull_filter launches."""
     import torch
     from paper_2303_10581_amd import workloads
@@ -277,7 +280,7 @@ def bench_batched(ctx, dev):
     same = bool(torch.equal(counts, c1))
     n = int(pts.shape[0])
     return {
-        "workload": "configs[3]: 4096 sets, sizes log-uniform [1e2, 1e6], kinds uniform, seed 6",
+        "workload": "4096 sets, sizes log-uniform [1e2, 1e6], kinds uniform, seed 6",
         "points": n,
         "batched_ms": round(b_ms, 3),
         "batched_hulls_per_s": round(S / (b_ms / 1e3), 1),
@@ -287,6 +290,125 @@ def bench_batched(ctx, dev):
         "speedup": round(p_ms / b_ms, 2),
         "counts_match": same,
     }
+
+
+def _pool(count: int, seed: int):
+    """Distinct serving requests in page-locked host memory: sizes
+    log-uniform in [1e3, 1e7], kinds uniform, moved and scaled as in the
+    batched workload."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2303_10581_amd import workloads
+    _, sizes, kinds, seeds = workloads.arrivals(count, seed=seed, qps=1.0)
+
+    def make(k):
+        xy = workloads.request(kinds[k], int(sizes[k]), int(seeds[k]))
+        t = torch.empty(xy.shape, dtype=torch.float32, pin_memory=True)
+        t.copy_(torch.from_numpy(xy))
+        return t
+
+    with ThreadPoolExecutor(16) as ex:
+        return list(ex.map(make, range(count)))
+
+
+def _serve(srv, pool, times, order):
+    """Submit pool[order[k]] at times[k] (s, open loop) while a second
+    thread collects results; returns (latencies ms, hulls, wall s)."""
+    import threading
+    n = len(times)
+    ids = [None] * n
+    late = np.zeros(n)
+    res = [None] * n
+    ready = threading.Semaphore(0)
+
+    def collect():
+        for k in range(n):
+            ready.acquire()
+            res[k] = srv.wait(ids[k])
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    for k in range(n):
+        wait = t0 + times[k] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        late[k] = max(0.0, time.perf_counter() - (t0 + times[k]))
+        ids[k] = srv.submit(pool[order[k]])
+        ready.release()
+    th.join()
+    wall = time.perf_counter() - t0
+    lat = np.array([late[k] * 1e3 + res[k][1]["done_us"] * 1e-3 for k in range(n)])
+    return lat, res, wall
+
+
+def bench_serving(args):
+    """Serving: hull requests (sizes log-uniform in [1e3, 1e7], kinds mixed)
+    through the request loop.  A burst of every pool request at once gives
+    the capacity; open-loop Poisson arrivals at fractions of it give p50/p99
+    latency (scheduled arrival -> hull on the host) and hulls/s.  The same
+    pool run one request at a time through convex_hull (H2D, plain launch,
+    host finishing) is the per-request baseline."""
+    import torch
+    from paper_2303_10581_amd import hullf, workloads
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pool = _pool(args.serve_pool, seed=7)
+    pts = sum(int(t.shape[0]) for t in pool)
+    log(f"[bench] serving pool: {len(pool)} requests, {pts} points, {time.time() - t0:.1f}s")
+    out = {"workload": f"hull requests, sizes log-uniform [1e3, 1e7], kinds uniform, pool of {len(pool)} "
+                       f"(seed 7), Poisson arrivals", "pool_points": pts}
+
+    # per-request baseline: one at a time, plain launches
+    ctx = hullf.Context(0)
+    base_hulls = []
+    t0 = time.perf_counter()
+    for t in pool:
+        d = t.to(dev, non_blocking=False)
+        base_hulls.append(ctx.convex_hull(d))
+    base_s = time.perf_counter() - t0
+    ctx.close()
+    out["sequential_hulls_per_s"] = round(len(pool) / base_s, 1)
+    log(f"[bench] sequential baseline {len(pool) / base_s:.1f} hulls/s")
+
+    with hullf.Server(0, arena_points=args.serve_arena, max_inflight=1024,
+                      finish_threads=args.serve_finish, sort_threads=args.serve_sort) as srv:
+        # capacity: everything at once (twice; the first warms up)
+        zero = np.zeros(len(pool))
+        for rep in range(2):
+            lat, res, wall = _serve(srv, pool, zero, list(range(len(pool))))
+        cap = len(pool) / wall
+        same = all(np.array_equal(res[k][0], base_hulls[k]) for k in range(len(pool)))
+        out["capacity_hulls_per_s"] = round(cap, 1)
+        out["burst"] = {"requests": len(pool), "wall_s": round(wall, 3),
+                        "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 2)}
+        log(f"[bench] serving capacity {cap:.1f} hulls/s (burst of {len(pool)})")
+        runs = []
+        for frac in args.serve_fracs:
+            qps = frac * cap
+            m = int(min(args.serve_requests, max(200, qps * args.serve_seconds)))
+            times, _, _, _ = workloads.arrivals(m, seed=8, qps=qps)
+            order = [k % len(pool) for k in range(m)]
+            st0 = srv.stats()
+            lat, res, wall = _serve(srv, pool, times, order)
+            st1 = srv.stats()
+            same = same and all(np.array_equal(res[k][0], base_hulls[order[k]]) for k in range(m))
+            nb = st1["batches"] - st0["batches"]
+            runs.append({
+                "qps": round(qps, 1), "load": frac, "requests": m,
+                "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "hulls_per_s": round(m / wall, 1),
+                "mean_batch_requests": round((st1["batched_requests"] - st0["batched_requests"]) / max(nb, 1), 2),
+                "gpu_busy_frac": round((st1["batch_ms"] - st0["batch_ms"]) / 1e3 / wall, 4),
+            })
+            log(f"[bench] serving at {qps:.1f} qps: p50 {runs[-1]['p50_ms']} ms p99 {runs[-1]['p99_ms']} ms")
+        out["runs"] = runs
+        out["hulls_match_sequential"] = bool(same)
+        out["server"] = {"arena_points": args.serve_arena, "finish_threads": args.serve_finish,
+                         "sort_threads": args.serve_sort}
+    return out
 
 
 def profile_pass(args):
@@ -387,6 +509,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-pool", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-seconds", type=float, default=12.0)
+    ap.add_argument("--serve-fracs", type=float, nargs="+", default=[0.25, 0.5, 0.9])
+    ap.add_argument("--serve-arena", type=int, default=1 << 30)
+    ap.add_argument("--serve-finish", type=int, default=4)
+    ap.add_argument("--serve-sort", type=int, default=4)
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--parse-pmc", default=None)
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None)

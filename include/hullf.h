@@ -66,14 +66,16 @@ typedef enum {
     HULLF_ENONFINITE = 2,  /* an input coordinate is NaN or infinite */
     HULLF_ECAPACITY = 3,   /* output capacity too small; the count is still written */
     HULLF_ENOMEM = 4,      /* device or host allocation failed */
-    HULLF_EDEVICE = 5      /* a HIP runtime call failed */
+    HULLF_EDEVICE = 5,     /* a HIP runtime call failed */
+    HULLF_EAGAIN = 6       /* a served request is not finished yet */
 } hullf_status;
 
 /* Written to *d_count by the asynchronous calls when an input coordinate is
  * not finite (they cannot return HULLF_ENONFINITE without a host sync). */
 #define HULLF_COUNT_NONFINITE UINT64_MAX
 /* Written to a batched count when d_off is not a valid offset array
- * (d_off[0] != 0, decreasing, or d_off[S] != n_total). */
+ * (d_off[0] != 0, decreasing, or d_off[S] != n_total), or a segment list is
+ * not ascending and disjoint within n_total. */
 #define HULLF_COUNT_BAD_OFFSETS (UINT64_MAX - 1)
 /* Written when the device reduction produced no vertex for a direction
  * (an internal error; never expected). */
@@ -137,6 +139,20 @@ hullf_status hull_filter_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
                                  const uint64_t *d_off, uint32_t S,
                                  uint64_t n_total, uint32_t *d_surv,
                                  uint64_t *d_counts, void *stream);
+
+/* Same work as hull_filter_batched for sets placed anywhere in d_pts,
+ * launched directly (no graph).  d_seg: S (begin, count) pairs of device
+ * uint64; set s is d_pts[begin .. begin+count).  Sets must be in ascending
+ * order and disjoint, and end within n_total (gaps are allowed and not
+ * read).  d_surv: n_total device uint32; the survivors of set s are written
+ * as set-local ascending indices at d_surv + begin.  d_counts as for
+ * hull_filter_batched; an invalid list sets every count to
+ * HULLF_COUNT_BAD_OFFSETS.  This is the form a resident arena of requests
+ * uses (see hullf_server.h). */
+hullf_status hull_filter_segments(hullf_ctx_t ctx, const hullf_pt *d_pts,
+                                  const uint64_t *d_seg, uint32_t S,
+                                  uint64_t n_total, uint32_t *d_surv,
+                                  uint64_t *d_counts, void *stream);
 
 /* Same work as hull_filter_batched, launched directly (no graph), with an
  * explicit launch shape.  block in {256, 512}, ppt (points per thread per

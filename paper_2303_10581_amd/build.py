@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libhullf.so")
 ARCH = os.environ.get("HULLF_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["hullf_kernels.hip"]
-HOST_SOURCES = ["hullf_runtime.cpp", "hull_host.cpp"]
+HOST_SOURCES = ["hullf_runtime.cpp", "hullf_server.cpp", "hull_host.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", INCLUDE, "-I", CSRC]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-fno-gpu-flush-denormals-to-zero",
@@ -58,7 +58,7 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        _run([hipcc, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + f".tmp{os.getpid()}"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"], verbose)

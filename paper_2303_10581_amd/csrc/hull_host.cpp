@@ -88,10 +88,10 @@ inline bool less_xyi(const HostPt& a, const HostPt& b) {
 }
 
 // Parallel sort: sort P slices in threads, then merge pairwise in rounds.
-void sort_points(std::vector<HostPt>& p) {
+void sort_points(std::vector<HostPt>& p, unsigned max_threads) {
     const size_t n = p.size();
     unsigned hw = std::thread::hardware_concurrency();
-    size_t P = std::min<size_t>(hw ? hw : 1, 16);
+    size_t P = std::min<size_t>(hw ? hw : 1, std::max(1u, max_threads));
     if (n < (1u << 20) || P < 2) {
         std::sort(p.begin(), p.end(), less_xyi);
         return;
@@ -134,10 +134,10 @@ void sort_points(std::vector<HostPt>& p) {
 
 }  // namespace
 
-void monotone_chain(std::vector<HostPt>& p, std::vector<uint32_t>& out) {
+void monotone_chain(std::vector<HostPt>& p, std::vector<uint32_t>& out, unsigned max_threads) {
     out.clear();
     if (p.empty()) return;
-    sort_points(p);
+    sort_points(p, max_threads);
     // one entry per coordinate pair: the lowest index sorts first
     size_t d = 0;
     for (size_t k = 0; k < p.size(); ++k) {

@@ -13,8 +13,8 @@ struct HostPt {
 
 // Strict counter-clockwise hull of p (reordered in place) starting at the
 // lexicographically smallest point; the lowest index is kept per repeated
-// coordinate pair.
-void monotone_chain(std::vector<HostPt>& p, std::vector<uint32_t>& out);
+// coordinate pair.  The sort uses at most max_threads threads.
+void monotone_chain(std::vector<HostPt>& p, std::vector<uint32_t>& out, unsigned max_threads = 16);
 
 // Exact sign of (a-o) x (b-o) for FP32 points.
 int orient_sign(float ox, float oy, float ax, float ay, float bx, float by);

@@ -97,10 +97,11 @@ bool shape_supported(Shape shape);
 
 // Batched: plan, reduction, octagon set-up and compaction (four launches).
 // part: 9 * max_rtiles uint64 scratch; tile_status: max_ftiles words.
-hipError_t launch_batch(const float2* pts, const uint64_t* off, uint32_t S, uint64_t n_total, SetInfo* sets,
-                        BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles, Octagon* octs,
-                        uint64_t* tile_status, uint32_t max_ftiles, uint32_t* surv, uint64_t* counts,
-                        Shape shape, int cus, hipStream_t stream);
+// off: S+1 CSR offsets, or (seg) S (begin, count) pairs, ascending and disjoint.
+hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
+                        SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
+                        Octagon* octs, uint64_t* tile_status, uint32_t max_ftiles, uint32_t* surv,
+                        uint64_t* counts, Shape shape, int cus, hipStream_t stream);
 uint64_t batch_max_tiles(uint64_t n_total, uint32_t S, Shape shape);
 uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S);
 

@@ -119,16 +119,6 @@ __device__ __forceinline__ float4 load_pair_buf(__amdgpu_buffer_rsrc_t r, uint32
     }
 }
 
-// Pair load with per-point range checks against [lo, hi).
-__device__ __forceinline__ float4 load_pair_checked(const float2* __restrict__ pts, uint64_t g,
-                                                    uint64_t lo, uint64_t hi, bool& v0, bool& v1) {
-    v0 = (g >= lo) && (g < hi);
-    v1 = (g + 1 >= lo) && (g + 1 < hi);
-    float2 a = v0 ? pts[g] : make_float2(0.0f, 0.0f);
-    float2 b = v1 ? pts[g + 1] : make_float2(0.0f, 0.0f);
-    return make_float4(a.x, a.y, b.x, b.y);
-}
-
 // ---------------------------------------------------------------------------
 // Sec. 3.1: the eight extremes
 // ---------------------------------------------------------------------------
@@ -169,18 +159,66 @@ __device__ __forceinline__ float min8(const float* v) {
     return min3f(min3f(v[0], v[1], v[2]), min3f(v[3], v[4], v[5]), __builtin_elementwise_minimum(v[6], v[7]));
 }
 
-struct BlockExtremes {
-    float key[8];       // block best per slot (packed orientation: maxima)
-    uint32_t idx[8];    // lowest index attaining it (relative to lo), or ~0
-    int bad;            // NaN seen
+// Point of a sub-range at local index p (0 <= p < span) with the validity
+// test lo_rel <= p < hi_rel; one 8-byte buffer load, executed only for valid
+// lanes (the descriptor's record limit hi_rel also stops any access beyond it).
+__device__ __forceinline__ float2 load_point_checked(__amdgpu_buffer_rsrc_t r, uint32_t p, uint32_t lo_rel,
+                                                     uint32_t hi_rel, bool& ok) {
+    ok = (p >= lo_rel) && (p < hi_rel);
+    float2 v = make_float2(0.0f, 0.0f);
+    if (ok) {
+        const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(8u * p), 0, 0);
+        v = make_float2(__uint_as_float(a.x), __uint_as_float(a.y));
+    }
+    return v;
+}
+
+// Wave-uniform copies in scalar registers.  readfirstlane yields a signed
+// int: the low word goes through uint32_t so that it is not sign-extended
+// into the high word.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    return ((uint64_t)uniform_u32((uint32_t)(x >> 32)) << 32) | (uint64_t)uniform_u32((uint32_t)x);
+}
+
+// Descriptor and relative bounds of points [lo, hi) seen from base b
+// covering `span` points.
+struct RangeView {
+    __amdgpu_buffer_rsrc_t r;
+    uint32_t lo_rel, hi_rel;
 };
+__device__ __forceinline__ RangeView range_view(const float2* __restrict__ pts, uint64_t b, uint32_t span,
+                                                uint64_t lo, uint64_t hi) {
+    // every field is wave-uniform; readfirstlane keeps the descriptor in
+    // scalar registers (a vector-register descriptor forces a loop per access)
+    RangeView v;
+    v.lo_rel = uniform_u32(lo > b ? (uint32_t)min<uint64_t>(lo - b, span) : 0u);
+    v.hi_rel = uniform_u32(hi > b ? (uint32_t)min<uint64_t>(hi - b, span) : 0u);
+    const uint64_t a = uniform_u64(reinterpret_cast<uint64_t>(pts + b));
+    v.r = make_rsrc(reinterpret_cast<const void*>(a), 8u * v.hi_rel);
+    return v;
+}
+
+// The lane index as an opaque value: offsets derived from it inside a rarely
+// taken branch are then computed there instead of being hoisted (and kept
+// live, or spilled) across the whole kernel.
+__device__ __forceinline__ uint32_t opaque_tid() {
+    uint32_t t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
 
 // Reduction of points [lo, hi) over chunks c = c0, c0+cstep, ... < nch of
-// CH = BLOCK*G*2 points starting at the pair-aligned base al <= lo.  The
-// block result is left in `res` (valid in every thread after return).
+// CH = BLOCK*G*2 points starting at the pair-aligned base al <= lo.  On
+// return (all threads), rec[j] (j < 8) holds the block's packed (key,
+// lowest index relative to lo) for direction j, or 0 if the block saw no
+// point, and rec[8] is 1 if a NaN was seen.
 template <int BLOCK, int G, bool VEC4>
 __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, uint64_t lo, uint64_t hi, uint64_t al,
-                              uint32_t c0, uint32_t cstep, uint32_t nch, BlockExtremes& res) {
+                                              uint32_t c0, uint32_t cstep, uint32_t nch,
+                                              unsigned long long* rec) {
     constexpr uint32_t CH = BLOCK * G * 2;
     constexpr int NW = BLOCK / 64;
     __shared__ float sh_v[8][NW];
@@ -214,10 +252,11 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
                 ss[i] = xs[i] + ys[i];
                 ds[i] = xs[i] - ys[i];
             }
-#pragma unroll
-            for (int i = 0; i < 8; i += 2) bad |= __builtin_isunordered(ss[i], ss[i + 1]);
             const float m0 = max8(xs), m1 = max8(ss), m2 = max8(ys), m3 = min8(ds);
             const float m4 = min8(xs), m5 = min8(ss), m6 = min8(ys), m7 = max8(ds);
+            // maximum() propagates NaN: one test on the x+y maximum covers
+            // every NaN coordinate of the group
+            bad |= __builtin_isnan(m1);
             if (m0 > v[0]) { v[0] = m0; grp[0] = c; }
             if (m1 > v[1]) { v[1] = m1; grp[1] = c; }
             if (m2 > v[2]) { v[2] = m2; grp[2] = c; }
@@ -227,31 +266,32 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
             if (m6 < v[6]) { v[6] = m6; grp[6] = c; }
             if (m7 > v[7]) { v[7] = m7; grp[7] = c; }
         } else {
+            const RangeView rv = range_view(pts, cb, CH, lo, hi);
+            const uint32_t tt = opaque_tid();
 #pragma unroll 1
-            for (int k = 0; k < G; ++k) {
-                bool ok0, ok1;
-                const float4 q = load_pair_checked(pts, cb + 2ull * (k * BLOCK + t), lo, hi, ok0, ok1);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const bool ok = h ? ok1 : ok0;
-                    if (!ok) continue;
-                    const float x = h ? q.z : q.x, y = h ? q.w : q.y;
-                    const float s = x + y, d = x - y;
-                    bad |= __builtin_isnan(s);
-                    if (x > v[0]) { v[0] = x; grp[0] = c; }
-                    if (s > v[1]) { v[1] = s; grp[1] = c; }
-                    if (y > v[2]) { v[2] = y; grp[2] = c; }
-                    if (d < v[3]) { v[3] = d; grp[3] = c; }
-                    if (x < v[4]) { v[4] = x; grp[4] = c; }
-                    if (s < v[5]) { v[5] = s; grp[5] = c; }
-                    if (y < v[6]) { v[6] = y; grp[6] = c; }
-                    if (d > v[7]) { v[7] = d; grp[7] = c; }
-                }
+            for (uint32_t k = 0; k < 2 * G; ++k) {
+                bool ok;
+                const uint32_t p = 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
+                const float2 q = load_point_checked(rv.r, p, rv.lo_rel, rv.hi_rel, ok);
+                if (!ok) continue;
+                const float x = q.x, y = q.y;
+                const float s = x + y, d = x - y;
+                bad |= __builtin_isnan(s);
+                if (x > v[0]) { v[0] = x; grp[0] = c; }
+                if (s > v[1]) { v[1] = s; grp[1] = c; }
+                if (y > v[2]) { v[2] = y; grp[2] = c; }
+                if (d < v[3]) { v[3] = d; grp[3] = c; }
+                if (x < v[4]) { v[4] = x; grp[4] = c; }
+                if (s < v[5]) { v[5] = s; grp[5] = c; }
+                if (y < v[6]) { v[6] = y; grp[6] = c; }
+                if (d > v[7]) { v[7] = d; grp[7] = c; }
             }
         }
     }
 
-    // block best per key
+    // block best per key, then the lowest index attaining it: the threads
+    // holding the best reload the one chunk where they first reached it.
+    // Done key by key so that few values are live at once.
     const uint32_t lane = lane_id(), wave = t >> 6;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -260,47 +300,43 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
         if (lane == 0) sh_v[j][wave] = w;
     }
     __syncthreads();
-    float best[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const bool is_max = (j == 0 || j == 1 || j == 2 || j == 7);
-        float b = sh_v[j][0];
-        for (int w = 1; w < NW; ++w) b = is_max ? fmaxf(b, sh_v[j][w]) : fminf(b, sh_v[j][w]);
-        best[j] = b;
-    }
-    // lowest index attaining the best: reload the chunk where this thread
-    // first reached it
-    uint32_t cand[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        cand[j] = 0xFFFFFFFFu;
-        if (v[j] == best[j] && grp[j] < nch) {
+        float best = sh_v[j][0];
+        for (int w = 1; w < NW; ++w) best = is_max ? fmaxf(best, sh_v[j][w]) : fminf(best, sh_v[j][w]);
+        uint32_t cand = 0xFFFFFFFFu;
+        if (v[j] == best && grp[j] < nch) {
+            // the lanes in here may hold different chunks: per-lane addresses
             const uint64_t cb = al + (uint64_t)grp[j] * CH;
-            for (int k = 0; k < G && cand[j] == 0xFFFFFFFFu; ++k) {
-                const uint64_t g = cb + 2ull * (k * BLOCK + t);
-                bool ok0, ok1;
-                const float4 q = load_pair_checked(pts, g, lo, hi, ok0, ok1);
-                if (ok0 && key_of(j, q.x, q.y) == best[j]) cand[j] = (uint32_t)(g - lo);
-                else if (ok1 && key_of(j, q.z, q.w) == best[j]) cand[j] = (uint32_t)(g + 1 - lo);
+#pragma unroll 1
+            for (uint32_t k = 0; k < 2 * G; ++k) {
+                const uint64_t g = cb + 2u * ((k >> 1) * BLOCK + t) + (k & 1u);
+                if (g < lo || g >= hi) continue;
+                const float2 q = pts[g];
+                if (key_of(j, q.x, q.y) == best) {
+                    cand = (uint32_t)(g - lo);
+                    break;
+                }
             }
         }
-    }
-    __syncthreads();   // sh_v reads done before reuse of shared state
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const uint32_t w = wave_min_u32(cand[j]);
-        if (lane == 0) sh_i[j][wave] = w;
+        cand = wave_min_u32(cand);
+        if (lane == 0) sh_i[j][wave] = cand;
     }
     const int any_bad = __syncthreads_or(bad ? 1 : 0);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        uint32_t b = sh_i[j][0];
-        for (int w = 1; w < NW; ++w) b = min(b, sh_i[j][w]);
-        res.idx[j] = b;
+    if (t < 8) {
+        const int j = (int)t;
         const bool is_max = (j == 0 || j == 1 || j == 2 || j == 7);
-        res.key[j] = is_max ? best[j] : -best[j];
+        float best = sh_v[j][0];
+        uint32_t idx = sh_i[j][0];
+        for (int w = 1; w < NW; ++w) {
+            best = is_max ? fmaxf(best, sh_v[j][w]) : fminf(best, sh_v[j][w]);
+            idx = min(idx, sh_i[j][w]);
+        }
+        rec[j] = (idx != 0xFFFFFFFFu) ? pack_key(is_max ? best : -best, idx) : 0ull;
+    } else if (t == 8) {
+        rec[8] = any_bad ? 1ull : 0ull;
     }
-    res.bad = any_bad;
     __syncthreads();
 }
 
@@ -538,11 +574,16 @@ __device__ __forceinline__ uint32_t load_sub(const float2* __restrict__ pts, uin
         for (int j = 0; j < NP; ++j) q[j] = load_pair_buf<VEC4>(rs, 16u * t, 16u * j * BLOCK);
         return (NP >= 16) ? 0xFFFFFFFFu : ((1u << (2 * NP)) - 1u);
     }
+    const RangeView rv = range_view(pts, sb, ST, lo, hi);
+    const uint32_t tt = opaque_tid();
     uint32_t validm = 0;
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         bool v0, v1;
-        q[j] = load_pair_checked(pts, sb + 2ull * (j * BLOCK + t), lo, hi, v0, v1);
+        const uint32_t p = 2u * (j * BLOCK + tt);
+        const float2 a = load_point_checked(rv.r, p, rv.lo_rel, rv.hi_rel, v0);
+        const float2 b = load_point_checked(rv.r, p + 1u, rv.lo_rel, rv.hi_rel, v1);
+        q[j] = make_float4(a.x, a.y, b.x, b.y);
         validm |= (v0 ? 1u : 0u) << (2 * j);
         validm |= (v1 ? 1u : 0u) << (2 * j + 1);
     }
@@ -591,7 +632,8 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
             const int b = __ffs(pendm) - 1;
             pendm &= pendm - 1u;
             const float2 pt = *reinterpret_cast<const float2*>(
-                reinterpret_cast<const char*>(tp) + 16u * ((uint32_t)(b >> 1) * BLOCK + t) + 8u * (uint32_t)(b & 1));
+                reinterpret_cast<const char*>(tp) + 16u * ((uint32_t)(b >> 1) * BLOCK + opaque_tid()) +
+                8u * (uint32_t)(b & 1));
             // an opaque copy of the pointer keeps the compiler from hoisting
             // the binary64 edge data into registers on the hot path
             const Octagon* oo = o;
@@ -712,14 +754,17 @@ __device__ __forceinline__ void scan_lookback(uint32_t* cnt, uint32_t tile, uint
 // rank (off is relative to the tile's first survivor, so it can reach the
 // tile size `span`), values = point index relative to lo; entries at or
 // beyond cap are dropped.  vbase = (sub-tile base - lo) mod 2^32.
+// Each wave first compacts a pair slot's survivors into its own 128-word LDS
+// area `stage`, then stores them as rows of 64 consecutive words, so every
+// store instruction writes one contiguous 256-byte run.
 template <int BLOCK, int PPT>
 __device__ __forceinline__ void write_sub(uint32_t keepm, const uint32_t* off, uint64_t excl,
                                           uint32_t vbase, uint32_t* __restrict__ out, uint64_t cap,
-                                          uint32_t span) {
+                                          uint32_t span, uint32_t* stage) {
     constexpr int NP = PPT / 2;
     constexpr int NW = BLOCK / 64;
     if (__ballot(keepm != 0u) == 0ull) return;
-    const uint32_t t = threadIdx.x, wave = t >> 6;
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
     const uint64_t room = (cap > excl) ? cap - excl : 0ull;
     const uint32_t capr = room > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)room;
     const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + excl, 4u * (capr < span ? capr : span));
@@ -730,10 +775,22 @@ __device__ __forceinline__ void write_sub(uint32_t keepm, const uint32_t* off, u
         if ((b0 | b1) == 0ull) continue;
         const bool k0 = (keepm >> (2 * j)) & 1u, k1 = (keepm >> (2 * j + 1)) & 1u;
         const uint32_t idx = vbase + 2u * (j * BLOCK + t);
-        const uint32_t pos = off[j * NW + wave] + rank_below(b0) + rank_below(b1);
-        if (k0 && pos < capr) __builtin_amdgcn_raw_buffer_store_b32(idx, ro, (int)(4u * pos), 0, kAuxNT);
-        const uint32_t pos1 = pos + (k0 ? 1u : 0u);
-        if (k1 && pos1 < capr) __builtin_amdgcn_raw_buffer_store_b32(idx + 1u, ro, (int)(4u * pos1), 0, kAuxNT);
+        const uint32_t r = rank_below(b0) + rank_below(b1);
+        const uint32_t cnt = (uint32_t)(__popcll(b0) + __popcll(b1));
+        if (k0) stage[r] = idx;
+        if (k1) stage[r + (k0 ? 1u : 0u)] = idx + 1u;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t base = off[j * NW + wave];
+#pragma unroll
+        for (uint32_t h = 0; h < 2; ++h) {
+            const uint32_t w = lane + 64u * h;
+            if (w < cnt) {
+                const uint32_t pos = base + w;
+                const uint32_t val = stage[w];
+                if (pos < capr) __builtin_amdgcn_raw_buffer_store_b32(val, ro, (int)(4u * pos), 0, kAuxNT);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -748,6 +805,7 @@ __device__ __forceinline__ void filter_tile(const float2* __restrict__ pts, uint
     constexpr uint32_t T = BLOCK * PPT;
     __shared__ uint32_t sh_cnt[NS];
     __shared__ uint64_t sh_excl;
+    __shared__ uint32_t sh_stage[NW][128];
     const uint64_t tb = al + (uint64_t)tile * T;
     float4 q[NP];
     const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, tb, q);
@@ -756,9 +814,8 @@ __device__ __forceinline__ void filter_tile(const float2* __restrict__ pts, uint
     __syncthreads();
     if ((threadIdx.x >> 6) == 0) scan_lookback<NS>(sh_cnt, tile, status, &sh_excl, count);
     __syncthreads();
-    const uint64_t excl = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_excl >> 32)) << 32) |
-                          __builtin_amdgcn_readfirstlane((uint32_t)sh_excl);
-    write_sub<BLOCK, PPT>(keepm, sh_cnt, excl, (uint32_t)(tb - lo), out, cap, T);
+    const uint64_t excl = uniform_u64(sh_excl);
+    write_sub<BLOCK, PPT>(keepm, sh_cnt, excl, (uint32_t)(tb - lo), out, cap, T, sh_stage[threadIdx.x >> 6]);
     __syncthreads();
 }
 
@@ -796,15 +853,9 @@ __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 
     constexpr uint32_t CH = kRBlock * kRG * 2;
     const uint32_t nch = (uint32_t)((n + CH - 1) / CH);
-    BlockExtremes r;
-    reduce_points<kRBlock, kRG, VEC4>(pts, 0, n, 0, blockIdx.x, gridDim.x, nch, r);
-    if (threadIdx.x < 9) {
-        const int j = threadIdx.x;
-        unsigned long long v;
-        if (j < 8) v = (r.idx[j] != 0xFFFFFFFFu) ? pack_key(r.key[j], r.idx[j]) : 0ull;
-        else v = r.bad ? 1ull : 0ull;
-        part[(uint64_t)blockIdx.x * 9 + j] = v;
-    }
+    __shared__ unsigned long long rec[9];
+    reduce_points<kRBlock, kRG, VEC4>(pts, 0, n, 0, blockIdx.x, gridDim.x, nch, rec);
+    if (threadIdx.x < 9) part[(uint64_t)blockIdx.x * 9 + threadIdx.x] = rec[threadIdx.x];
 }
 
 // One point set, pass 2 (one block of 256 threads): merge the `nblocks`
@@ -871,6 +922,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     __shared__ uint32_t sh_cnt[SUB * NSS];
     __shared__ uint64_t sh_excl;
     __shared__ uint32_t sh_tk;
+    __shared__ uint32_t sh_stage[NW][128];
     const uint32_t wave = threadIdx.x >> 6;
 
     if (threadIdx.x == 0) sh_tk = atomicAdd(&slots->ticket, 1u);
@@ -897,12 +949,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
         if (wave == 0)
             scan_lookback<SUB * NSS>(sh_cnt, tile, tile_status, &sh_excl, tile == num_tiles - 1 ? count : nullptr);
         __syncthreads();
-        const uint64_t excl = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_excl >> 32)) << 32) |
-                              __builtin_amdgcn_readfirstlane((uint32_t)sh_excl);
+        const uint64_t excl = uniform_u64(sh_excl);
 #pragma unroll 1
         for (int sidx = 0; sidx < SUB; ++sidx) {
             const uint32_t k = (uint32_t)(keep >> (sidx * PPT)) & (PPT >= 32 ? 0xFFFFFFFFu : ((1u << PPT) - 1u));
-            write_sub<BLOCK, PPT>(k, &sh_cnt[sidx * NSS], excl, (uint32_t)(tb + (uint64_t)sidx * ST), surv, cap, T);
+            write_sub<BLOCK, PPT>(k, &sh_cnt[sidx * NSS], excl, (uint32_t)(tb + (uint64_t)sidx * ST), surv, cap, T,
+                                  sh_stage[wave]);
         }
         __syncthreads();
         tile = next;
@@ -985,6 +1037,20 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
     return r;
 }
 
+// Set s spans [b, e): CSR offsets (b, e) = (off[s], off[s+1]), or a segment
+// list of (begin, count) pairs, (b, e) = (seg[2s], seg[2s] + seg[2s+1]).
+template <bool SEG>
+__device__ __forceinline__ void set_span(const uint64_t* __restrict__ a, uint32_t s, uint64_t& b, uint64_t& e) {
+    if (SEG) {
+        b = a[2ull * s];
+        e = b + a[2ull * s + 1];
+    } else {
+        b = a[s];
+        e = a[s + 1];
+    }
+}
+
+template <bool SEG>
 __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict__ off, uint32_t S,
                                                      SetInfo* sets, BatchTotals* tot, uint64_t* counts,
                                                      uint64_t* tile_status, uint32_t max_ftiles,
@@ -993,10 +1059,17 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
     __shared__ uint32_t sh_carry[2];
     const uint32_t t = threadIdx.x;
     if (t == 0) sh_carry[0] = sh_carry[1] = 0u;
-    // offsets must start at 0, end at n_total and never decrease
+    // CSR: offsets start at 0, end at n_total and never decrease.  Segments:
+    // each ends within n_total, after its begin, and before the next begins
+    // (ascending, disjoint).
     int bad = 0;
-    for (uint32_t s = t; s < S; s += 1024) bad |= (off[s + 1] < off[s]) ? 1 : 0;
-    if (t == 0) bad |= (off[0] != 0ull || off[S] != n_total) ? 1 : 0;
+    for (uint32_t s = t; s < S; s += 1024) {
+        uint64_t b, e;
+        set_span<SEG>(off, s, b, e);
+        bad |= (e < b || e > n_total) ? 1 : 0;
+        if (SEG && s + 1 < S) bad |= (e > off[2ull * (s + 1)]) ? 1 : 0;
+    }
+    if (!SEG && t == 0) bad |= (off[0] != 0ull || off[S] != n_total) ? 1 : 0;
     bad = __syncthreads_or(bad);
     if (bad) {
         // every set empty for the later launches, every count flagged
@@ -1021,8 +1094,9 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
         uint32_t rt = 0, fc = 0;
         uint64_t b = 0, n = 0;
         if (s < S) {
-            b = off[s];
-            n = off[s + 1] - b;
+            uint64_t e;
+            set_span<SEG>(off, s, b, e);
+            n = e - b;
             const uint64_t al = b & ~1ull;
             rt = n ? (uint32_t)((b + n - al + kBatchRT - 1) / kBatchRT) : 0u;
             fc = n ? (uint32_t)((b + n - al + ft - 1) / ft) : 0u;
@@ -1058,15 +1132,9 @@ __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
         const uint32_t s = set_of(sets, S, r, false);
         const uint64_t b = sets[s].begin, n = sets[s].n;
         const uint64_t tb = (b & ~1ull) + (uint64_t)(r - sets[s].r_tile0) * kBatchRT;
-        BlockExtremes res;
-        reduce_points<kRBlock, kRG, VEC4>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, res);
-        if (threadIdx.x < 9) {
-            const int j = threadIdx.x;
-            unsigned long long v;
-            if (j < 8) v = (res.idx[j] != 0xFFFFFFFFu) ? pack_key(res.key[j], res.idx[j]) : 0ull;
-            else v = res.bad ? 1ull : 0ull;
-            part[(uint64_t)r * 9 + j] = v;
-        }
+        __shared__ unsigned long long rec[9];
+        reduce_points<kRBlock, kRG, VEC4>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec);
+        if (threadIdx.x < 9) part[(uint64_t)r * 9 + threadIdx.x] = rec[threadIdx.x];
     }
 }
 
@@ -1240,13 +1308,18 @@ uint64_t batch_max_tiles(uint64_t n_total, uint32_t S, Shape shape) {
 
 uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S) { return n_total / kBatchRT + 2ull * S + 1ull; }
 
-hipError_t launch_batch(const float2* pts, const uint64_t* off, uint32_t S, uint64_t n_total, SetInfo* sets,
-                        BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles, Octagon* octs,
-                        uint64_t* tile_status, uint32_t max_ftiles, uint32_t* surv, uint64_t* counts,
-                        Shape shape, int cus, hipStream_t stream) {
+hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
+                        SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
+                        Octagon* octs, uint64_t* tile_status, uint32_t max_ftiles, uint32_t* surv,
+                        uint64_t* counts, Shape shape, int cus, hipStream_t stream) {
     if (!shape_supported(shape)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts, tile_status,
-                       max_ftiles, max_rtiles, n_total, (uint32_t)(shape.block * shape.ppt));
+    const uint32_t ft = (uint32_t)(shape.block * shape.ppt);
+    if (seg)
+        hipLaunchKernelGGL(k_batch_plan<true>, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts,
+                           tile_status, max_ftiles, max_rtiles, n_total, ft);
+    else
+        hipLaunchKernelGGL(k_batch_plan<false>, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts,
+                           tile_status, max_ftiles, max_rtiles, n_total, ft);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const bool v = is_vec4(pts);

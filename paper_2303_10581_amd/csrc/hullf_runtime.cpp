@@ -243,9 +243,9 @@ hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, Shape shap
 
 hullf_status enqueue_batched(hullf_ctx* c, const hullf_pt* d_pts, const uint64_t* d_off, uint32_t S,
                              uint64_t n_total, uint32_t* d_surv, uint64_t* d_counts, Shape shape,
-                             hipStream_t s) {
+                             hipStream_t s, bool seg = false) {
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
-    CHECK_HIP(launch_batch(pts, d_off, S, n_total, c->b_sets, c->b_tot, c->b_part,
+    CHECK_HIP(launch_batch(pts, d_off, seg, S, n_total, c->b_sets, c->b_tot, c->b_part,
                            (uint32_t)std::min<uint64_t>(c->b_part_cap, 0xFFFFFFFFull), c->b_octs, c->b_status,
                            (uint32_t)std::min<uint64_t>(c->b_status_cap, 0xFFFFFFFFull), d_surv, d_counts,
                            shape, c->cus, s));
@@ -275,6 +275,7 @@ const char* hullf_status_str(hullf_status s) {
         case HULLF_ECAPACITY: return "output capacity too small";
         case HULLF_ENOMEM: return "out of memory";
         case HULLF_EDEVICE: return "HIP device error";
+        case HULLF_EAGAIN: return "request not finished";
     }
     return "unknown status";
 }
@@ -430,6 +431,23 @@ hullf_status hull_filter_batched_shape(hullf_ctx_t c, const hullf_pt* d_pts, con
     hullf_status r = HULLF_OK;
     CHECK_HIP(timed(c, 2, s, [&] {
         r = enqueue_batched(c, d_pts, d_off, S, n_total, d_surv, d_counts, shape, s);
+        return r == HULLF_OK ? hipSuccess : hipErrorLaunchFailure;
+    }));
+    return r;
+}
+
+hullf_status hull_filter_segments(hullf_ctx_t c, const hullf_pt* d_pts, const uint64_t* d_seg, uint32_t S,
+                                  uint64_t n_total, uint32_t* d_surv, uint64_t* d_counts, void* stream) {
+    hullf_status st = check_batch_args(c, d_pts, d_seg, S, n_total, d_surv, d_counts);
+    if (st != HULLF_OK || S == 0) return st;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const Shape shape = c->batch_shape;
+    st = ensure_batch(c, S, n_total, shape, s);
+    if (st != HULLF_OK) return st;
+    hullf_status r = HULLF_OK;
+    CHECK_HIP(timed(c, 2, s, [&] {
+        r = enqueue_batched(c, d_pts, d_seg, S, n_total, d_surv, d_counts, shape, s, true);
         return r == HULLF_OK ? hipSuccess : hipErrorLaunchFailure;
     }));
     return r;

@@ -15,7 +15,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhullf.so")
 
-OK, EINVAL, ENONFINITE, ECAPACITY, ENOMEM, EDEVICE = range(6)
+OK, EINVAL, ENONFINITE, ECAPACITY, ENOMEM, EDEVICE, EAGAIN = range(7)
 COUNT_NONFINITE = (1 << 64) - 1
 COUNT_BAD_OFFSETS = (1 << 64) - 2
 
@@ -46,10 +46,16 @@ def _load():
         "convex_hull": ([P, P, U64, P, U64, P, P], st),
         "hullf_flags": ([P, P, U64, P, P], st),
         "hull_filter_batched": ([P, P, P, U32, U64, P, P, P], st),
+        "hull_filter_segments": ([P, P, P, U32, U64, P, P, P], st),
         "hull_filter_batched_shape": ([P, P, P, U32, U64, P, P, I, I, P], st),
         "hullf_autotune_batched": ([P, P, P, U32, U64, P, P, I, P, P, P, P], st),
         "hullf_timing_enable": ([P, I], st),
         "hullf_timing_read": ([P, P, P], st),
+        "hullf_server_create": ([I, P, ctypes.POINTER(P)], st),
+        "hullf_server_destroy": ([P], None),
+        "hullf_server_submit": ([P, P, U64, ctypes.POINTER(U64)], st),
+        "hullf_server_wait": ([P, U64, I, P, U64, ctypes.POINTER(U64), P], st),
+        "hullf_server_stats": ([P, P], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -185,6 +191,27 @@ class Context:
         _check(st, "hull_filter_batched")
         return surv, counts
 
+    def hull_filter_segments(self, pts, seg, n_total=None, surv=None, counts=None, stream=None):
+        """Enqueue the batched filter over sets at arbitrary places.
+        seg: uint64/int64 device tensor (S, 2) of (begin, count), ascending
+        and disjoint.  Returns (surv int32[n_total], counts int64[S]);
+        survivors of set s are set-local indices at surv[begin:begin+counts[s]]."""
+        torch = _torch()
+        pts = _points(pts)
+        if seg.dim() != 2 or seg.shape[1] != 2 or not seg.is_contiguous():
+            raise TypeError("seg must be a contiguous (S, 2) tensor")
+        S = seg.shape[0]
+        if n_total is None:
+            n_total = pts.shape[0]
+        if surv is None:
+            surv = torch.empty(max(n_total, 1), dtype=torch.int32, device=pts.device)
+        if counts is None:
+            counts = torch.empty(max(S, 1), dtype=torch.int64, device=pts.device)
+        _check(_load().hull_filter_segments(self.handle, pts.data_ptr(), seg.data_ptr(), S, int(n_total),
+                                            surv.data_ptr(), counts.data_ptr(), _stream(stream)),
+               "hull_filter_segments")
+        return surv, counts
+
     def autotune_batched(self, pts, off, surv, counts, reps: int = 3, stream=None):
         """Pick the fastest (block, ppt) for the batched kernel; returns
         (block, ppt, ms)."""
@@ -209,8 +236,122 @@ class Context:
         return {k: (launches[i], ms[i]) for i, k in enumerate(("reduce", "filter", "batched", "setup"))}
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("arena_points", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("finish_threads", ctypes.c_uint32), ("sort_threads", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("admitted_us", ctypes.c_double), ("resident_us", ctypes.c_double),
+                ("launched_us", ctypes.c_double), ("filtered_us", ctypes.c_double),
+                ("done_us", ctypes.c_double), ("n", ctypes.c_uint64), ("survivors", ctypes.c_uint64),
+                ("hull", ctypes.c_uint64), ("batch", ctypes.c_uint64), ("batch_requests", ctypes.c_uint32),
+                ("status", ctypes.c_uint32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("batched_requests", ctypes.c_uint64),
+                ("arena_points", ctypes.c_uint64), ("arena_peak_points", ctypes.c_uint64),
+                ("inflight", ctypes.c_uint32), ("queued", ctypes.c_uint32), ("batch_ms", ctypes.c_double)]
+
+
+def _fields(obj):
+    return {name: getattr(obj, name) for name, _ in obj._fields_ if name != "reserved"}
+
+
+def _host_points(pts):
+    """(pointer, n, keep-alive object) of a host (n, 2) float32 array."""
+    try:
+        import torch
+        if isinstance(pts, torch.Tensor):
+            if pts.is_cuda or pts.dtype != torch.float32 or pts.dim() != 2 or pts.shape[1] != 2 \
+                    or not pts.is_contiguous():
+                raise TypeError("points must be a contiguous host float32 tensor of shape (n, 2)")
+            return pts.data_ptr(), pts.shape[0], pts
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(pts, dtype=np.float32)
+    if a.ndim != 2 or a.shape[1] != 2:
+        raise TypeError("points must have shape (n, 2)")
+    return a.ctypes.data, a.shape[0], a
+
+
+class Server:
+    """Request loop with continuous batching (include/hullf_server.h).
+
+    submit() returns an id at once; the server keeps a reference to the
+    points until wait() has returned that request's result."""
+
+    def __init__(self, device: int = 0, arena_points: int = 0, max_inflight: int = 0,
+                 finish_threads: int = 0, sort_threads: int = 0):
+        lib = _load()
+        cfg = _ServerConfig(arena_points, max_inflight, finish_threads, sort_threads, 0)
+        h = ctypes.c_void_p()
+        _check(lib.hullf_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h)),
+               "hullf_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def close(self):
+        if self.handle:
+            _load().hullf_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, pts) -> int:
+        ptr, n, keep = _host_points(pts)
+        rid = ctypes.c_uint64(0)
+        _check(_load().hullf_server_submit(self.handle, ptr, n, ctypes.byref(rid)), "hullf_server_submit")
+        self._keep[rid.value] = keep
+        return rid.value
+
+    def wait(self, rid: int, timeout_ms: int = -1):
+        """(hull uint32 array, info dict) of a finished request; None if it
+        has not finished within timeout_ms.  Raises HullfError for a failed
+        request."""
+        lib = _load()
+        keep = self._keep.get(rid)
+        cap = 64 if keep is None else max(len(keep), 1)
+        info = _RequestInfo()
+        for _ in range(2):
+            out = np.zeros(cap, dtype=np.uint32)
+            h = ctypes.c_uint64(0)
+            st = lib.hullf_server_wait(self.handle, int(rid), int(timeout_ms), out.ctypes.data, cap,
+                                       ctypes.byref(h), ctypes.byref(info))
+            if st == EAGAIN:
+                return None
+            if st == ECAPACITY:
+                cap = int(h.value)
+                continue
+            self._keep.pop(rid, None)
+            _check(st, "hullf_server_wait")
+            return out[:h.value].copy(), _fields(info)
+        raise HullfError(ECAPACITY, "hullf_server_wait")
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(_load().hullf_server_stats(self.handle, ctypes.byref(s)), "hullf_server_stats")
+        return _fields(s)
+
+
 def exported_symbols():
     """Names of the C-ABI functions the binding expects."""
     return ["hullf_create", "hullf_destroy", "hullf_status_str", "hullf_octagon", "hull_filter",
-            "convex_hull", "hullf_flags", "hull_filter_batched", "hull_filter_batched_shape",
-            "hullf_autotune_batched", "hullf_timing_enable", "hullf_timing_read"]
+            "convex_hull", "hullf_flags", "hull_filter_batched", "hull_filter_segments",
+            "hull_filter_batched_shape", "hullf_autotune_batched", "hullf_timing_enable",
+            "hullf_timing_read", "hullf_server_create", "hullf_server_destroy", "hullf_server_submit",
+            "hullf_server_wait", "hullf_server_stats"]

@@ -9,14 +9,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "hullf.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^(?:hullf_status|void|const char \*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)
-    return sorted(set(names))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"^(?:hullf_status|void|const char \*)\s*\**\s*(\w+)\s*\(", src, flags=re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -31,7 +33,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("hull_filter", "convex_hull", "hullf_octagon", "hull_filter_batched",
-                     "hullf_create", "hullf_destroy", "hullf_status_str"):
+                     "hull_filter_segments", "hullf_create", "hullf_destroy", "hullf_status_str",
+                     "hullf_server_create", "hullf_server_submit", "hullf_server_wait"):
         assert required in names
 
 
@@ -46,7 +49,7 @@ def test_binding_covers_the_header():
 
 
 def test_status_strings(lib):
-    for s in range(6):
+    for s in range(7):
         assert lib.hullf_status_str(s)
     assert b"ok" == lib.hullf_status_str(0)
 
@@ -57,6 +60,15 @@ def test_create_without_gpu_fails_cleanly(lib):
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert lib.hullf_create(0, ctypes.byref(h)) != 0
+    assert not h.value
+
+
+def test_server_create_without_gpu_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert lib.hullf_server_create(0, None, ctypes.byref(h)) != 0
     assert not h.value
 
 
