@@ -67,10 +67,14 @@ def make_sets():
     return out
 
 
-def algorithmic_bytes(n: int, survivors: int):
-    """Bytes the method must move: reduction reads 8 B/pt; the fused inside
-    test + compaction reads 8 B/pt and writes 4 B per survivor."""
-    return {"reduce": 8 * n, "filter": 8 * n + 4 * survivors}
+def algorithmic_bytes(n: int, survivors: int, two_pass: bool = True):
+    """Bytes each kernel must move.  Reduction: 8 B/pt read.  Two-pass
+    compaction: the inside test reads 8 B/pt and writes the keep bits
+    (1 bit/pt); the compaction reads the bits and writes 4 B per survivor.
+    Single pass: 8 B/pt read + 4 B per survivor written."""
+    if two_pass:
+        return {"reduce": 8 * n, "filter": 8 * n + n // 8, "compact": n // 8 + 4 * survivors}
+    return {"reduce": 8 * n, "filter": 8 * n + 4 * survivors, "compact": 0}
 
 
 def cpu_baseline(sets, budget_s: float = 15.0):
@@ -140,6 +144,9 @@ def run_bench(args):
     kt = ctx.timing_read()
     ctx.timing(False)
 
+    two_pass = kt["compact"][0] > 0
+    names = {"reduce": "k_reduce", "filter": "k_classify" if two_pass else "k_filter", "compact": "k_compact"}
+
     # per-pass, per-set breakdown (one instrumented pass per set)
     per_set = {}
     for i, (kind, _, _) in enumerate(sets):
@@ -149,39 +156,38 @@ def run_bench(args):
             ctx.hull_filter(dpts[i], surv=surv[i], count=cnt[i], stream=stream)
         r = ctx.timing_read()
         ctx.timing(False)
-        ab = algorithmic_bytes(N_SET, survivors[i])
-        red_ms = r["reduce"][1] / r["reduce"][0]
-        set_ms = r["setup"][1] / r["setup"][0]
-        fil_ms = r["filter"][1] / r["filter"][0]
-        dev_ms = red_ms + set_ms + fil_ms
-        per_set[kind] = {
-            "survivors": survivors[i],
-            "reduce_us": round(red_ms * 1e3, 2),
-            "setup_us": round(set_ms * 1e3, 2),
-            "filter_us": round(fil_ms * 1e3, 2),
-            "reduce_GBs": round(ab["reduce"] / red_ms / 1e6, 1),
-            "filter_GBs": round(ab["filter"] / fil_ms / 1e6, 1),
-            "Gpoints_s": round(N_SET / dev_ms / 1e6, 1),
-            "hbm_frac": round((ab["reduce"] + ab["filter"]) / dev_ms / 1e6 / HBM_PEAK_GBS, 3),
-        }
+        ab = algorithmic_bytes(N_SET, survivors[i], two_pass)
+        ms = {k: (r[k][1] / r[k][0] if r[k][0] else 0.0) for k in ("reduce", "setup", "filter", "compact")}
+        dev_ms = sum(ms.values())
+        entry = {"survivors": survivors[i], "setup_us": round(ms["setup"] * 1e3, 2)}
+        for k in ("reduce", "filter", "compact"):
+            if ms[k] > 0:
+                entry[f"{names[k]}_us"] = round(ms[k] * 1e3, 2)
+                entry[f"{names[k]}_GBs"] = round(ab[k] / ms[k] / 1e6, 1)
+        entry["Gpoints_s"] = round(N_SET / dev_ms / 1e6, 1)
+        entry["hbm_frac"] = round(sum(ab.values()) / dev_ms / 1e6 / HBM_PEAK_GBS, 3)
+        per_set[kind] = entry
 
     total_pts = N_SET * len(sets) * args.steps
     value = total_pts / elapsed / 1e9
     ms_per_step = elapsed * 1e3 / args.steps
 
-    # dominant kernel: the kind with the larger summed device time
-    dom = max(("reduce", "filter"), key=lambda k: kt[k][1])
-    bytes_per_step = sum(algorithmic_bytes(N_SET, s)[dom] for s in survivors)
+    # dominant kernel: the one with the largest summed device time
+    dom = max(("reduce", "filter", "compact"), key=lambda k: kt[k][1])
+    bytes_per_step = sum(algorithmic_bytes(N_SET, s, two_pass)[dom] for s in survivors)
     launches, total_ms = kt[dom]
     per_launch_bytes = bytes_per_step / len(sets)
     avg_ms = total_ms / launches
     achieved = per_launch_bytes / avg_ms / 1e6
     traffic = None
     st = stored_traffic()
-    if st and dom in st.get("bytes_per_dispatch", {}):
-        traffic = st["bytes_per_dispatch"][dom]
-    all_bytes = sum(sum(algorithmic_bytes(N_SET, s).values()) for s in survivors)
+    if st and names[dom] in st.get("bytes_per_dispatch", {}):
+        traffic = st["bytes_per_dispatch"][names[dom]]
+    all_bytes = sum(sum(algorithmic_bytes(N_SET, s, two_pass).values()) for s in survivors)
     step_hbm_frac = all_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS
+    per_kernel = {names[k]: {"launches": kt[k][0], "avg_us": round(kt[k][1] / kt[k][0] * 1e3, 2)}
+                  for k in ("reduce", "setup", "filter", "compact") if kt[k][0] and k in names}
+    per_kernel["k_setup"] = {"launches": kt["setup"][0], "avg_us": round(kt["setup"][1] / kt["setup"][0] * 1e3, 2)}
 
     result = {
         "metric": METRIC,
@@ -200,11 +206,12 @@ def run_bench(args):
             "workload": "3 single sets of 1e8 FP32 points -- normal N(0,1) seed 2, "
                         "circle r=1 seed 3, displaced r=1+U[-0.05,0.05] seed 4; hull_filter per set",
             "points_per_step": N_SET * len(sets),
-            "filter_shape": {"block": 512, "ppt": 16, "tile_points": 32768},
+            "inside_test_shape": {"block": 512, "ppt": 16},
         },
         "hbm_frac_step": round(step_hbm_frac, 3),
+        "kernels": per_kernel,
         "roofline": {
-            "kernel": "k_filter" if dom == "filter" else "k_reduce",
+            "kernel": names[dom],
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
@@ -372,7 +379,7 @@ def bench_serving(args):
     log(f"[bench] sequential baseline {len(pool) / base_s:.1f} hulls/s")
 
     with hullf.Server(0, arena_points=args.serve_arena, max_inflight=1024,
-                      finish_threads=args.serve_finish, sort_threads=args.serve_sort) as srv:
+                      finish_threads=args.serve_finish) as srv:
         # capacity: everything at once (twice; the first warms up)
         zero = np.zeros(len(pool))
         for rep in range(2):
@@ -406,8 +413,7 @@ def bench_serving(args):
             log(f"[bench] serving at {qps:.1f} qps: p50 {runs[-1]['p50_ms']} ms p99 {runs[-1]['p99_ms']} ms")
         out["runs"] = runs
         out["hulls_match_sequential"] = bool(same)
-        out["server"] = {"arena_points": args.serve_arena, "finish_threads": args.serve_finish,
-                         "sort_threads": args.serve_sort}
+        out["server"] = {"arena_points": args.serve_arena, "finish_threads": args.serve_finish}
     return out
 
 
@@ -472,7 +478,7 @@ def traffic_summary(fetch_dir, write_dir, out_path=TRAFFIC_JSON):
     kernel of the same run; the result is tagged with the kernel source hash
     so that bench.py reports it only while the kernels are unchanged."""
     def kind(name):
-        for k in ("k_reduce", "k_setup", "k_filter"):
+        for k in ("k_reduce", "k_setup", "k_filter", "k_classify", "k_compact"):
             if "::" + k in name or name.startswith(k):
                 return k
         return None
@@ -494,8 +500,7 @@ def traffic_summary(fetch_dir, write_dir, out_path=TRAFFIC_JSON):
         f = d.get("FETCH_SIZE", [])
         w = d.get("WRITE_SIZE", [])
         if f and w and len(f) == len(w):
-            out["bytes_per_dispatch"]["reduce" if k == "k_reduce" else ("filter" if k == "k_filter" else k)] = \
-                round(sum(a + b for a, b in zip(f, w)) / len(f))
+            out["bytes_per_dispatch"][k] = round(sum(a + b for a, b in zip(f, w)) / len(f))
     with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out["bytes_per_dispatch"]))
@@ -516,7 +521,6 @@ def main():
     ap.add_argument("--serve-fracs", type=float, nargs="+", default=[0.25, 0.5, 0.9])
     ap.add_argument("--serve-arena", type=int, default=1 << 30)
     ap.add_argument("--serve-finish", type=int, default=4)
-    ap.add_argument("--serve-sort", type=int, default=4)
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--parse-pmc", default=None)
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None)

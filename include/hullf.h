@@ -110,13 +110,25 @@ hullf_status hull_filter(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
                          void *stream);
 
 /* Algorithm 1 end to end, synchronous: hull_filter, then the monotone-chain
- * hull (Sec. 3.3) of the survivors on the host.
+ * hull (Sec. 3.3) of the survivors (hull_from_survivors).
  * h_hull: host array receiving the counter-clockwise vertex indices (into
  * d_pts) with capacity `cap`; *h_count receives the vertex count.  Returns
  * HULLF_ECAPACITY (with *h_count set) if cap is too small. */
 hullf_status convex_hull(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
                          uint32_t *h_hull, uint64_t cap, uint64_t *h_count,
                          void *stream);
+
+/* Hull finishing (Sec. 3.3) of a survivor list, synchronous.
+ * d_surv: m device uint32 indices into d_pts (n points), ascending, as
+ * hull_filter and the batched calls write them; every index must be below n
+ * (otherwise HULLF_EINVAL).  h_hull / cap / h_count as for convex_hull: the
+ * hull of the listed points, by indices into d_pts; of repeated
+ * coordinates the first listed index is kept.  From 2^18 survivors on the
+ * points are sorted and reduced by chunked monotone chains on the device,
+ * and only the remaining candidates are chained on the host. */
+hullf_status hull_from_survivors(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
+                                 const uint32_t *d_surv, uint64_t m, uint32_t *h_hull,
+                                 uint64_t cap, uint64_t *h_count, void *stream);
 
 /* Debug export of the bit vector of Sec. 3.2 (one byte per point, 1 =
  * survives), asynchronous.  d_flags: n device bytes.  If a coordinate is not
@@ -178,9 +190,10 @@ hullf_status hullf_autotune_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
  * launches is bracketed by HIP events on its stream.  hullf_timing_read
  * waits for those events and returns, per kernel kind, the number of
  * launches and their summed duration in milliseconds, then clears them.
- * kinds: 0 = extremes reduction, 1 = inside test + compaction,
- * 2 = batched launch (plan + persistent kernel), 3 = octagon set-up (merge
- * of the reduction's per-block records).  Arrays hold at least 4 entries. */
+ * kinds: 0 = extremes reduction, 1 = inside test (the classify pass, or
+ * the single-pass test + compaction), 2 = batched launch (plan + persistent
+ * kernels), 3 = octagon set-up (merge of the reduction's per-block
+ * records), 4 = compaction pass.  Arrays hold at least 5 entries. */
 hullf_status hullf_timing_enable(hullf_ctx_t ctx, int enable);
 hullf_status hullf_timing_read(hullf_ctx_t ctx, uint64_t *launches,
                                double *total_ms);

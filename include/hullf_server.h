@@ -12,9 +12,9 @@
  *  3. whenever the device is idle, launches one batched filter over every
  *     request whose points are resident (hull_filter_segments in hullf.h:
  *     extremes, inside test and compaction per request, one launch set);
- *  4. copies each request's survivors back, frees its arena region, and
- *     finishes its hull on a host thread (monotone chain, Sec. 3.3) while
- *     later batches run.
+ *  4. finishes each request's hull from its resident survivors
+ *     (hull_from_survivors: monotone chain, Sec. 3.3) on a finisher thread
+ *     and stream, then frees its arena region, while later batches run.
  * Requests that arrive while a batch runs join the next batch.  A request's
  * hull depends only on its own points: it is the same alone or in any mix
  * (hull conventions as in hullf.h).
@@ -38,11 +38,11 @@ typedef struct {
     uint64_t arena_points;
     /* Requests admitted at once (slots).  0 = 1024. */
     uint32_t max_inflight;
-    /* Host threads finishing hulls.  0 = 4. */
+    /* Threads finishing hulls (each with its own context and stream: the
+     * device sort and chains for large survivor sets, the host chain for
+     * small ones).  0 = 4. */
     uint32_t finish_threads;
-    /* Threads one hull's sort may use.  0 = 4. */
-    uint32_t sort_threads;
-    uint32_t reserved;
+    uint32_t reserved[2];
 } hullf_server_config;
 
 /* Timeline and sizes of one finished request.  Times are microseconds

@@ -165,6 +165,40 @@ void monotone_chain(std::vector<HostPt>& p, std::vector<uint32_t>& out, unsigned
     for (const HostPt& q : h) out.push_back(q.i);
 }
 
+namespace {
+
+// Drop repeated coordinates of a sorted list, keeping the first of a run.
+std::vector<HostPt> unique_sorted(const std::vector<HostPt>& p) {
+    std::vector<HostPt> u;
+    u.reserve(p.size());
+    for (const HostPt& q : p)
+        if (u.empty() || q.x != u.back().x || q.y != u.back().y) u.push_back(q);
+    return u;
+}
+
+}  // namespace
+
+void chain_sorted(const std::vector<HostPt>& lower, const std::vector<HostPt>& upper, std::vector<uint32_t>& out) {
+    out.clear();
+    const std::vector<HostPt> lo = unique_sorted(lower), up = unique_sorted(upper);
+    if (lo.empty()) return;
+    std::vector<HostPt> h;
+    h.reserve(lo.size() + up.size());
+    for (const HostPt& q : lo) {   // lower chain, left to right
+        while (h.size() >= 2 && orient(h[h.size() - 2], h[h.size() - 1], q) <= 0) h.pop_back();
+        h.push_back(q);
+    }
+    std::vector<HostPt> g;
+    g.reserve(up.size());
+    for (size_t k = up.size(); k-- > 0;) {   // upper chain, right to left
+        while (g.size() >= 2 && orient(g[g.size() - 2], g[g.size() - 1], up[k]) <= 0) g.pop_back();
+        g.push_back(up[k]);
+    }
+    out.reserve(h.size() + g.size());
+    for (const HostPt& q : h) out.push_back(q.i);
+    for (size_t k = 1; k + 1 < g.size(); ++k) out.push_back(g[k].i);
+}
+
 int orient_sign(float ox, float oy, float ax, float ay, float bx, float by) {
     HostPt o{ox, oy, 0}, a{ax, ay, 0}, b{bx, by, 0};
     return orient(o, a, b);

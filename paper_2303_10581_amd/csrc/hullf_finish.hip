@@ -1,0 +1,452 @@
+// Hull finishing on the device (the monotone chain of Sec. 3.3 for large
+// survivor sets): lexicographic sort of the survivors, then monotone chains
+// over fixed chunks of the sorted sequence, repeated on the chain vertices
+// until few points remain; the host chains what is left.
+//
+//   k_fin_keys     64-bit key (x, then y, order-preserving bits, -0 = +0)
+//                  and the point index of every survivor
+//   k_rs_*         stable LSD radix sort of (key, index), 8 passes of 8 bits
+//   k_chain        one thread per chunk: strict lower and upper chains of the
+//                  chunk (positions into the sorted sequence)
+//   k_scan_counts  exclusive scan of the chunk chain lengths (one block)
+//   k_chain_gather the chain vertices of all chunks, in order
+//
+// Why chunks are enough: a point that is not a vertex of its chunk's lower
+// chain lies on or above a segment between two points of the chunk, so it
+// is not a strict vertex of the lower hull of all points (likewise upper).
+// Equal coordinates sort together with the lowest index first (the sort is
+// stable and the survivors come in ascending index order); only the first
+// of a run enters a chain.
+//
+// Orientation is exact: binary64 determinant with Shewchuk's error bound
+// first; otherwise the determinant of FP32 coordinates is the sum of six
+// products that binary64 represents exactly, summed as a floating-point
+// expansion (Two-Sum, Grow-Expansion), whose largest component gives the
+// sign.  Built with -ffp-contract=off.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "hullf_internal.h"
+
+namespace hullf {
+namespace {
+
+constexpr int kRsBlock = 256;
+constexpr int kRsItems = 16;
+constexpr uint32_t kRsTile = kRsBlock * kRsItems;   // 4096 items per tile
+constexpr int kRsBins = 256;
+
+__device__ __forceinline__ uint32_t ord32(float f) {
+    f = (f == 0.0f) ? 0.0f : f;
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord32(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+__device__ __forceinline__ float key_x(uint64_t k) { return unord32((uint32_t)(k >> 32)); }
+__device__ __forceinline__ float key_y(uint64_t k) { return unord32((uint32_t)k); }
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+// An index >= n is not read: it sets *bad and takes the point (0, 0).
+__global__ __launch_bounds__(256) void k_fin_keys(const float2* __restrict__ pts, uint64_t n,
+                                                  const uint32_t* __restrict__ surv, uint32_t m,
+                                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                  uint64_t* bad) {
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < m; i += gridDim.x * 256u) {
+        const uint32_t j = surv[i];
+        float2 p = make_float2(0.0f, 0.0f);
+        if (j < n) p = pts[j];
+        else *bad = 1ull;
+        keys[i] = ((uint64_t)ord32(p.x) << 32) | ord32(p.y);
+        vals[i] = j;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// radix sort
+// ---------------------------------------------------------------------------
+// hist[d * tiles + t] = items of tile t with digit d (then, after the two
+// scans, the output position of the first of them).
+
+__global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t m, uint32_t shift,
+                                                      uint32_t tiles, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kRsBins];
+    const uint32_t t = threadIdx.x, tile = blockIdx.x;
+    h[t] = 0u;
+    __syncthreads();
+    const uint64_t base = (uint64_t)tile * kRsTile;
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        const uint64_t i = base + (uint32_t)r * kRsBlock + t;
+        if (i < m) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)t * tiles + tile] = h[t];
+}
+
+// Block d: total of digit d over all tiles.
+__global__ __launch_bounds__(256) void k_rs_rowsum(const uint32_t* __restrict__ hist, uint32_t tiles,
+                                                   uint32_t* __restrict__ rowsum) {
+    __shared__ uint32_t s[256];
+    const uint32_t d = blockIdx.x, t = threadIdx.x;
+    uint32_t acc = 0;
+    for (uint32_t i = t; i < tiles; i += 256) acc += hist[(uint64_t)d * tiles + i];
+    s[t] = acc;
+    __syncthreads();
+    for (uint32_t o = 128; o > 0; o >>= 1) {
+        if (t < o) s[t] += s[t + o];
+        __syncthreads();
+    }
+    if (t == 0) rowsum[d] = s[0];
+}
+
+// Block d: output positions of digit d per tile = (items of smaller digits)
+// + (items of digit d in earlier tiles).
+__global__ __launch_bounds__(256) void k_rs_rowscan(uint32_t* __restrict__ hist, uint32_t tiles,
+                                                    const uint32_t* __restrict__ rowsum) {
+    __shared__ uint32_t s[256];
+    __shared__ uint32_t carry;
+    const uint32_t d = blockIdx.x, t = threadIdx.x;
+    s[t] = (t < d) ? rowsum[t] : 0u;
+    __syncthreads();
+    for (uint32_t o = 128; o > 0; o >>= 1) {
+        if (t < o) s[t] += s[t + o];
+        __syncthreads();
+    }
+    if (t == 0) carry = s[0];
+    __syncthreads();
+    uint32_t* row = hist + (uint64_t)d * tiles;
+    for (uint32_t b = 0; b < tiles; b += 256) {
+        const uint32_t i = b + t;
+        const uint32_t v = (i < tiles) ? row[i] : 0u;
+        s[t] = v;
+        __syncthreads();
+        for (uint32_t o = 1; o < 256; o <<= 1) {
+            const uint32_t u = (t >= o) ? s[t - o] : 0u;
+            __syncthreads();
+            s[t] += u;
+            __syncthreads();
+        }
+        const uint32_t excl = carry + s[t] - v;
+        if (i < tiles) row[i] = excl;
+        const uint32_t tot = s[255];
+        __syncthreads();
+        if (t == 0) carry += tot;
+        __syncthreads();
+    }
+}
+
+// Stable scatter of one tile.  Items are ranked in tile order (round r,
+// then thread) per digit: lanes of a wave with equal digits are found with
+// eight ballots, earlier waves and rounds through LDS counters.  Items are
+// first placed in LDS in digit order, then written out so that each
+// digit's run of the tile is a contiguous store.
+__global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin, uint32_t m,
+                                                         uint32_t shift, uint32_t tiles,
+                                                         const uint32_t* __restrict__ hist,
+                                                         uint64_t* __restrict__ kout,
+                                                         uint32_t* __restrict__ vout) {
+    constexpr int NW = kRsBlock / 64;
+    __shared__ uint64_t sk[kRsTile];
+    __shared__ uint32_t sv[kRsTile];
+    __shared__ uint32_t cnt[kRsBins];    // tile digit counts, then their exclusive scan
+    __shared__ uint32_t gpos[kRsBins];   // output position of the tile's first item per digit
+    __shared__ uint32_t run[kRsBins];    // items of each digit placed so far
+    __shared__ uint32_t wc[NW][kRsBins];
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6, tile = blockIdx.x;
+    const uint64_t base = (uint64_t)tile * kRsTile;
+    const uint32_t nt = (uint32_t)min<uint64_t>(kRsTile, (uint64_t)m - base);
+    cnt[t] = 0u;
+    run[t] = 0u;
+    gpos[t] = hist[(uint64_t)t * tiles + tile];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wc[w][t] = 0u;
+    __syncthreads();
+    uint64_t k[kRsItems];
+    uint32_t v[kRsItems];
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        const uint32_t i = (uint32_t)r * kRsBlock + t;
+        if (i < nt) {
+            k[r] = kin[base + i];
+            v[r] = vin[base + i];
+            atomicAdd(&cnt[(uint32_t)(k[r] >> shift) & 255u], 1u);
+        } else {
+            k[r] = 0ull;
+            v[r] = 0u;
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the 256 digit counts by wave 0 (4 per lane)
+    if (wave == 0) {
+        uint32_t c[4], s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = cnt[lane * 4 + q];
+            s += c[q];
+        }
+        uint32_t incl = s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+            if ((int)lane >= o) incl += u;
+        }
+        uint32_t e = incl - s;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cnt[lane * 4 + q] = e;
+            e += c[q];
+        }
+    }
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll 1
+    for (int r = 0; r < kRsItems; ++r) {
+        const uint32_t i = (uint32_t)r * kRsBlock + t;
+        const bool valid = i < nt;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const unsigned long long bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        if (valid && rank == 0) wc[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = run[d];
+            for (uint32_t w = 0; w < wave; ++w) pre += wc[w][d];
+            const uint32_t q = cnt[d] + pre + rank;
+            if (q < kRsTile) {
+                sk[q] = k[r];
+                sv[q] = v[r];
+            }
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            add += wc[w][t];
+            wc[w][t] = 0u;
+        }
+        run[t] += add;
+        __syncthreads();
+    }
+    // LDS holds the tile in digit order; item q of digit d goes to
+    // gpos[d] + (q - cnt[d])
+#pragma unroll 1
+    for (uint32_t q = t; q < nt; q += kRsBlock) {
+        const uint64_t key = sk[q];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t o = gpos[d] + (q - cnt[d]);
+        if (o < m) {
+            kout[o] = key;
+            vout[o] = sv[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// exact orientation
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    const double bv = s - a;
+    const double av = s - bv;
+    e = (a - av) + (b - bv);
+}
+
+// Exact sign of (a-o) x (b-o) for FP32 coordinates: the six products are
+// exact in binary64 (24-bit significands, no underflow for FP32 inputs).
+__device__ __noinline__ int orient_exact_dev(float ox, float oy, float ax, float ay, float bx, float by) {
+    double t[6];
+    t[0] = (double)ax * (double)by;
+    t[1] = -((double)ay * (double)bx);
+    t[2] = -((double)ax * (double)oy);
+    t[3] = (double)ay * (double)ox;
+    t[4] = -((double)ox * (double)by);
+    t[5] = (double)oy * (double)bx;
+    double h[6];
+    int len = 0;
+    for (int i = 0; i < 6; ++i) {
+        double q = t[i];
+        for (int j = 0; j < len; ++j) {
+            double s, e;
+            two_sum(q, h[j], s, e);
+            h[j] = e;
+            q = s;
+        }
+        h[len++] = q;
+    }
+    for (int j = len - 1; j >= 0; --j)
+        if (h[j] != 0.0) return h[j] > 0.0 ? 1 : -1;
+    return 0;
+}
+
+__device__ __forceinline__ int orient_dev(float ox, float oy, float ax, float ay, float bx, float by) {
+    const double l = ((double)ax - (double)ox) * ((double)by - (double)oy);
+    const double r = ((double)ay - (double)oy) * ((double)bx - (double)ox);
+    const double det = l - r;
+    const double bound = 0x1.8000000000004p-52 * (fabs(l) + fabs(r));
+    if (det > bound) return 1;
+    if (-det > bound) return -1;
+    return orient_exact_dev(ox, oy, ax, ay, bx, by);
+}
+
+// ---------------------------------------------------------------------------
+// chunk chains
+// ---------------------------------------------------------------------------
+// Thread c takes positions [c*C, min(m, (c+1)*C)) of the sorted keys and
+// writes the positions of its strict lower chain (sign = 1: pop while the
+// turn is not counter-clockwise) or upper chain (sign = -1) to
+// out[c*C ...], their number to cnt[c].  dedup: skip a point whose key
+// equals its predecessor's (the first level only; later levels have no
+// repeats).
+__global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys, uint32_t m, uint32_t C, int sign,
+                                              int dedup, uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
+    const uint32_t c = blockIdx.x * 64u + threadIdx.x;
+    const uint32_t nch = (m + C - 1) / C;
+    if (c >= nch) return;
+    const uint32_t b = c * C, e = min(m, b + C);
+    uint32_t* st = out + (uint64_t)b;
+    uint32_t len = 0;
+    float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f;   // top (2) and below-top (1) of the stack
+    uint64_t prev = (b > 0) ? keys[b - 1] : 0ull;
+    bool have_prev = b > 0;
+    for (uint32_t i = b; i < e; ++i) {
+        const uint64_t k = keys[i];
+        if (dedup && have_prev && k == prev) continue;
+        prev = k;
+        have_prev = true;
+        const float x = key_x(k), y = key_y(k);
+        while (len >= 2 && orient_dev(x1, y1, x2, y2, x, y) * sign <= 0) {
+            --len;
+            x2 = x1;
+            y2 = y1;
+            if (len >= 2) {
+                const uint64_t kb = keys[st[len - 2]];
+                x1 = key_x(kb);
+                y1 = key_y(kb);
+            }
+        }
+        st[len++] = i;
+        x1 = x2;
+        y1 = y2;
+        x2 = x;
+        y2 = y;
+    }
+    cnt[c] = len;
+}
+
+// Exclusive scan of n counts in place (one block of 1024); the total goes
+// to *total.
+__global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ a, uint32_t n, uint32_t* total) {
+    __shared__ uint32_t s[1024];
+    __shared__ uint32_t carry;
+    const uint32_t t = threadIdx.x;
+    if (t == 0) carry = 0u;
+    __syncthreads();
+    for (uint32_t b = 0; b < n; b += 1024) {
+        const uint32_t i = b + t;
+        const uint32_t v = (i < n) ? a[i] : 0u;
+        s[t] = v;
+        __syncthreads();
+        for (uint32_t o = 1; o < 1024; o <<= 1) {
+            const uint32_t u = (t >= o) ? s[t - o] : 0u;
+            __syncthreads();
+            s[t] += u;
+            __syncthreads();
+        }
+        if (i < n) a[i] = carry + s[t] - v;
+        const uint32_t tot = s[1023];
+        __syncthreads();
+        if (t == 0) carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) *total = carry;
+}
+
+// Chain vertices of every chunk, in order: chunk c's entries out[c*C + j]
+// (j < its length, i.e. next offset - offset) go to position off[c] + j.
+__global__ __launch_bounds__(256) void k_chain_gather(const uint64_t* __restrict__ keys,
+                                                      const uint32_t* __restrict__ vals, uint32_t m, uint32_t C,
+                                                      const uint32_t* __restrict__ chain,
+                                                      const uint32_t* __restrict__ off, uint32_t total,
+                                                      uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+    const uint32_t nch = (m + C - 1) / C;
+    // one wave per chunk
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t c = blockIdx.x * 4u + (threadIdx.x >> 6); c < nch; c += gridDim.x * 4u) {
+        const uint32_t o = off[c];
+        const uint32_t end = (c + 1 < nch) ? off[c + 1] : total;
+        for (uint32_t j = lane; o + j < end; j += 64) {
+            const uint32_t p = chain[(uint64_t)c * C + j];
+            kout[o + j] = keys[p];
+            vout[o + j] = vals[p];
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+uint32_t finish_sort_tiles(uint32_t m) { return (m + kRsTile - 1) / kRsTile; }
+
+hipError_t launch_finish_keys(const float2* pts, uint64_t n, const uint32_t* surv, uint32_t m, uint64_t* keys,
+                              uint32_t* vals, uint64_t* bad, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fin_keys, dim3(grid), dim3(256), 0, stream, pts, n, surv, m, keys, vals, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
+                              uint32_t* hist, uint32_t* rowsum, hipStream_t stream) {
+    const uint32_t tiles = finish_sort_tiles(m);
+    uint64_t* ka = keys;
+    uint32_t* va = vals;
+    uint64_t* kb = keys2;
+    uint32_t* vb = vals2;
+    for (uint32_t shift = 0; shift < 64; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(kRsBlock), 0, stream, ka, m, shift, tiles, hist);
+        hipLaunchKernelGGL(k_rs_rowsum, dim3(kRsBins), dim3(256), 0, stream, hist, tiles, rowsum);
+        hipLaunchKernelGGL(k_rs_rowscan, dim3(kRsBins), dim3(256), 0, stream, hist, tiles, rowsum);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(kRsBlock), 0, stream, ka, va, m, shift, tiles, hist, kb,
+                           vb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    return hipSuccess;   // eight passes: the result is back in keys / vals
+}
+
+hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, int dedup, uint32_t* chain,
+                        uint32_t* cnt, hipStream_t stream) {
+    const uint32_t nch = (m + C - 1) / C;
+    hipLaunchKernelGGL(k_chain, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup, chain, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, hipStream_t stream) {
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, cnt, n, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint32_t m, uint32_t C,
+                               const uint32_t* chain, const uint32_t* off, uint32_t total, uint64_t* kout,
+                               uint32_t* vout, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(k_chain_gather, dim3(grid), dim3(256), 0, stream, keys, vals, m, C, chain, off, total, kout,
+                       vout);
+    return hipGetLastError();
+}
+
+}  // namespace hullf

@@ -95,14 +95,53 @@ uint32_t filter_tile_points(Shape shape);
 uint32_t reduce_chunk_points();
 bool shape_supported(Shape shape);
 
+// Two-pass compaction of one set: classify (inside test -> keep bits in
+// point order, one survivor count per block), then compact (ascending
+// indices).  Block b of both launches owns points [b*R, (b+1)*R) with
+// R = spans * compact_span_points(); grid = ceil(n / R) blocks.
+// bits: 2 * ceil(n / 128) words; blkcnt: grid words.
+uint32_t compact_span_points();
+bool classify_shape_supported(Shape shape);
+hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
+                           uint32_t* blkcnt, Shape shape, int grid, hipStream_t stream);
+hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
+                          const Octagon* oct, uint32_t* out, uint64_t cap, uint64_t* count, int grid,
+                          hipStream_t stream);
+
 // Batched: plan, reduction, octagon set-up and compaction (four launches).
-// part: 9 * max_rtiles uint64 scratch; tile_status: max_ftiles words.
-// off: S+1 CSR offsets, or (seg) S (begin, count) pairs, ascending and disjoint.
+// part: 9 * max_rtiles uint64 scratch.  off: S+1 CSR offsets, or (seg) S
+// (begin, count) pairs, ascending and disjoint.
+// Two-pass compaction when bits != nullptr: bits holds max_ftiles *
+// batch_item_words() words and blkcnt max_ftiles counts (max_ftiles >=
+// batch_max_items).  Otherwise single pass with look-back: tile_status
+// holds max_ftiles words (>= batch_max_tiles).
 hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
                         SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
-                        Octagon* octs, uint64_t* tile_status, uint32_t max_ftiles, uint32_t* surv,
-                        uint64_t* counts, Shape shape, int cus, hipStream_t stream);
+                        Octagon* octs, uint64_t* tile_status, uint64_t* bits, uint32_t* blkcnt,
+                        uint32_t max_ftiles, uint32_t* surv, uint64_t* counts, Shape shape, int cus,
+                        hipStream_t stream);
 uint64_t batch_max_tiles(uint64_t n_total, uint32_t S, Shape shape);
+uint64_t batch_max_items(uint64_t n_total, uint32_t S);
+uint32_t batch_item_words();
 uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S);
+
+// Hull finishing on the device (hullf_finish.hip).
+// keys: (ordered x << 32 | ordered y), vals: point indices.  The sort needs
+// a second key/val buffer pair of m entries, hist of 256 * tiles words and
+// rowsum of 256 words; the result is back in keys / vals.
+uint32_t finish_sort_tiles(uint32_t m);
+// An index >= n sets *bad (a word the caller zeroed) instead of being read.
+hipError_t launch_finish_keys(const float2* pts, uint64_t n, const uint32_t* surv, uint32_t m, uint64_t* keys,
+                              uint32_t* vals, uint64_t* bad, int grid, hipStream_t stream);
+hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
+                              uint32_t* hist, uint32_t* rowsum, hipStream_t stream);
+// Chains of chunks of C sorted points: chain holds m words (chunk c's
+// chain at c*C), cnt ceil(m/C) words.  sign 1 = lower, -1 = upper.
+hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, int dedup, uint32_t* chain,
+                        uint32_t* cnt, hipStream_t stream);
+hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, hipStream_t stream);
+hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint32_t m, uint32_t C,
+                               const uint32_t* chain, const uint32_t* off, uint32_t total, uint64_t* kout,
+                               uint32_t* vout, int grid, hipStream_t stream);
 
 }  // namespace hullf

@@ -961,6 +961,157 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-pass compaction: classify (inside test, keep bits) then compact
+// ---------------------------------------------------------------------------
+// Pass 1 streams the points once and stores the keep bits in point order:
+// group g is points [128g, 128g+128); word 2g holds the even points and
+// word 2g+1 the odd ones, bit l of word 2g+h being point 128g + 2l + h
+// (the layout of one wave's two ballots over a pair slot).  Block b owns the
+// points [b*R, (b+1)*R), R = spans * kSpan, and writes its survivor count;
+// no block waits for another.  Pass 2 runs the same blocks over the same
+// ranges: the sum of the earlier blocks' counts is block b's output offset,
+// and each span of kSpan points (64 groups, one per lane) is ordered by a
+// wave-wide scan of the group counts.  Both passes read or write every byte
+// once: 8 bytes per point and 1/4 byte of keep bits per point in pass 1,
+// the keep bits and 4 bytes per survivor in pass 2.
+
+constexpr uint32_t kSpan = 8192;
+constexpr uint32_t kSpanGroups = kSpan / 128;
+static_assert(kSpanGroups == 64, "one group per lane");
+
+template <int BLOCK, int PPT, bool VEC4>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_classify(
+    const float2* __restrict__ pts, uint64_t n, const Octagon* __restrict__ oct, uint32_t spans,
+    uint64_t* __restrict__ bits, uint32_t* __restrict__ blkcnt) {
+    constexpr int NP = PPT / 2;
+    constexpr int NW = BLOCK / 64;
+    constexpr uint32_t ST = BLOCK * PPT;
+    static_assert(kSpan % ST == 0, "sub-tiles tile a span");
+    static_assert(NP <= 64, "one lane per pair slot stores the bits");
+    __shared__ uint32_t sh_w[NW];
+    if (oct->status != 0) return;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t r0 = (uint64_t)blockIdx.x * spans * kSpan;
+    const uint64_t r1 = min<uint64_t>(n, r0 + (uint64_t)spans * kSpan);
+    const uint64_t ngroups = (n + 127) / 128;
+    uint32_t total = 0;
+    for (uint64_t sb = r0; sb < r1; sb += ST) {
+        float4 q[NP];
+        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q);
+        const uint32_t k = classify_sub<BLOCK, PPT>(oct, pts, sb, q, validm);
+        // lane j keeps the two ballots of pair slot j, then all NP groups
+        // of this wave are stored by one instruction
+        unsigned long long m0 = 0ull, m1 = 0ull;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
+            const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
+            if (lane == (uint32_t)j) {
+                m0 = b0;
+                m1 = b1;
+            }
+            total += (uint32_t)(__popcll(b0) + __popcll(b1));
+        }
+        const uint64_t g = (sb >> 7) + (uint64_t)(lane * NW + wave);
+        if (lane < (uint32_t)NP && g < ngroups) {
+            ulonglong2 v;
+            v.x = m0;
+            v.y = m1;
+            *reinterpret_cast<ulonglong2*>(bits + 2 * g) = v;
+        }
+    }
+    if (lane == 0) sh_w[wave] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sum += sh_w[w];
+        blkcnt[blockIdx.x] = sum;
+    }
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, uint32_t l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_compact(const uint64_t* __restrict__ bits,
+                                                   const uint32_t* __restrict__ blkcnt, uint64_t n,
+                                                   uint32_t spans, const Octagon* __restrict__ oct,
+                                                   uint32_t* __restrict__ out, uint64_t cap, uint64_t* count) {
+    constexpr int NW = BLOCK / 64;
+    __shared__ uint32_t sh_stage[NW][128];
+    __shared__ uint64_t sh_part[NW];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    if (oct->status != 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *count = (oct->status == 1) ? kCountNonFinite : kCountInternal;
+        return;
+    }
+    // output offset of this block: the survivors of all earlier blocks
+    uint64_t pre = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += BLOCK) pre += blkcnt[b];
+    pre = wave_sum_u64(pre);
+    if (lane == 0) sh_part[wave] = pre;
+    __syncthreads();
+    uint64_t base = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) base += sh_part[w];
+    base = uniform_u64(base);
+
+    const uint64_t r0 = (uint64_t)blockIdx.x * spans * kSpan;
+    const uint64_t r1 = min<uint64_t>(n, r0 + (uint64_t)spans * kSpan);
+    const uint64_t ngroups = (n + 127) / 128;
+    uint32_t* stage = sh_stage[wave];
+    for (uint64_t sb = r0; sb < r1; sb += kSpan) {
+        const uint64_t g0 = sb >> 7;
+        unsigned long long w0 = 0ull, w1 = 0ull;
+        if (g0 + lane < ngroups) {
+            const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(bits + 2 * (g0 + lane));
+            w0 = v.x;
+            w1 = v.y;
+        }
+        const uint32_t c = (uint32_t)(__popcll(w0) + __popcll(w1));
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+            if ((int)lane >= o) incl += u;
+        }
+        const uint32_t excl = incl - c;
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        // survivors of this span go to [base, base + tot); lanes store
+        // through a descriptor clipped to the capacity
+        const uint64_t room = cap > base ? cap - base : 0ull;
+        const uint32_t lim = room < (uint64_t)kSpan ? (uint32_t)room : kSpan;
+        const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + base, 4u * lim);
+        for (uint32_t g = wave; g < kSpanGroups; g += NW) {
+            const unsigned long long B0 = readlane_u64(w0, g), B1 = readlane_u64(w1, g);
+            if ((B0 | B1) == 0ull) continue;
+            const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)excl, (int)g);
+            const bool k0 = (B0 >> lane) & 1ull, k1 = (B1 >> lane) & 1ull;
+            const uint32_t r = rank_below(B0) + rank_below(B1);
+            const uint32_t cnt = (uint32_t)(__popcll(B0) + __popcll(B1));
+            const uint32_t idx = (uint32_t)((g0 + g) * 128u) + 2u * lane;
+            if (k0) stage[r] = idx;
+            if (k1) stage[r + (k0 ? 1u : 0u)] = idx + 1u;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (uint32_t h = 0; h < 2; ++h) {
+                const uint32_t w = lane + 64u * h;
+                const uint32_t pos = P + w;
+                if (w < cnt && pos < lim)
+                    __builtin_amdgcn_raw_buffer_store_b32(stage[w], ro, (int)(4u * pos), 0, kAuxNT);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        base += tot;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *count = base;
+}
+
 template <bool VEC4>
 __global__ __launch_bounds__(256) void k_flags(const float2* __restrict__ pts, uint64_t n,
                                                const Octagon* __restrict__ oct, uint8_t* flags) {
@@ -1115,7 +1266,8 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
     }
     const uint32_t rtiles = sh_carry[0], ftiles = sh_carry[1];
     const bool fits = ftiles <= max_ftiles && rtiles <= max_rtiles;
-    for (uint32_t i = t; i < ftiles && i < max_ftiles; i += 1024) tile_status[i] = 0ull;
+    if (tile_status)
+        for (uint32_t i = t; i < ftiles && i < max_ftiles; i += 1024) tile_status[i] = 0ull;
     if (t == 0) {
         tot->r_tiles = fits ? rtiles : 0u;
         tot->f_tiles = fits ? ftiles : 0u;
@@ -1175,6 +1327,155 @@ __global__ __launch_bounds__(256) void k_batch_setup(const float2* __restrict__ 
         }
         const int st = setup_octagon(pts, sets[s].begin, n, mine, (uint32_t)nf, &octs[s]);
         if (lane == 0 && st != 0) counts[s] = (st == 1) ? kCountNonFinite : kCountInternal;
+    }
+}
+
+// Two-pass compaction of a batch.  Every set is cut into work items of
+// kBatchItem points counted from its pair-aligned start al = begin & ~1
+// (SetInfo f_tiles / f_tile0 count items).  Item i owns kBatchItem/64 words
+// of keep bits (same layout as the single-set pass, groups counted from the
+// item's first point) and one survivor count.
+constexpr uint32_t kBatchItem = 4 * kSpan;
+
+template <int BLOCK, int PPT, bool VEC4>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_batch_classify(
+    const float2* __restrict__ pts, uint32_t S, const SetInfo* __restrict__ sets,
+    const Octagon* __restrict__ octs, const BatchTotals* __restrict__ tot, uint64_t* __restrict__ bits,
+    uint32_t* __restrict__ blkcnt) {
+    constexpr int NP = PPT / 2;
+    constexpr int NW = BLOCK / 64;
+    constexpr uint32_t ST = BLOCK * PPT;
+    static_assert(kBatchItem % ST == 0, "sub-tiles tile an item");
+    __shared__ uint32_t sh_w[NW];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t items = tot->f_tiles;
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const uint32_t s = set_of(sets, S, it, true);
+        const Octagon* o = &octs[s];
+        uint32_t total = 0;
+        if (o->status == 0) {
+            const uint64_t b = sets[s].begin, hi = b + sets[s].n;
+            const uint64_t r0 = (b & ~1ull) + (uint64_t)(it - sets[s].f_tile0) * kBatchItem;
+            const uint64_t r1 = min<uint64_t>(hi, r0 + kBatchItem);
+            uint64_t* ib = bits + (uint64_t)it * (kBatchItem / 64);
+            for (uint64_t sb = r0; sb < r1; sb += ST) {
+                float4 q[NP];
+                const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, b, hi, sb, q);
+                const uint32_t k = classify_sub<BLOCK, PPT>(o, pts, sb, q, validm);
+                unsigned long long m0 = 0ull, m1 = 0ull;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
+                    const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
+                    if (lane == (uint32_t)j) {
+                        m0 = b0;
+                        m1 = b1;
+                    }
+                    total += (uint32_t)(__popcll(b0) + __popcll(b1));
+                }
+                const uint32_t g = (uint32_t)((sb - r0) >> 7) + lane * NW + wave;
+                if (lane < (uint32_t)NP) {
+                    ulonglong2 v;
+                    v.x = m0;
+                    v.y = m1;
+                    *reinterpret_cast<ulonglong2*>(ib + 2 * g) = v;
+                }
+            }
+        }
+        if (lane == 0) sh_w[wave] = total;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t sum = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) sum += sh_w[w];
+            blkcnt[it] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch_compact(uint32_t S, const SetInfo* __restrict__ sets,
+                                                         const Octagon* __restrict__ octs,
+                                                         const BatchTotals* __restrict__ tot,
+                                                         const uint64_t* __restrict__ bits,
+                                                         const uint32_t* __restrict__ blkcnt,
+                                                         uint32_t* __restrict__ surv, uint64_t* counts) {
+    constexpr int NW = BLOCK / 64;
+    __shared__ uint32_t sh_stage[NW][128];
+    __shared__ uint64_t sh_part[NW];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t* stage = sh_stage[wave];
+    const uint32_t items = tot->f_tiles;
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const uint32_t s = set_of(sets, S, it, true);
+        const uint32_t first = sets[s].f_tile0, li = it - first;
+        const int ost = octs[s].status;
+        if (ost != 0) {
+            if (li == 0 && threadIdx.x == 0) counts[s] = (ost == 1) ? kCountNonFinite : kCountInternal;
+            continue;
+        }
+        // offset inside the set: survivors of the set's earlier items
+        uint64_t pre = 0;
+        for (uint32_t k = threadIdx.x; k < li; k += BLOCK) pre += blkcnt[first + k];
+        pre = wave_sum_u64(pre);
+        __syncthreads();
+        if (lane == 0) sh_part[wave] = pre;
+        __syncthreads();
+        uint64_t base = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) base += sh_part[w];
+        base = uniform_u64(base);
+
+        const uint64_t b = sets[s].begin, n = sets[s].n;
+        const uint64_t r0 = (b & ~1ull) + (uint64_t)li * kBatchItem;
+        const uint64_t r1 = min<uint64_t>(b + n, r0 + kBatchItem);
+        const uint64_t* ib = bits + (uint64_t)it * (kBatchItem / 64);
+        uint32_t* so = surv + b;
+        for (uint64_t sb = r0; sb < r1; sb += kSpan) {
+            const uint32_t g0 = (uint32_t)((sb - r0) >> 7);
+            unsigned long long w0 = 0ull, w1 = 0ull;
+            if (sb + 128ull * lane < r1) {
+                const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(ib + 2 * (g0 + lane));
+                w0 = v.x;
+                w1 = v.y;
+            }
+            const uint32_t c = (uint32_t)(__popcll(w0) + __popcll(w1));
+            uint32_t incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+                if ((int)lane >= o) incl += u;
+            }
+            const uint32_t excl = incl - c;
+            const uint32_t spantot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            const uint64_t room = n > base ? n - base : 0ull;
+            const uint32_t lim = room < (uint64_t)kSpan ? (uint32_t)room : kSpan;
+            const __amdgpu_buffer_rsrc_t ro = make_rsrc(so + base, 4u * lim);
+            for (uint32_t g = wave; g < kSpanGroups; g += NW) {
+                const unsigned long long B0 = readlane_u64(w0, g), B1 = readlane_u64(w1, g);
+                if ((B0 | B1) == 0ull) continue;
+                const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)excl, (int)g);
+                const bool k0 = (B0 >> lane) & 1ull, k1 = (B1 >> lane) & 1ull;
+                const uint32_t r = rank_below(B0) + rank_below(B1);
+                const uint32_t cnt = (uint32_t)(__popcll(B0) + __popcll(B1));
+                // set-local index of the pair's first point
+                const uint32_t idx = (uint32_t)(sb + 128ull * g - b) + 2u * lane;
+                if (k0) stage[r] = idx;
+                if (k1) stage[r + (k0 ? 1u : 0u)] = idx + 1u;
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (uint32_t h = 0; h < 2; ++h) {
+                    const uint32_t w = lane + 64u * h;
+                    const uint32_t pos = P + w;
+                    if (w < cnt && pos < lim)
+                        __builtin_amdgcn_raw_buffer_store_b32(stage[w], ro, (int)(4u * pos), 0, kAuxNT);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            base += spantot;
+        }
+        if (li == sets[s].f_tiles - 1 && threadIdx.x == 0) counts[s] = base;
     }
 }
 
@@ -1283,6 +1584,40 @@ hipError_t launch_filter(const float2* pts, uint64_t n, const Octagon* oct, Redu
     return hipErrorInvalidValue;
 }
 
+uint32_t compact_span_points() { return kSpan; }
+
+bool classify_shape_supported(Shape s) {
+    return shape_supported(s) && kSpan % (uint32_t)(s.block * s.ppt) == 0u;
+}
+
+#define HULLF_CLASSIFY_SHAPES(X) X(256, 8) X(256, 16) X(256, 32) X(512, 8) X(512, 16)
+
+hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
+                           uint32_t* blkcnt, Shape shape, int grid, hipStream_t stream) {
+    const bool v = is_vec4(pts);
+#define X(B, P)                                                                                           \
+    if (shape.block == B && shape.ppt == P) {                                                             \
+        if (v)                                                                                            \
+            hipLaunchKernelGGL((k_classify<B, P, true>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
+                               bits, blkcnt);                                                             \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_classify<B, P, false>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
+                               bits, blkcnt);                                                             \
+        return hipGetLastError();                                                                         \
+    }
+    HULLF_CLASSIFY_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
+                          const Octagon* oct, uint32_t* out, uint64_t cap, uint64_t* count, int grid,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL(k_compact<256>, dim3(grid), dim3(256), 0, stream, bits, blkcnt, n, spans, oct, out, cap,
+                       count);
+    return hipGetLastError();
+}
+
 hipError_t launch_flags(const float2* pts, uint64_t n, const Octagon* oct, uint8_t* flags, int grid,
                         hipStream_t stream) {
     hipLaunchKernelGGL(k_flags<true>, dim3(grid), dim3(256), 0, stream, pts, n, oct, flags);
@@ -1306,20 +1641,39 @@ uint64_t batch_max_tiles(uint64_t n_total, uint32_t S, Shape shape) {
     return n_total / (uint64_t)(shape.block * shape.ppt) + 2ull * S + 1ull;
 }
 
+uint64_t batch_max_items(uint64_t n_total, uint32_t S) { return n_total / kBatchItem + 2ull * S + 1ull; }
+
+uint32_t batch_item_words() { return kBatchItem / 64; }
+
 uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S) { return n_total / kBatchRT + 2ull * S + 1ull; }
+
+#define HULLF_BATCH_CLASSIFY(B, P)                                                                         \
+    if (shape.block == B && shape.ppt == P) {                                                              \
+        if (v)                                                                                             \
+            hipLaunchKernelGGL((k_batch_classify<B, P, true>), dim3(fgrid), dim3(B), 0, stream, pts, S, sets, \
+                               octs, tot, bits, blkcnt);                                                  \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_batch_classify<B, P, false>), dim3(fgrid), dim3(B), 0, stream, pts, S,     \
+                               sets, octs, tot, bits, blkcnt);                                            \
+        e = hipGetLastError();                                                                             \
+        done = true;                                                                                       \
+    }
 
 hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
                         SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
-                        Octagon* octs, uint64_t* tile_status, uint32_t max_ftiles, uint32_t* surv,
-                        uint64_t* counts, Shape shape, int cus, hipStream_t stream) {
+                        Octagon* octs, uint64_t* tile_status, uint64_t* bits, uint32_t* blkcnt,
+                        uint32_t max_ftiles, uint32_t* surv, uint64_t* counts, Shape shape, int cus,
+                        hipStream_t stream) {
     if (!shape_supported(shape)) return hipErrorInvalidValue;
-    const uint32_t ft = (uint32_t)(shape.block * shape.ppt);
+    const bool two = bits != nullptr;
+    const uint32_t ft = two ? kBatchItem : (uint32_t)(shape.block * shape.ppt);
+    uint64_t* ts = two ? nullptr : tile_status;
     if (seg)
         hipLaunchKernelGGL(k_batch_plan<true>, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts,
-                           tile_status, max_ftiles, max_rtiles, n_total, ft);
+                           ts, max_ftiles, max_rtiles, n_total, ft);
     else
         hipLaunchKernelGGL(k_batch_plan<false>, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts,
-                           tile_status, max_ftiles, max_rtiles, n_total, ft);
+                           ts, max_ftiles, max_rtiles, n_total, ft);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const bool v = is_vec4(pts);
@@ -1334,6 +1688,21 @@ hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32
     hipLaunchKernelGGL(k_batch_setup, dim3(sblocks), dim3(256), 0, stream, pts, S, sets, part, octs, counts);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (two) {
+        const int fgrid = cus * (shape.block >= 512 ? 3 : 6);
+        bool done = false;
+        HULLF_BATCH_CLASSIFY(256, 8)
+        HULLF_BATCH_CLASSIFY(256, 16)
+        HULLF_BATCH_CLASSIFY(256, 32)
+        HULLF_BATCH_CLASSIFY(512, 8)
+        HULLF_BATCH_CLASSIFY(512, 16)
+        HULLF_BATCH_CLASSIFY(512, 32)
+        if (!done) return hipErrorInvalidValue;
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_batch_compact<256>, dim3(cus * 8), dim3(256), 0, stream, S, sets, octs, tot, bits,
+                           blkcnt, surv, counts);
+        return hipGetLastError();
+    }
     const int fgrid = cus * (shape.block >= 512 ? 3 : 6);
 #define X(B, P)                                                                                          \
     if (shape.block == B && shape.ppt == P)                                                              \

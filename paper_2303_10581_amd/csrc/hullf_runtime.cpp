@@ -18,7 +18,8 @@ using namespace hullf;
 
 namespace {
 
-constexpr int kKinds = 4;   // 0 reduce, 1 filter, 2 batched, 3 octagon set-up
+constexpr int kKinds = 5;   // 0 reduce, 1 inside test, 2 batched, 3 octagon set-up, 4 compaction
+constexpr uint32_t kMaxBlocks = 4096;   // blocks of the two compaction passes
 
 struct GraphEntry {
     const void* pts;
@@ -59,7 +60,26 @@ struct hullf_ctx {
     uint64_t h_xy_cap = 0;
     uint64_t* h_count = nullptr;
     Octagon* h_oct = nullptr;
+    // hull finishing on the device (large survivor sets)
+    uint64_t* fk[3] = {nullptr, nullptr, nullptr};   // keys: sorted, then level outputs
+    uint32_t* fv[3] = {nullptr, nullptr, nullptr};   // point indices
+    uint32_t* fchain = nullptr;
+    uint32_t* fcnt = nullptr;
+    uint32_t* fhist = nullptr;
+    uint32_t* frow = nullptr;     // 256 row sums + 1 total
+    uint64_t f_cap = 0;           // entries of fk/fv/fchain
+    uint64_t fhist_cap = 0;
+    uint64_t* h_fk = nullptr;
+    uint32_t* h_fv = nullptr;
+    uint64_t h_f_cap = 0;
+    uint64_t h_fv_cap = 0;
+    uint32_t* h_total = nullptr;
     Shape filter_shape{512, 16};
+    bool two_pass = true;                  // classify + compact (else single-pass look-back)
+    bool host_finish = false;              // hull finishing always on the host
+    uint64_t* bits = nullptr;              // keep bits, 2 words per 128 points
+    uint64_t bits_cap = 0;
+    uint32_t* blkcnt = nullptr;            // kMaxBlocks survivor counts
     // batched
     uint32_t b_sets_cap = 0;
     SetInfo* b_sets = nullptr;
@@ -69,6 +89,9 @@ struct hullf_ctx {
     uint64_t b_part_cap = 0;   // records (9 words each)
     uint64_t* b_status = nullptr;
     uint64_t b_status_cap = 0;
+    uint64_t* b_bits = nullptr;            // two-pass: keep bits per work item
+    uint32_t* b_blkcnt = nullptr;          // two-pass: survivors per work item
+    uint64_t b_items_cap = 0;
     Shape batch_shape{256, 16};
     hipStream_t capture = nullptr;
     std::vector<GraphEntry> graphs;
@@ -76,8 +99,8 @@ struct hullf_ctx {
     bool timing = false;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
-    uint64_t launches[kKinds] = {0, 0, 0, 0};
-    double total_ms[kKinds] = {0, 0, 0, 0};
+    uint64_t launches[kKinds] = {0, 0, 0, 0, 0};
+    double total_ms[kKinds] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -188,24 +211,164 @@ void drop_graphs(hullf_ctx* c) {
     c->graphs.clear();
 }
 
-// Enqueue reduce + filter for one set (n >= 1).
+// Enqueue reduce + set-up + inside test and compaction for one set (n >= 1).
 hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uint32_t* d_surv,
                             uint64_t cap, uint64_t* d_count, hipStream_t s) {
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
-    const uint64_t T = filter_tile_points(c->filter_shape);
-    const uint64_t tiles = (n + T - 1) / T;
-    CHECK_HIP(grow_device(&c->status, &c->status_cap, tiles, s));
     const int rg = reduce_grid(c, n);
-    CHECK_HIP(timed(c, 0, s, [&] {
-        return launch_reduce(pts, n, c->slots, c->part, c->status, (uint32_t)tiles, rg, s);
-    }));
+    if (!c->two_pass) {
+        const uint64_t T = filter_tile_points(c->filter_shape);
+        const uint64_t tiles = (n + T - 1) / T;
+        CHECK_HIP(grow_device(&c->status, &c->status_cap, tiles, s));
+        CHECK_HIP(timed(c, 0, s, [&] {
+            return launch_reduce(pts, n, c->slots, c->part, c->status, (uint32_t)tiles, rg, s);
+        }));
+        CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
+        const int per_cu = c->filter_shape.block >= 512 ? 4 : 8;
+        const int fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)c->cus * per_cu));
+        CHECK_HIP(timed(c, 1, s, [&] {
+            return launch_filter(pts, n, c->oct, c->slots, c->status, (uint32_t)tiles, d_surv, cap,
+                                 d_count, c->filter_shape, fg, s);
+        }));
+        return HULLF_OK;
+    }
+    Shape sh = c->filter_shape;
+    if (!classify_shape_supported(sh)) sh = Shape{512, 16};
+    const uint64_t span = compact_span_points();
+    const uint64_t nspans = (n + span - 1) / span;
+    const uint64_t target = std::min<uint64_t>((uint64_t)c->cus * (sh.block >= 512 ? 3 : 6), kMaxBlocks);
+    const uint64_t spans = (nspans + target - 1) / target;
+    const int grid = (int)((nspans + spans - 1) / spans);
+    CHECK_HIP(grow_device(&c->bits, &c->bits_cap, 2 * ((n + 127) / 128), s));
+    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->slots, c->part, nullptr, 0, rg, s); }));
     CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
-    const int per_cu = c->filter_shape.block >= 512 ? 4 : 8;
-    const int fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)c->cus * per_cu));
     CHECK_HIP(timed(c, 1, s, [&] {
-        return launch_filter(pts, n, c->oct, c->slots, c->status, (uint32_t)tiles, d_surv, cap,
-                             d_count, c->filter_shape, fg, s);
+        return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, sh, grid, s);
     }));
+    CHECK_HIP(timed(c, 4, s, [&] {
+        return launch_compact(c->bits, c->blkcnt, n, (uint32_t)spans, c->oct, d_surv, cap, d_count, grid, s);
+    }));
+    return HULLF_OK;
+}
+
+constexpr uint32_t kChainChunk = 256;          // sorted points per chain thread
+constexpr uint64_t kDeviceFinishMin = 1u << 18;   // survivors from which the device sorts and chains
+constexpr uint32_t kHostChainMax = 1u << 16;      // chain levels stop at this many candidates
+
+hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
+    if (m > c->f_cap) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        for (int k = 0; k < 3; ++k) {
+            (void)hipFree(c->fk[k]);
+            (void)hipFree(c->fv[k]);
+            c->fk[k] = nullptr;
+            c->fv[k] = nullptr;
+        }
+        (void)hipFree(c->fchain);
+        (void)hipFree(c->fcnt);
+        c->fchain = nullptr;
+        c->fcnt = nullptr;
+        c->f_cap = 0;
+        const uint64_t cap = m + m / 8 + 1024;
+        for (int k = 0; k < 3; ++k) {
+            if ((e = hipMalloc((void**)&c->fk[k], cap * sizeof(uint64_t))) != hipSuccess) return e;
+            if ((e = hipMalloc((void**)&c->fv[k], cap * sizeof(uint32_t))) != hipSuccess) return e;
+        }
+        if ((e = hipMalloc((void**)&c->fchain, cap * sizeof(uint32_t))) != hipSuccess) return e;
+        if ((e = hipMalloc((void**)&c->fcnt, (cap / kChainChunk + 1) * sizeof(uint32_t))) != hipSuccess) return e;
+        c->f_cap = cap;
+    }
+    const uint64_t hw = 256ull * finish_sort_tiles((uint32_t)m);
+    hipError_t e = grow_device(&c->fhist, &c->fhist_cap, hw, s);
+    if (e != hipSuccess) return e;
+    // frow: 256 row sums, [256] a total, [258..259] the bad-index flag (uint64)
+    if (!c->frow && (e = hipMalloc((void**)&c->frow, 260 * sizeof(uint32_t))) != hipSuccess) return e;
+    if (!c->h_total && (e = hipHostMalloc((void**)&c->h_total, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+inline float unord_host(uint32_t k) {
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    float f;
+    std::memcpy(&f, &u, sizeof f);
+    return f;
+}
+
+// Sort the m survivors on the device, reduce them to chain candidates by
+// chunked monotone chains, and finish on the host.
+hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const uint32_t* d_surv, uint64_t m,
+                              std::vector<uint32_t>& out, hipStream_t s) {
+    CHECK_HIP(ensure_finish(c, m, s));
+    const uint32_t mm = (uint32_t)m;
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((m + 255) / 256, (uint64_t)c->cus * 8));
+    uint64_t* bad = reinterpret_cast<uint64_t*>(c->frow + 258);
+    CHECK_HIP(launch_write_count(bad, 0, s));
+    CHECK_HIP(launch_finish_keys(pts, n, d_surv, mm, c->fk[0], c->fv[0], bad, grid, s));
+    CHECK_HIP(hipMemcpyAsync(c->h_count, bad, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    if (*c->h_count != 0) return HULLF_EINVAL;
+    CHECK_HIP(launch_finish_sort(c->fk[0], c->fv[0], c->fk[1], c->fv[1], mm, c->fhist, c->frow, s));
+    std::vector<HostPt> lists[2];
+    for (int side = 0; side < 2; ++side) {
+        const int sign = side == 0 ? 1 : -1;
+        int cur = 0, dedup = 1;
+        uint32_t cm = mm;
+        while (cm > kHostChainMax) {
+            const int nxt = (cur == 1) ? 2 : 1;
+            const uint32_t nch = (cm + kChainChunk - 1) / kChainChunk;
+            CHECK_HIP(launch_chain(c->fk[cur], cm, kChainChunk, sign, dedup, c->fchain, c->fcnt, s));
+            CHECK_HIP(launch_scan_counts(c->fcnt, nch, c->frow + 256, s));
+            CHECK_HIP(hipMemcpyAsync(c->h_total, c->frow + 256, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            CHECK_HIP(hipStreamSynchronize(s));
+            const uint32_t tot = *c->h_total;
+            if (tot > cm) return HULLF_EDEVICE;
+            const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((nch + 3) / 4, (uint32_t)c->cus * 8));
+            CHECK_HIP(launch_chain_gather(c->fk[cur], c->fv[cur], cm, kChainChunk, c->fchain, c->fcnt, tot,
+                                          c->fk[nxt], c->fv[nxt], gg, s));
+            const bool slow = (uint64_t)tot * 4 > (uint64_t)cm * 3;   // little left to gain
+            cur = nxt;
+            dedup = 0;
+            cm = tot;
+            if (slow) break;
+        }
+        CHECK_HIP(grow_host(&c->h_fk, &c->h_f_cap, cm));
+        CHECK_HIP(grow_host(&c->h_fv, &c->h_fv_cap, cm));
+        CHECK_HIP(hipMemcpyAsync(c->h_fk, c->fk[cur], (uint64_t)cm * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipMemcpyAsync(c->h_fv, c->fv[cur], (uint64_t)cm * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        std::vector<HostPt>& L = lists[side];
+        L.resize(cm);
+        for (uint32_t k = 0; k < cm; ++k)
+            L[k] = HostPt{unord_host((uint32_t)(c->h_fk[k] >> 32)), unord_host((uint32_t)c->h_fk[k]), c->h_fv[k]};
+    }
+    chain_sorted(lists[0], lists[1], out);
+    return HULLF_OK;
+}
+
+// Hull of pts[d_surv[0..m)] (m indices below n, ascending): the host chain
+// for few survivors, the device sort and chains for many.
+hullf_status hull_of(hullf_ctx* c, const float2* pts, uint64_t n, const uint32_t* d_surv, uint64_t m,
+                     std::vector<uint32_t>& out, hipStream_t s) {
+    out.clear();
+    if (m == 0) return HULLF_OK;
+    if (m >= kDeviceFinishMin && !c->host_finish) return finish_on_device(c, pts, n, d_surv, m, out, s);
+    CHECK_HIP(grow_device(&c->gather, &c->gather_cap, m, s));
+    CHECK_HIP(grow_host(&c->h_surv, &c->h_cap, m));
+    CHECK_HIP(grow_host(&c->h_xy, &c->h_xy_cap, m));
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((m + 255) / 256, (uint64_t)c->cus * 8));
+    CHECK_HIP(launch_write_count(c->count, m, s));
+    CHECK_HIP(launch_gather(pts, d_surv, c->count, m, n, c->gather, grid, s));
+    CHECK_HIP(hipMemcpyAsync(c->h_surv, d_surv, m * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipMemcpyAsync(c->h_xy, c->gather, m * sizeof(float2), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<HostPt> p(m);
+    for (uint64_t k = 0; k < m; ++k) {
+        if (c->h_surv[k] >= n) return HULLF_EINVAL;
+        p[k] = HostPt{c->h_xy[k].x, c->h_xy[k].y, c->h_surv[k]};
+    }
+    monotone_chain(p, out);
     return HULLF_OK;
 }
 
@@ -224,10 +387,24 @@ hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, Shape shap
         c->b_sets_cap = cap;
         realloc = true;
     }
-    const uint64_t ftiles = batch_max_tiles(n_total, S, shape);
+    const uint64_t ftiles = c->two_pass ? batch_max_items(n_total, S) : batch_max_tiles(n_total, S, shape);
     const uint64_t rtiles = batch_max_rtiles(n_total, S);
     if (ftiles > 0xFFFFFFFFull || rtiles > 0xFFFFFFFFull) return HULLF_EINVAL;
-    if (ftiles > c->b_status_cap || !c->b_status) {
+    if (c->two_pass) {
+        if (ftiles > c->b_items_cap || !c->b_bits || !c->b_blkcnt) {
+            CHECK_HIP(hipStreamSynchronize(s));
+            (void)hipFree(c->b_bits);
+            (void)hipFree(c->b_blkcnt);
+            c->b_bits = nullptr;
+            c->b_blkcnt = nullptr;
+            c->b_items_cap = 0;
+            const uint64_t cap = ftiles + ftiles / 4 + 64;
+            CHECK_HIP(hipMalloc((void**)&c->b_bits, cap * batch_item_words() * sizeof(uint64_t)));
+            CHECK_HIP(hipMalloc((void**)&c->b_blkcnt, cap * sizeof(uint32_t)));
+            c->b_items_cap = cap;
+            realloc = true;
+        }
+    } else if (ftiles > c->b_status_cap || !c->b_status) {
         CHECK_HIP(grow_device(&c->b_status, &c->b_status_cap, ftiles, s));
         realloc = true;
     }
@@ -245,10 +422,12 @@ hullf_status enqueue_batched(hullf_ctx* c, const hullf_pt* d_pts, const uint64_t
                              uint64_t n_total, uint32_t* d_surv, uint64_t* d_counts, Shape shape,
                              hipStream_t s, bool seg = false) {
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
+    const uint64_t fcap = c->two_pass ? c->b_items_cap : c->b_status_cap;
     CHECK_HIP(launch_batch(pts, d_off, seg, S, n_total, c->b_sets, c->b_tot, c->b_part,
                            (uint32_t)std::min<uint64_t>(c->b_part_cap, 0xFFFFFFFFull), c->b_octs, c->b_status,
-                           (uint32_t)std::min<uint64_t>(c->b_status_cap, 0xFFFFFFFFull), d_surv, d_counts,
-                           shape, c->cus, s));
+                           c->two_pass ? c->b_bits : nullptr, c->b_blkcnt,
+                           (uint32_t)std::min<uint64_t>(fcap, 0xFFFFFFFFull), d_surv, d_counts, shape, c->cus,
+                           s));
     return HULLF_OK;
 }
 
@@ -295,11 +474,14 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
         Shape sh{0, 0};
         if (std::sscanf(e, "%d,%d", &sh.block, &sh.ppt) == 2 && shape_supported(sh)) c->filter_shape = sh;
     }
+    if (const char* e = std::getenv("HULLF_COMPACTION")) c->two_pass = std::strcmp(e, "single") != 0;
+    if (const char* e = std::getenv("HULLF_FINISH")) c->host_finish = std::strcmp(e, "host") == 0;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc((void**)&c->slots, sizeof(ReduceSlots));
     if (e == hipSuccess) e = hipMalloc((void**)&c->oct, sizeof(Octagon));
     if (e == hipSuccess) e = hipMalloc((void**)&c->part, 9ull * kReduceMaxGrid * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&c->count, sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->blkcnt, kMaxBlocks * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&c->b_tot, sizeof(BatchTotals));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_count, sizeof(uint64_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_oct, sizeof(Octagon), hipHostMallocDefault);
@@ -324,11 +506,15 @@ void hullf_destroy(hullf_ctx_t c) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
-    void* dev[] = {c->slots, c->oct, c->part, c->status, c->count, c->surv, c->gather,
-                   c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_status};
+    void* dev[] = {c->slots, c->oct, c->part, c->status, c->count, c->surv, c->gather, c->bits, c->blkcnt,
+                   c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_status, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
-    void* host[] = {c->h_surv, c->h_xy, c->h_count, c->h_oct};
+    void* fin[] = {c->fk[0], c->fk[1], c->fk[2], c->fv[0], c->fv[1], c->fv[2], c->fchain, c->fcnt, c->fhist,
+                   c->frow};
+    for (void* p : fin)
+        if (p) (void)hipFree(p);
+    void* host[] = {c->h_surv, c->h_xy, c->h_count, c->h_oct, c->h_fk, c->h_fv, c->h_total};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     if (c->capture) (void)hipStreamDestroy(c->capture);
@@ -396,19 +582,26 @@ hullf_status convex_hull(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint3
     const uint64_t m = *c->h_count;
     if (m == kCountNonFinite) return HULLF_ENONFINITE;
     if (m > n) return HULLF_EDEVICE;
-    CHECK_HIP(grow_device(&c->gather, &c->gather_cap, m, s));
-    CHECK_HIP(grow_host(&c->h_surv, &c->h_cap, m));
-    CHECK_HIP(grow_host(&c->h_xy, &c->h_xy_cap, m));
-    const float2* pts = reinterpret_cast<const float2*>(d_pts);
-    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((m + 255) / 256, (uint64_t)c->cus * 8));
-    CHECK_HIP(launch_gather(pts, c->surv, c->count, m, n, c->gather, grid, s));
-    CHECK_HIP(hipMemcpyAsync(c->h_surv, c->surv, m * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    CHECK_HIP(hipMemcpyAsync(c->h_xy, c->gather, m * sizeof(float2), hipMemcpyDeviceToHost, s));
-    CHECK_HIP(hipStreamSynchronize(s));
-    std::vector<HostPt> p(m);
-    for (uint64_t k = 0; k < m; ++k) p[k] = HostPt{c->h_xy[k].x, c->h_xy[k].y, c->h_surv[k]};
     std::vector<uint32_t> out;
-    monotone_chain(p, out);
+    st = hull_of(c, reinterpret_cast<const float2*>(d_pts), n, c->surv, m, out, s);
+    if (st != HULLF_OK) return st;
+    *h_count = out.size();
+    if (out.size() > cap) return HULLF_ECAPACITY;
+    std::copy(out.begin(), out.end(), h_hull);
+    return HULLF_OK;
+}
+
+hullf_status hull_from_survivors(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, const uint32_t* d_surv,
+                                 uint64_t m, uint32_t* h_hull, uint64_t cap, uint64_t* h_count, void* stream) {
+    if (!c || !h_count || n >= (1ull << 32) || m > n) return HULLF_EINVAL;
+    if (m > 0 && (!d_pts || !d_surv || !aligned8(d_pts) || (cap > 0 && !h_hull))) return HULLF_EINVAL;
+    *h_count = 0;
+    if (m == 0) return HULLF_OK;
+    DeviceGuard g(c->device);
+    std::vector<uint32_t> out;
+    const hullf_status st = hull_of(c, reinterpret_cast<const float2*>(d_pts), n, d_surv, m, out,
+                                    (hipStream_t)stream);
+    if (st != HULLF_OK) return st;
     *h_count = out.size();
     if (out.size() > cap) return HULLF_ECAPACITY;
     std::copy(out.begin(), out.end(), h_hull);

@@ -141,6 +141,7 @@ struct hullf_server {
 
     std::thread sched_th, copy_th;
     std::vector<std::thread> finish_th;
+    std::vector<hullf_ctx_t> fctx;   // one context per finisher thread
 
     // -- scheduler ----------------------------------------------------------
     void admit_locked() {
@@ -305,13 +306,11 @@ struct hullf_server {
     }
 
     // -- finishers ----------------------------------------------------------
-    void finish_loop() {
+    void finish_loop(hullf_ctx_t fctx) {
         (void)hipSetDevice(device);
         hipStream_t fs = nullptr;
         hipError_t se = hipStreamCreateWithFlags(&fs, hipStreamNonBlocking);
-        uint32_t* hbuf = nullptr;
-        uint64_t hcap = 0;
-        std::vector<hullf::HostPt> p;
+        std::vector<uint32_t> hbuf(1u << 16);
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
             cv_finish.wait(lk, [&] { return stop_workers || !finish_q.empty(); });
@@ -327,20 +326,18 @@ struct hullf_server {
                 else if (c > r->n) s = HULLF_EDEVICE;
                 else if (se != hipSuccess) s = map_err(se);
             }
-            if (s == HULLF_OK && c > hcap) {
-                if (hbuf) (void)hipHostFree(hbuf);
-                hbuf = nullptr;
-                hcap = 0;
-                const uint64_t want = std::max<uint64_t>(c + c / 4, 1u << 16);
-                const hipError_t e = hipHostMalloc((void**)&hbuf, want * sizeof(uint32_t), hipHostMallocDefault);
-                if (e != hipSuccess) s = map_err(e);
-                else hcap = want;
-            }
             if (s == HULLF_OK && c > 0) {
-                hipError_t e = hipMemcpyAsync(hbuf, d_surv + r->begin, c * sizeof(uint32_t),
-                                              hipMemcpyDeviceToHost, fs);
-                if (e == hipSuccess) e = hipStreamSynchronize(fs);
-                s = map_err(e);
+                // hull of the resident survivors (device sort and chains for
+                // large sets); the arena region is read until this returns
+                uint64_t h = 0;
+                s = hull_from_survivors(fctx, d_pts + r->begin, r->n, d_surv + r->begin, c, hbuf.data(),
+                                        hbuf.size(), &h, fs);
+                if (s == HULLF_ECAPACITY) {
+                    hbuf.resize(h);
+                    s = hull_from_survivors(fctx, d_pts + r->begin, r->n, d_surv + r->begin, c, hbuf.data(),
+                                            hbuf.size(), &h, fs);
+                }
+                if (s == HULLF_OK) r->hull.assign(hbuf.begin(), hbuf.begin() + h);
             }
             lk.lock();
             if (r->span) {
@@ -349,16 +346,6 @@ struct hullf_server {
                 --inflight;
                 cv_sched.notify_one();
             }
-            lk.unlock();
-            if (s == HULLF_OK) {
-                p.resize(c);
-                for (uint64_t k = 0; k < c; ++k) {
-                    const uint32_t i = hbuf[k];
-                    p[k] = hullf::HostPt{r->h[i].x, r->h[i].y, i};
-                }
-                hullf::monotone_chain(p, r->hull, cfg.sort_threads);
-            }
-            lk.lock();
             r->status = s;
             r->count = c;
             r->t_done = Clock::now();
@@ -367,7 +354,6 @@ struct hullf_server {
             cv_done.notify_all();
         }
         lk.unlock();
-        if (hbuf) (void)hipHostFree(hbuf);
         if (fs) (void)hipStreamDestroy(fs);
     }
 
@@ -388,6 +374,7 @@ struct hullf_server {
         for (auto& kv : reqs)
             if (kv.second->loaded) (void)hipEventDestroy(kv.second->loaded);
         if (batch_ev) (void)hipEventDestroy(batch_ev);
+        for (hullf_ctx_t f : fctx) hullf_destroy(f);
         if (compute) (void)hipStreamDestroy(compute);
         if (copy) (void)hipStreamDestroy(copy);
         if (ctx) hullf_destroy(ctx);
@@ -403,7 +390,6 @@ hullf_status hullf_server_create(int device, const hullf_server_config* cfg, hul
     if (c.arena_points == 0) c.arena_points = 1ull << 28;
     if (c.max_inflight == 0) c.max_inflight = 1024;
     if (c.finish_threads == 0) c.finish_threads = 4;
-    if (c.sort_threads == 0) c.sort_threads = 4;
     c.arena_points = (c.arena_points + kGranule - 1) / kGranule * kGranule;
     if (c.arena_points >= (1ull << 32) || c.max_inflight > (1u << 20) || c.finish_threads > 256)
         return HULLF_EINVAL;
@@ -443,6 +429,11 @@ hullf_status hullf_server_create(int device, const hullf_server_config* cfg, hul
     if (r == HULLF_OK) r = hull_filter_segments(s->ctx, s->d_pts, s->d_seg, (uint32_t)M, A, s->d_surv,
                                                 s->d_counts, s->compute);
     if (r == HULLF_OK) r = map_err(hipStreamSynchronize(s->compute));
+    for (uint32_t k = 0; k < c.finish_threads && r == HULLF_OK; ++k) {
+        hullf_ctx_t f = nullptr;
+        r = hullf_create(device, &f);
+        if (r == HULLF_OK) s->fctx.push_back(f);
+    }
     if (r != HULLF_OK) {
         s->release_all();
         delete s;
@@ -452,7 +443,10 @@ hullf_status hullf_server_create(int device, const hullf_server_config* cfg, hul
     s->st.arena_points = A;
     s->sched_th = std::thread([s] { s->sched_loop(); });
     s->copy_th = std::thread([s] { s->copy_loop(); });
-    for (uint32_t k = 0; k < c.finish_threads; ++k) s->finish_th.emplace_back([s] { s->finish_loop(); });
+    for (uint32_t k = 0; k < c.finish_threads; ++k) {
+        hullf_ctx_t f = s->fctx[k];
+        s->finish_th.emplace_back([s, f] { s->finish_loop(f); });
+    }
     *out = s;
     return HULLF_OK;
 }

@@ -45,6 +45,7 @@ def _load():
         "hull_filter": ([P, P, U64, P, U64, P, P], st),
         "convex_hull": ([P, P, U64, P, U64, P, P], st),
         "hullf_flags": ([P, P, U64, P, P], st),
+        "hull_from_survivors": ([P, P, U64, P, U64, P, U64, P, P], st),
         "hull_filter_batched": ([P, P, P, U32, U64, P, P, P], st),
         "hull_filter_segments": ([P, P, P, U32, U64, P, P, P], st),
         "hull_filter_batched_shape": ([P, P, P, U32, U64, P, P, I, I, P], st),
@@ -164,6 +165,20 @@ class Context:
                                    ctypes.byref(h), _stream(stream)), "convex_hull")
         return out[:h.value].copy()
 
+    def hull_from_survivors(self, pts, surv, m=None, stream=None) -> np.ndarray:
+        """Counter-clockwise hull (indices into pts) of the points listed by
+        the ascending int32 device tensor surv (first m entries)."""
+        pts = _points(pts)
+        if m is None:
+            m = surv.numel()
+        cap = max(int(m), 1)
+        out = np.zeros(cap, dtype=np.uint32)
+        h = ctypes.c_uint64(0)
+        _check(_load().hull_from_survivors(self.handle, pts.data_ptr(), pts.shape[0], surv.data_ptr(), int(m),
+                                           out.ctypes.data, cap, ctypes.byref(h), _stream(stream)),
+               "hull_from_survivors")
+        return out[:h.value].copy()
+
     # -- batched -------------------------------------------------------------
     def hull_filter_batched(self, pts, off, n_total=None, surv=None, counts=None, stream=None,
                             block=None, ppt=None):
@@ -229,17 +244,18 @@ class Context:
         _check(_load().hullf_timing_enable(self.handle, 1 if enable else 0), "hullf_timing_enable")
 
     def timing_read(self):
-        """{kind: (launches, total_ms)} for kinds reduce, filter, batched, setup."""
-        launches = (ctypes.c_uint64 * 4)()
-        ms = (ctypes.c_double * 4)()
+        """{kind: (launches, total_ms)} for kinds reduce, filter (inside
+        test), batched, setup, compact."""
+        kinds = ("reduce", "filter", "batched", "setup", "compact")
+        launches = (ctypes.c_uint64 * len(kinds))()
+        ms = (ctypes.c_double * len(kinds))()
         _check(_load().hullf_timing_read(self.handle, launches, ms), "hullf_timing_read")
-        return {k: (launches[i], ms[i]) for i, k in enumerate(("reduce", "filter", "batched", "setup"))}
+        return {k: (launches[i], ms[i]) for i, k in enumerate(kinds)}
 
 
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("arena_points", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
-                ("finish_threads", ctypes.c_uint32), ("sort_threads", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("finish_threads", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
 
 
 class _RequestInfo(ctypes.Structure):
@@ -285,9 +301,9 @@ class Server:
     points until wait() has returned that request's result."""
 
     def __init__(self, device: int = 0, arena_points: int = 0, max_inflight: int = 0,
-                 finish_threads: int = 0, sort_threads: int = 0):
+                 finish_threads: int = 0):
         lib = _load()
-        cfg = _ServerConfig(arena_points, max_inflight, finish_threads, sort_threads, 0)
+        cfg = _ServerConfig(arena_points, max_inflight, finish_threads)
         h = ctypes.c_void_p()
         _check(lib.hullf_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h)),
                "hullf_server_create")
@@ -351,7 +367,7 @@ class Server:
 def exported_symbols():
     """Names of the C-ABI functions the binding expects."""
     return ["hullf_create", "hullf_destroy", "hullf_status_str", "hullf_octagon", "hull_filter",
-            "convex_hull", "hullf_flags", "hull_filter_batched", "hull_filter_segments",
+            "convex_hull", "hullf_flags", "hull_from_survivors", "hull_filter_batched", "hull_filter_segments",
             "hull_filter_batched_shape", "hullf_autotune_batched", "hullf_timing_enable",
             "hullf_timing_read", "hullf_server_create", "hullf_server_destroy", "hullf_server_submit",
             "hullf_server_wait", "hullf_server_stats"]

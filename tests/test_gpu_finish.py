@@ -1,0 +1,117 @@
+"""GPU parity of hull finishing on the device (sort + chunked monotone
+chains, used by convex_hull from 2^18 survivors on): the counter-clockwise
+hull index list must equal the oracle's bit for bit, also with repeated
+coordinates (lowest index kept), collinear and single-point sets, and must
+equal the host finishing path."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_10581_amd import hullf, workloads
+from tests import cases
+from tests.gpu_common import ctx, say, torch_dev, upload  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+DEVICE_MIN = 1 << 18
+
+
+def _hull_check(ctx, dev, xy, name, need_device=True):
+    t = upload(xy, dev)
+    want_s = oracle.survivors(xy)
+    if need_device:
+        assert want_s.size >= DEVICE_MIN, (name, want_s.size)
+    say(f"[gpu] finish {name}: n={xy.shape[0]} survivors={want_s.size}")
+    got = ctx.convex_hull(t)
+    want = oracle.hull(xy, want_s)
+    assert np.array_equal(got, want), (name, got.size, want.size)
+    return got
+
+
+@pytest.mark.parametrize("kind", ["circle", "collinear_h", "collinear_diag", "all_equal"])
+def test_named_sets_device_finish(ctx, torch_dev, kind):
+    xy = cases.named_sets(600_011, 29)[kind]
+    _hull_check(ctx, torch_dev, xy, kind)
+
+
+@pytest.mark.parametrize("kind", ["displaced", "circle_jitter", "displaced_huge", "displaced_tiny", "subnormal",
+                                  "grid", "normal_far"])
+def test_named_sets_any_finish(ctx, torch_dev, kind):
+    xy = cases.named_sets(600_011, 29)[kind]
+    _hull_check(ctx, torch_dev, xy, kind, need_device=False)
+
+
+def test_repeated_points_keep_lowest_index(ctx, torch_dev):
+    base = workloads.circle(200_003, 41)
+    rng = np.random.default_rng(5)
+    xy = np.concatenate([base, base[rng.permutation(base.shape[0])], base[:50_000]], axis=0)
+    _hull_check(ctx, torch_dev, xy, "circle with repeats")
+
+
+def test_signed_zero_and_far_values(ctx, torch_dev):
+    c = workloads.circle(560_017, 43)
+    xy = c.copy()
+    xy[::7, 0] = 0.0
+    xy[1::7, 0] = -0.0
+    xy[2::11, 1] = -0.0
+    _hull_check(ctx, torch_dev, xy * np.float32(3.0e30), "circle scaled 3e30 with zeros")
+
+
+@pytest.mark.parametrize("kind,n,seed", [("circle", 10_000_000, 3), ("displaced", 20_000_000, 4)])
+def test_large_device_finish(ctx, torch_dev, kind, n, seed):
+    xy = workloads.by_kind(kind, n, seed)
+    _hull_check(ctx, torch_dev, xy, f"{kind} {n}")
+
+
+def test_device_finish_equals_host_finish(ctx, torch_dev, monkeypatch):
+    xy = workloads.displaced(3_000_017, 47)
+    t = upload(xy, torch_dev)
+    dev_h = ctx.convex_hull(t)
+    monkeypatch.setenv("HULLF_FINISH", "host")
+    c2 = hullf.Context(0)
+    try:
+        host_h = c2.convex_hull(t)
+    finally:
+        c2.close()
+    assert np.array_equal(dev_h, host_h)
+
+
+def test_hulls_of_batched_survivors(ctx, torch_dev):
+    """The batched filter, then hull_from_survivors per set (set-local
+    indices into that set's points)."""
+    import torch
+    sizes = [5, 1, 0, 3000, 70_001, 300_007, 2]
+    parts = [workloads.request(workloads.KINDS[k % 3], n, 600 + k) if n else np.zeros((0, 2), np.float32)
+             for k, n in enumerate(sizes)]
+    parts[5] = workloads.circle(300_007, 61)   # device finishing
+    off = np.zeros(len(parts) + 1, np.uint64)
+    off[1:] = np.cumsum([p.shape[0] for p in parts])
+    pts = np.concatenate(parts, axis=0)
+    t = upload(pts, torch_dev)
+    o = torch.from_numpy(off.astype(np.int64)).to(torch_dev)
+    say("[gpu] finish: hulls of batched survivors")
+    surv, counts = ctx.hull_filter_batched(t, o)
+    torch.cuda.synchronize()
+    cn = counts.cpu().numpy()
+    for k, xy in enumerate(parts):
+        a, b = int(off[k]), int(off[k + 1])
+        h = ctx.hull_from_survivors(t[a:b], surv[a:], m=int(cn[k]))
+        want = oracle.convex_hull(xy) if b > a else np.zeros(0, np.uint32)
+        assert np.array_equal(h, want), k
+
+
+@pytest.mark.parametrize("m", [1000, 300_000])
+def test_out_of_range_survivor_index(ctx, torch_dev, m):
+    import torch
+    xy = workloads.circle(m, 67)
+    t = upload(xy, torch_dev)
+    s = torch.arange(m, dtype=torch.int32, device=torch_dev)
+    s[m // 2] = m + 5
+    say(f"[gpu] finish: out-of-range index, m={m}")
+    with pytest.raises(hullf.HullfError) as e:
+        ctx.hull_from_survivors(t, s)
+    assert e.value.status == hullf.EINVAL
+    s[m // 2] = m // 2
+    assert np.array_equal(ctx.hull_from_survivors(t, s), oracle.hull(xy))
