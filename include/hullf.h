@@ -168,7 +168,7 @@ hullf_status hull_filter_segments(hullf_ctx_t ctx, const hullf_pt *d_pts,
 
 /* Same work as hull_filter_batched, launched directly (no graph), with an
  * explicit launch shape.  block in {256, 512}, ppt (points per thread per
- * tile) in {8, 16, 32}; 0 picks the tuned or default value. */
+ * tile) in {8, 16}; 0 picks the tuned or default value. */
 hullf_status hull_filter_batched_shape(hullf_ctx_t ctx, const hullf_pt *d_pts,
                                        const uint64_t *d_off, uint32_t S,
                                        uint64_t n_total, uint32_t *d_surv,

@@ -527,7 +527,14 @@ __device__ __forceinline__ bool contract_inside(const Octagon* __restrict__ o, f
 }
 
 // Minimum over the edges of the scaled FP32 edge values (fast == 1).
-__device__ __forceinline__ float edge_min(const Octagon* __restrict__ o, float x, float y) {
+// The octagon record is written by an earlier launch and only read by the
+// kernels that test points: read through the constant address space, its
+// uniform fields become scalar loads (scalar cache, their own wait counter)
+// instead of vector loads whose waits would also drain the point stream.
+typedef const __attribute__((address_space(4))) Octagon OctagonK;
+__device__ __forceinline__ OctagonK* as_const(const Octagon* o) { return (OctagonK*)o; }
+
+__device__ __forceinline__ float edge_min(OctagonK* __restrict__ o, float x, float y) {
     const float qx = x - o->cx, qy = y - o->cy;
     float d[8];
 #pragma unroll
@@ -537,11 +544,12 @@ __device__ __forceinline__ float edge_min(const Octagon* __restrict__ o, float x
 
 // 1 = the point survives.  Decision-equivalent to the binary64 rule.
 __device__ __forceinline__ bool keep_point(const Octagon* __restrict__ o, float x, float y) {
-    if (o->mode == 0) return true;
-    const bool inbox = (o->bxl < x) & (x < o->bxh) & (o->byl < y) & (y < o->byh);
+    OctagonK* ok = as_const(o);
+    if (ok->mode == 0) return true;
+    const bool inbox = (ok->bxl < x) & (x < ok->bxh) & (ok->byl < y) & (y < ok->byh);
     if (inbox) return false;
-    if (o->fast) {
-        const float mn = edge_min(o, x, y);
+    if (ok->fast) {
+        const float mn = edge_min(ok, x, y);
         if (mn < -1.0f) return true;
         if (mn > 2.0f) return false;
     }
@@ -598,10 +606,11 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
                                                  uint64_t sb, const float4 (&q)[PPT / 2], uint32_t validm) {
     constexpr int NP = PPT / 2;
     const uint32_t t = threadIdx.x;
-    if (o->mode == 0) return validm;
+    OctagonK* ok = as_const(o);
+    if (ok->mode == 0) return validm;
     uint32_t keepm = 0, pendm = 0;
-    const float bxl = o->bxl, bxh = o->bxh, byl = o->byl, byh = o->byh;
-    const bool fast = o->fast != 0;
+    const float bxl = ok->bxl, bxh = ok->bxh, byl = ok->byl, byh = ok->byh;
+    const bool fast = ok->fast != 0;
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const bool ok0 = (validm >> (2 * j)) & 1u, ok1 = (validm >> (2 * j + 1)) & 1u;
@@ -613,8 +622,8 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
         if (__ballot(need0 | need1) != 0ull) {
             uint32_t k2 = 0, p2 = 0;
             if (fast) {
-                const float mn0 = edge_min(o, q[j].x, q[j].y);
-                const float mn1 = edge_min(o, q[j].z, q[j].w);
+                const float mn0 = edge_min(ok, q[j].x, q[j].y);
+                const float mn1 = edge_min(ok, q[j].z, q[j].w);
                 k2 = (need0 & (mn0 < -1.0f) ? 1u : 0u) | (need1 & (mn1 < -1.0f) ? 2u : 0u);
                 p2 = (need0 & !(mn0 < -1.0f) & !(mn0 > 2.0f) ? 1u : 0u) |
                      (need1 & !(mn1 < -1.0f) & !(mn1 > 2.0f) ? 2u : 0u);
@@ -1037,6 +1046,49 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, uint32_t l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Survivors of one span: (w0, w1) are this lane's group words (lane = group),
+// written in ascending order to out[base ...] through the wave's LDS stage.
+__device__ __forceinline__ void compact_span(unsigned long long w0, unsigned long long w1, uint64_t sb,
+                                             uint64_t base, uint64_t cap, uint32_t idx_shift,
+                                             uint32_t* __restrict__ out, uint32_t* stage) {
+    const uint32_t lane = lane_id();
+    const uint32_t c = (uint32_t)(__popcll(w0) + __popcll(w1));
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+        if ((int)lane >= o) incl += u;
+    }
+    const uint32_t excl = incl - c;
+    const uint64_t room = cap > base ? cap - base : 0ull;
+    const uint32_t lim = room < (uint64_t)kSpan ? (uint32_t)room : kSpan;
+    const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + base, 4u * lim);
+    unsigned long long live = __ballot(c != 0u);
+    while (live) {
+        const uint32_t g = (uint32_t)__builtin_ctzll(live);
+        live &= live - 1ull;
+        const unsigned long long B0 = readlane_u64(w0, g), B1 = readlane_u64(w1, g);
+        const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)excl, (int)g);
+        const bool k0 = (B0 >> lane) & 1ull, k1 = (B1 >> lane) & 1ull;
+        const uint32_t r = rank_below(B0) + rank_below(B1);
+        const uint32_t cnt = (uint32_t)(__popcll(B0) + __popcll(B1));
+        const uint32_t idx = (uint32_t)(sb + 128ull * g) - idx_shift + 2u * lane;
+        if (k0) stage[r] = idx;
+        if (k1) stage[r + (k0 ? 1u : 0u)] = idx + 1u;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (uint32_t h = 0; h < 2; ++h) {
+            const uint32_t w = lane + 64u * h;
+            const uint32_t pos = P + w;
+            if (w < cnt && pos < lim) __builtin_amdgcn_raw_buffer_store_b32(stage[w], ro, (int)(4u * pos), 0, kAuxNT);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Pass 2 of one set.  Each round the block's waves take consecutive spans
+// (one each); the next round's keep bits are loaded before this round's
+// survivors are stored, so the loads do not wait behind the stores.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_compact(const uint64_t* __restrict__ bits,
                                                    const uint32_t* __restrict__ blkcnt, uint64_t n,
@@ -1045,6 +1097,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const uint64_t* __restrict__ 
     constexpr int NW = BLOCK / 64;
     __shared__ uint32_t sh_stage[NW][128];
     __shared__ uint64_t sh_part[NW];
+    __shared__ uint32_t sh_tot[2][NW];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     if (oct->status != 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *count = (oct->status == 1) ? kCountNonFinite : kCountInternal;
@@ -1064,50 +1117,40 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const uint64_t* __restrict__ 
     const uint64_t r0 = (uint64_t)blockIdx.x * spans * kSpan;
     const uint64_t r1 = min<uint64_t>(n, r0 + (uint64_t)spans * kSpan);
     const uint64_t ngroups = (n + 127) / 128;
-    uint32_t* stage = sh_stage[wave];
-    for (uint64_t sb = r0; sb < r1; sb += kSpan) {
-        const uint64_t g0 = sb >> 7;
-        unsigned long long w0 = 0ull, w1 = 0ull;
-        if (g0 + lane < ngroups) {
-            const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(bits + 2 * (g0 + lane));
+    auto load_words = [&](uint64_t sb, unsigned long long& w0, unsigned long long& w1) {
+        w0 = 0ull;
+        w1 = 0ull;
+        const uint64_t g = (sb >> 7) + lane;
+        if (sb < r1 && g < ngroups) {
+            const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(bits + 2 * g);
             w0 = v.x;
             w1 = v.y;
         }
+    };
+    unsigned long long w0, w1;
+    load_words(r0 + (uint64_t)wave * kSpan, w0, w1);
+    uint32_t par = 0;
+    for (uint64_t rb = r0; rb < r1; rb += (uint64_t)NW * kSpan, par ^= 1u) {
+        const uint64_t sb = rb + (uint64_t)wave * kSpan;
+        unsigned long long n0, n1;
+        load_words(sb + (uint64_t)NW * kSpan, n0, n1);
         const uint32_t c = (uint32_t)(__popcll(w0) + __popcll(w1));
-        uint32_t incl = c;
+        uint32_t tot = c;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
-            if ((int)lane >= o) incl += u;
-        }
-        const uint32_t excl = incl - c;
-        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-        // survivors of this span go to [base, base + tot); lanes store
-        // through a descriptor clipped to the capacity
-        const uint64_t room = cap > base ? cap - base : 0ull;
-        const uint32_t lim = room < (uint64_t)kSpan ? (uint32_t)room : kSpan;
-        const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + base, 4u * lim);
-        for (uint32_t g = wave; g < kSpanGroups; g += NW) {
-            const unsigned long long B0 = readlane_u64(w0, g), B1 = readlane_u64(w1, g);
-            if ((B0 | B1) == 0ull) continue;
-            const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)excl, (int)g);
-            const bool k0 = (B0 >> lane) & 1ull, k1 = (B1 >> lane) & 1ull;
-            const uint32_t r = rank_below(B0) + rank_below(B1);
-            const uint32_t cnt = (uint32_t)(__popcll(B0) + __popcll(B1));
-            const uint32_t idx = (uint32_t)((g0 + g) * 128u) + 2u * lane;
-            if (k0) stage[r] = idx;
-            if (k1) stage[r + (k0 ? 1u : 0u)] = idx + 1u;
-            __builtin_amdgcn_wave_barrier();
+        for (int o = 32; o > 0; o >>= 1) tot += (uint32_t)__shfl_xor((int)tot, o, 64);
+        if (lane == 0) sh_tot[par][wave] = tot;
+        __syncthreads();
+        uint64_t mine = base, all = 0;
 #pragma unroll
-            for (uint32_t h = 0; h < 2; ++h) {
-                const uint32_t w = lane + 64u * h;
-                const uint32_t pos = P + w;
-                if (w < cnt && pos < lim)
-                    __builtin_amdgcn_raw_buffer_store_b32(stage[w], ro, (int)(4u * pos), 0, kAuxNT);
-            }
-            __builtin_amdgcn_wave_barrier();
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t t = sh_tot[par][w];
+            if (w < (int)wave) mine += t;
+            all += t;
         }
-        base += tot;
+        if (sb < r1) compact_span(w0, w1, sb, uniform_u64(mine), cap, 0u, out, sh_stage[wave]);
+        base += all;
+        w0 = n0;
+        w1 = n1;
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *count = base;
 }
@@ -1394,6 +1437,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     }
 }
 
+// Pass 2 of a batch: one work item (kBatchItem = 4 spans) per block and
+// round, one span per wave.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_batch_compact(uint32_t S, const SetInfo* __restrict__ sets,
                                                          const Octagon* __restrict__ octs,
@@ -1402,10 +1447,11 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(uint32_t S, const SetIn
                                                          const uint32_t* __restrict__ blkcnt,
                                                          uint32_t* __restrict__ surv, uint64_t* counts) {
     constexpr int NW = BLOCK / 64;
+    static_assert(NW * kSpan == kBatchItem, "one span per wave");
     __shared__ uint32_t sh_stage[NW][128];
     __shared__ uint64_t sh_part[NW];
+    __shared__ uint32_t sh_tot[NW];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    uint32_t* stage = sh_stage[wave];
     const uint32_t items = tot->f_tiles;
     for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
         const uint32_t s = set_of(sets, S, it, true);
@@ -1415,67 +1461,42 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(uint32_t S, const SetIn
             if (li == 0 && threadIdx.x == 0) counts[s] = (ost == 1) ? kCountNonFinite : kCountInternal;
             continue;
         }
+        const uint64_t b = sets[s].begin, n = sets[s].n;
+        const uint64_t r0 = (b & ~1ull) + (uint64_t)li * kBatchItem;
+        const uint64_t r1 = min<uint64_t>(b + n, r0 + kBatchItem);
+        const uint64_t sb = r0 + (uint64_t)wave * kSpan;
+        // this wave's span words (issued before the offset sums below)
+        unsigned long long w0 = 0ull, w1 = 0ull;
+        if (sb + 128ull * lane < r1) {
+            const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(
+                bits + (uint64_t)it * (kBatchItem / 64) + 2 * ((uint64_t)wave * kSpanGroups + lane));
+            w0 = v.x;
+            w1 = v.y;
+        }
         // offset inside the set: survivors of the set's earlier items
         uint64_t pre = 0;
         for (uint32_t k = threadIdx.x; k < li; k += BLOCK) pre += blkcnt[first + k];
         pre = wave_sum_u64(pre);
-        __syncthreads();
-        if (lane == 0) sh_part[wave] = pre;
-        __syncthreads();
-        uint64_t base = 0;
+        uint32_t t = (uint32_t)(__popcll(w0) + __popcll(w1));
 #pragma unroll
-        for (int w = 0; w < NW; ++w) base += sh_part[w];
-        base = uniform_u64(base);
-
-        const uint64_t b = sets[s].begin, n = sets[s].n;
-        const uint64_t r0 = (b & ~1ull) + (uint64_t)li * kBatchItem;
-        const uint64_t r1 = min<uint64_t>(b + n, r0 + kBatchItem);
-        const uint64_t* ib = bits + (uint64_t)it * (kBatchItem / 64);
-        uint32_t* so = surv + b;
-        for (uint64_t sb = r0; sb < r1; sb += kSpan) {
-            const uint32_t g0 = (uint32_t)((sb - r0) >> 7);
-            unsigned long long w0 = 0ull, w1 = 0ull;
-            if (sb + 128ull * lane < r1) {
-                const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(ib + 2 * (g0 + lane));
-                w0 = v.x;
-                w1 = v.y;
-            }
-            const uint32_t c = (uint32_t)(__popcll(w0) + __popcll(w1));
-            uint32_t incl = c;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
-                if ((int)lane >= o) incl += u;
-            }
-            const uint32_t excl = incl - c;
-            const uint32_t spantot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-            const uint64_t room = n > base ? n - base : 0ull;
-            const uint32_t lim = room < (uint64_t)kSpan ? (uint32_t)room : kSpan;
-            const __amdgpu_buffer_rsrc_t ro = make_rsrc(so + base, 4u * lim);
-            for (uint32_t g = wave; g < kSpanGroups; g += NW) {
-                const unsigned long long B0 = readlane_u64(w0, g), B1 = readlane_u64(w1, g);
-                if ((B0 | B1) == 0ull) continue;
-                const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)excl, (int)g);
-                const bool k0 = (B0 >> lane) & 1ull, k1 = (B1 >> lane) & 1ull;
-                const uint32_t r = rank_below(B0) + rank_below(B1);
-                const uint32_t cnt = (uint32_t)(__popcll(B0) + __popcll(B1));
-                // set-local index of the pair's first point
-                const uint32_t idx = (uint32_t)(sb + 128ull * g - b) + 2u * lane;
-                if (k0) stage[r] = idx;
-                if (k1) stage[r + (k0 ? 1u : 0u)] = idx + 1u;
-                __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                for (uint32_t h = 0; h < 2; ++h) {
-                    const uint32_t w = lane + 64u * h;
-                    const uint32_t pos = P + w;
-                    if (w < cnt && pos < lim)
-                        __builtin_amdgcn_raw_buffer_store_b32(stage[w], ro, (int)(4u * pos), 0, kAuxNT);
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-            base += spantot;
+        for (int o = 32; o > 0; o >>= 1) t += (uint32_t)__shfl_xor((int)t, o, 64);
+        __syncthreads();   // the previous item's reads of sh_part / sh_tot are done
+        if (lane == 0) {
+            sh_part[wave] = pre;
+            sh_tot[wave] = t;
         }
-        if (li == sets[s].f_tiles - 1 && threadIdx.x == 0) counts[s] = base;
+        __syncthreads();
+        uint64_t base = 0, mine = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            base += sh_part[w];
+            if (w < (int)wave) mine += sh_tot[w];
+        }
+        uint64_t all = base;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) all += sh_tot[w];
+        if (sb < r1) compact_span(w0, w1, sb, uniform_u64(base + mine), n, (uint32_t)b, surv + b, sh_stage[wave]);
+        if (li == sets[s].f_tiles - 1 && threadIdx.x == 0) counts[s] = all;
     }
 }
 
@@ -1543,7 +1564,7 @@ uint32_t reduce_chunk_points() { return kRBlock * kRG * 2; }
 uint32_t filter_tile_points(Shape s) { return (uint32_t)(s.block * 64); }   // 64/ppt sub-tiles
 
 bool shape_supported(Shape s) {
-    return (s.block == 256 || s.block == 512) && (s.ppt == 8 || s.ppt == 16 || s.ppt == 32);
+    return (s.block == 256 || s.block == 512) && (s.ppt == 8 || s.ppt == 16);
 }
 
 hipError_t launch_init_slots(ReduceSlots* slots, uint32_t count, hipStream_t stream) {
@@ -1569,7 +1590,7 @@ hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsig
     return hipGetLastError();
 }
 
-#define HULLF_SHAPES(X) X(256, 8) X(256, 16) X(256, 32) X(512, 8) X(512, 16) X(512, 32)
+#define HULLF_SHAPES(X) X(256, 8) X(256, 16) X(512, 8) X(512, 16)
 
 hipError_t launch_filter(const float2* pts, uint64_t n, const Octagon* oct, ReduceSlots* slots,
                          uint64_t* tile_status, uint32_t num_tiles, uint32_t* surv, uint64_t cap,
@@ -1590,7 +1611,7 @@ bool classify_shape_supported(Shape s) {
     return shape_supported(s) && kSpan % (uint32_t)(s.block * s.ppt) == 0u;
 }
 
-#define HULLF_CLASSIFY_SHAPES(X) X(256, 8) X(256, 16) X(256, 32) X(512, 8) X(512, 16)
+#define HULLF_CLASSIFY_SHAPES(X) X(256, 8) X(256, 16) X(512, 8) X(512, 16)
 
 hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
                            uint32_t* blkcnt, Shape shape, int grid, hipStream_t stream) {
@@ -1693,10 +1714,8 @@ hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32
         bool done = false;
         HULLF_BATCH_CLASSIFY(256, 8)
         HULLF_BATCH_CLASSIFY(256, 16)
-        HULLF_BATCH_CLASSIFY(256, 32)
         HULLF_BATCH_CLASSIFY(512, 8)
         HULLF_BATCH_CLASSIFY(512, 16)
-        HULLF_BATCH_CLASSIFY(512, 32)
         if (!done) return hipErrorInvalidValue;
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_batch_compact<256>, dim3(cus * 8), dim3(256), 0, stream, S, sets, octs, tot, bits,

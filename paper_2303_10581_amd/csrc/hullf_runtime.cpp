@@ -693,7 +693,7 @@ hullf_status hullf_autotune_batched(hullf_ctx_t c, const hullf_pt* d_pts, const 
     if (S == 0 || reps < 1) return HULLF_EINVAL;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    const Shape shapes[] = {{256, 8}, {256, 16}, {256, 32}, {512, 8}, {512, 16}, {512, 32}};
+    const Shape shapes[] = {{256, 8}, {256, 16}, {512, 8}, {512, 16}};
     hipEvent_t a = nullptr, b = nullptr;
     CHECK_HIP(hipEventCreate(&a));
     if (hipEventCreate(&b) != hipSuccess) {
