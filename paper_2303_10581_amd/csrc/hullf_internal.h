@@ -104,8 +104,9 @@ uint32_t compact_span_points();
 bool classify_shape_supported(Shape shape);
 hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
                            uint32_t* blkcnt, Shape shape, int grid, hipStream_t stream);
+// block: 256, 512 or 1024 threads (one span per wave and round).
 hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
-                          const Octagon* oct, uint32_t* out, uint64_t cap, uint64_t* count, int grid,
+                          const Octagon* oct, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,
                           hipStream_t stream);
 
 // Batched: plan, reduction, octagon set-up and compaction (four launches).

@@ -77,6 +77,8 @@ struct hullf_ctx {
     Shape filter_shape{512, 16};
     bool two_pass = true;                  // classify + compact (else single-pass look-back)
     bool host_finish = false;              // hull finishing always on the host
+    int classify_per_cu = 0;               // classify blocks per CU (0: what occupancy allows)
+    int compact_block = 512;               // threads per compaction block
     uint64_t* bits = nullptr;              // keep bits, 2 words per 128 points
     uint64_t bits_cap = 0;
     uint32_t* blkcnt = nullptr;            // kMaxBlocks survivor counts
@@ -236,7 +238,8 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
     if (!classify_shape_supported(sh)) sh = Shape{512, 16};
     const uint64_t span = compact_span_points();
     const uint64_t nspans = (n + span - 1) / span;
-    const uint64_t target = std::min<uint64_t>((uint64_t)c->cus * (sh.block >= 512 ? 3 : 6), kMaxBlocks);
+    const int per_cu = c->classify_per_cu > 0 ? c->classify_per_cu : (sh.block >= 512 ? 3 : 6);
+    const uint64_t target = std::min<uint64_t>((uint64_t)c->cus * per_cu, kMaxBlocks);
     const uint64_t spans = (nspans + target - 1) / target;
     const int grid = (int)((nspans + spans - 1) / spans);
     CHECK_HIP(grow_device(&c->bits, &c->bits_cap, 2 * ((n + 127) / 128), s));
@@ -246,7 +249,8 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
         return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, sh, grid, s);
     }));
     CHECK_HIP(timed(c, 4, s, [&] {
-        return launch_compact(c->bits, c->blkcnt, n, (uint32_t)spans, c->oct, d_surv, cap, d_count, grid, s);
+        return launch_compact(c->bits, c->blkcnt, n, (uint32_t)spans, c->oct, d_surv, cap, d_count,
+                              c->compact_block, grid, s);
     }));
     return HULLF_OK;
 }
@@ -476,6 +480,11 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
     }
     if (const char* e = std::getenv("HULLF_COMPACTION")) c->two_pass = std::strcmp(e, "single") != 0;
     if (const char* e = std::getenv("HULLF_FINISH")) c->host_finish = std::strcmp(e, "host") == 0;
+    if (const char* e = std::getenv("HULLF_CLASSIFY_PER_CU")) c->classify_per_cu = std::max(0, std::atoi(e));
+    if (const char* e = std::getenv("HULLF_COMPACT_BLOCK")) {
+        const int b = std::atoi(e);
+        if (b == 256 || b == 512 || b == 1024) c->compact_block = b;
+    }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc((void**)&c->slots, sizeof(ReduceSlots));
     if (e == hipSuccess) e = hipMalloc((void**)&c->oct, sizeof(Octagon));
