@@ -31,27 +31,17 @@ struct alignas(16) Octagon {
     double ax[8], ay[8], ex[8], ey[8];
 };
 
-// Device state of one single-set call: the compaction tile ticket (reset by
-// the reduction launch).  The remaining fields are kept zero.
-struct alignas(16) ReduceSlots {
-    unsigned long long key[8];
-    uint32_t nonfinite;
-    uint32_t done;
-    uint32_t ticket;
-    uint32_t ready;
-};
-
 // Per-set bookkeeping of the batched launch (written by the plan kernel).
 struct alignas(16) SetInfo {
     uint64_t begin;        // first point of the set
     uint64_t n;            // points in the set
     uint32_t r_tiles;      // reduction tiles
-    uint32_t f_tiles;      // inside-test/compaction tiles
+    uint32_t f_tiles;      // classify/compact work items
     uint32_t r_tile0;      // reduction tiles of all earlier sets (partial record offset)
-    uint32_t f_tile0;      // compaction tiles of all earlier sets (status array offset)
+    uint32_t f_tile0;      // work items of all earlier sets
 };
 
-// Batch-wide totals and the compaction ticket (device).
+// Batch-wide totals (device).
 struct alignas(16) BatchTotals {
     uint32_t r_tiles;
     uint32_t f_tiles;
@@ -59,9 +49,6 @@ struct alignas(16) BatchTotals {
     uint32_t pad;
 };
 
-constexpr uint64_t kFlagA = 1ull << 62;
-constexpr uint64_t kFlagP = 2ull << 62;
-constexpr uint64_t kValMask = (1ull << 62) - 1;
 constexpr uint64_t kCountNonFinite = ~0ull;
 constexpr uint64_t kCountBadOffsets = ~0ull - 1;
 constexpr uint64_t kCountInternal = ~0ull - 2;
@@ -73,25 +60,19 @@ struct Shape {
 
 
 // Launchers (all asynchronous on `stream`; return the launch error).
-hipError_t launch_init_slots(ReduceSlots* slots, uint32_t count, hipStream_t stream);
 // Extremes of one set in two launches: launch_reduce writes 9 * grid
-// uint64 partial records to `part` (and clears the compaction state);
-// launch_setup merges them and writes the octagon.
-hipError_t launch_reduce(const float2* pts, uint64_t n, ReduceSlots* slots, unsigned long long* part,
-                         uint64_t* tile_status, uint32_t num_tiles, int grid, hipStream_t stream);
+// uint64 partial records to `part`; launch_setup merges them and writes the
+// octagon.
+hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, int grid, hipStream_t stream);
 hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsigned long long* part,
                         uint32_t nblocks, hipStream_t stream);
 constexpr int kReduceMaxGrid = 4096;
-hipError_t launch_filter(const float2* pts, uint64_t n, const Octagon* oct, ReduceSlots* slots,
-                         uint64_t* tile_status, uint32_t num_tiles, uint32_t* surv, uint64_t cap,
-                         uint64_t* count, Shape shape, int grid, hipStream_t stream);
 hipError_t launch_flags(const float2* pts, uint64_t n, const Octagon* oct, uint8_t* flags,
                         int grid, hipStream_t stream);
 hipError_t launch_write_count(uint64_t* count, uint64_t value, hipStream_t stream);
 hipError_t launch_gather(const float2* pts, const uint32_t* surv, const uint64_t* count,
                          uint64_t cap, uint64_t n, float2* out, int grid, hipStream_t stream);
 
-uint32_t filter_tile_points(Shape shape);
 uint32_t reduce_chunk_points();
 bool shape_supported(Shape shape);
 
@@ -109,19 +90,15 @@ hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t
                           const Octagon* oct, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,
                           hipStream_t stream);
 
-// Batched: plan, reduction, octagon set-up and compaction (four launches).
-// part: 9 * max_rtiles uint64 scratch.  off: S+1 CSR offsets, or (seg) S
-// (begin, count) pairs, ascending and disjoint.
-// Two-pass compaction when bits != nullptr: bits holds max_ftiles *
-// batch_item_words() words and blkcnt max_ftiles counts (max_ftiles >=
-// batch_max_items).  Otherwise single pass with look-back: tile_status
-// holds max_ftiles words (>= batch_max_tiles).
+// Batched: plan, reduction, octagon set-up, classify and compact (five
+// launches).  part: 9 * max_rtiles uint64 scratch.  off: S+1 CSR offsets,
+// or (seg) S (begin, count) pairs, ascending and disjoint.  bits holds
+// max_items * batch_item_words() words and blkcnt max_items counts
+// (max_items >= batch_max_items).
 hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
                         SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
-                        Octagon* octs, uint64_t* tile_status, uint64_t* bits, uint32_t* blkcnt,
-                        uint32_t max_ftiles, uint32_t* surv, uint64_t* counts, Shape shape, int cus,
-                        hipStream_t stream);
-uint64_t batch_max_tiles(uint64_t n_total, uint32_t S, Shape shape);
+                        Octagon* octs, uint64_t* bits, uint32_t* blkcnt, uint32_t max_items, uint32_t* surv,
+                        uint64_t* counts, Shape shape, int cus, hipStream_t stream);
 uint64_t batch_max_items(uint64_t n_total, uint32_t S);
 uint32_t batch_item_words();
 uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S);

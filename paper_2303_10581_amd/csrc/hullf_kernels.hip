@@ -1,10 +1,11 @@
 // HIP kernels (gfx950, wave64) for the octagon filter of Carrasco et al.,
 // "An Evaluation of GPU Filters for Accelerating the 2D Convex Hull":
-//   k_reduce   Sec. 3.1, the eight extremes by a min/max reduction
-//   k_filter   Sec. 3.2 + Sec. 4.1.1, inside test fused with a single-pass
-//              stream compaction (ballot/popcount inside a wave, LDS scan
-//              across waves, decoupled look-back across tiles)
-//   k_batch    both steps for many sets in one persistent launch
+//   k_reduce    Sec. 3.1, the eight extremes by a min/max reduction
+//   k_setup     the octagon record (edges, FP32 prefilter, quick-accept box)
+//   k_classify  Sec. 3.2, the inside test, keep bits in point order
+//   k_compact   Sec. 4.1.1, stream compaction of the keep bits (ballot,
+//               popcount and wave scans; block offsets from block counts)
+//   k_batch_*   the same steps for many sets in one graph of launches
 //
 // Data layout: points are float2 (x, y), 8 bytes, AoS.  A block reads a
 // chunk/tile of consecutive points as float4 pairs: pair slot j of thread t
@@ -27,7 +28,6 @@ namespace {
 // Shewchuk (1997) for a 2x2 determinant of differences.
 constexpr double kBoundC = 0x1.8000000000004p-52;
 constexpr float kInfF = __builtin_huge_valf();
-constexpr int kLB = 8;   // look-back groups of 64 predecessors per round
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -82,13 +82,6 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
         v += ((uint64_t)hi << 32) | lo;
     }
     return v;
-}
-
-__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -499,12 +492,6 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
     return 0;
 }
 
-__device__ __forceinline__ void reset_slots(ReduceSlots* s) {
-    for (int j = 0; j < 8; ++j) s->key[j] = 0ull;
-    s->nonfinite = 0u;
-    s->done = 0u;
-}
-
 // ---------------------------------------------------------------------------
 // Sec. 3.2: inside test
 // ---------------------------------------------------------------------------
@@ -559,17 +546,11 @@ __device__ __forceinline__ bool keep_point(const Octagon* __restrict__ o, float 
 }
 
 // ---------------------------------------------------------------------------
-// Sec. 4.1.1: compaction with decoupled look-back, in phases
+// Sub-tiles: loading and testing
 // ---------------------------------------------------------------------------
-// Geometry: a tile is SUB sub-tiles of ST = BLOCK*PPT points; pair slot j of
-// thread t in a sub-tile with base sb covers points sb + 2*(j*BLOCK + t) +
-// {0, 1}.  Survivor order inside a tile is (sub-tile, j, wave, lane, point),
-// which is ascending point order.  A tile's survivor count is the sum of
-// NS = SUB*NP*NW wave-segment counts kept in LDS.
-//
-// Tile status words (one per tile of a set): flag in bits 62-63 (0 not
-// ready, 1 aggregate, 2 inclusive prefix), count in the low bits; flag and
-// value share one 64-bit word, so relaxed agent-scope atomics suffice.
+// A sub-tile is ST = BLOCK*PPT points; pair slot j of thread t in a sub-tile
+// with base sb covers points sb + 2*(j*BLOCK + t) + {0, 1}.  Masks hold bit
+// 2j+h for point h of pair slot j.
 
 // Load one sub-tile; returns the validity mask (bit 2j+h).
 template <int BLOCK, int PPT, bool VEC4>
@@ -655,196 +636,12 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
     return keepm;
 }
 
-// Wave-segment survivor counts of one sub-tile into cnt[j*NW + wave].
-template <int BLOCK, int PPT>
-__device__ __forceinline__ void count_sub(uint32_t keepm, uint32_t* cnt) {
-    constexpr int NP = PPT / 2;
-    constexpr int NW = BLOCK / 64;
-    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const unsigned long long b0 = __ballot((keepm >> (2 * j)) & 1u);
-        const unsigned long long b1 = __ballot((keepm >> (2 * j + 1)) & 1u);
-        if (lane == 0) cnt[j * NW + wave] = (uint32_t)(__popcll(b0) + __popcll(b1));
-    }
-}
-
-// Wave 0: exclusive scan of the NS segment counts in place, then the
-// tile's decoupled look-back.  Writes the tile's exclusive prefix to *excl_out
-// and, for the last tile, the set's total to *count.
-template <int NS>
-__device__ __forceinline__ void scan_lookback(uint32_t* cnt, uint32_t tile, uint64_t* status,
-                                              uint64_t* excl_out, uint64_t* count) {
-    static_assert(NS <= 512, "at most 8 segments per lane");
-    constexpr int PER = (NS + 63) / 64;
-    const uint32_t lane = lane_id();
-    uint32_t v[PER];
-    uint32_t local = 0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const uint32_t e = lane * PER + i;
-        v[i] = (e < NS) ? cnt[e] : 0u;
-        local += v[i];
-    }
-    uint32_t incl = local;
-#pragma unroll
-    for (int o2 = 1; o2 < 64; o2 <<= 1) {
-        const uint32_t u = (uint32_t)__shfl_up((int)incl, o2, 64);
-        if ((int)lane >= o2) incl += u;
-    }
-    const uint64_t agg = (uint32_t)__shfl((int)incl, 63, 64);
-    uint32_t run = incl - local;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const uint32_t e = lane * PER + i;
-        if (e < NS) cnt[e] = run;
-        run += v[i];
-    }
-
-    uint64_t excl = 0;
-    if (tile == 0) {
-        if (lane == 0) status_store(&status[0], kFlagP | agg);
-    } else {
-        if (lane == 0) status_store(&status[tile], kFlagA | agg);
-        // Rounds read `chunks` groups of 64 consecutive predecessors
-        // (group k holds tiles look-64k-lane): one group first, all kLB
-        // groups once no inclusive prefix is within reach.
-        int64_t look = (int64_t)tile - 1;
-        int chunks = 1;
-        for (;;) {
-            uint64_t w[kLB];
-#pragma unroll
-            for (int k = 0; k < kLB; ++k) {
-                w[k] = kFlagP;
-                if (k < chunks) {
-                    const int64_t top = look - 64 * k;   // uniform
-                    const uint32_t lim = top < 0 ? 0u : (top >= 63 ? 64u : (uint32_t)top + 1u);
-                    if (lane < lim) {
-                        const uint64_t* b = status + (top - 63);
-                        w[k] = status_load(reinterpret_cast<const uint64_t*>(
-                            reinterpret_cast<const char*>(b) + 8u * (63u - lane)));
-                    }
-                }
-            }
-            int k = 0;
-            bool found = false, stalled = false;
-            uint64_t sum = 0;
-#pragma unroll
-            for (; k < kLB; ++k) {
-                if (k >= chunks) break;
-                const uint32_t flag = (uint32_t)(w[k] >> 62);
-                const unsigned long long pm = __ballot(flag == 2u);
-                const unsigned long long xm = __ballot(flag == 0u);
-                const int first_p = pm ? (__ffsll((long long)pm) - 1) : 64;
-                const unsigned long long need = (first_p >= 63) ? ~0ull : ((2ull << first_p) - 1ull);
-                if (xm & need) {
-                    stalled = true;
-                    break;
-                }
-                sum += wave_sum_u64(((int)lane <= first_p) ? (w[k] & kValMask) : 0ull);
-                if (first_p < 64) {
-                    found = true;
-                    break;
-                }
-            }
-            excl += sum;
-            if (found) break;
-            look -= 64 * k;   // groups before k held aggregates only
-            if (stalled) __builtin_amdgcn_s_sleep(1);
-            else chunks = kLB;
-        }
-        if (lane == 0) status_store(&status[tile], kFlagP | (excl + agg));
-    }
-    if (lane == 0) {
-        *excl_out = excl;
-        if (count) *count = excl + agg;
-    }
-}
-
-// Write the survivors of one sub-tile: positions excl + off[j*NW + wave] +
-// rank (off is relative to the tile's first survivor, so it can reach the
-// tile size `span`), values = point index relative to lo; entries at or
-// beyond cap are dropped.  vbase = (sub-tile base - lo) mod 2^32.
-// Each wave first compacts a pair slot's survivors into its own 128-word LDS
-// area `stage`, then stores them as rows of 64 consecutive words, so every
-// store instruction writes one contiguous 256-byte run.
-template <int BLOCK, int PPT>
-__device__ __forceinline__ void write_sub(uint32_t keepm, const uint32_t* off, uint64_t excl,
-                                          uint32_t vbase, uint32_t* __restrict__ out, uint64_t cap,
-                                          uint32_t span, uint32_t* stage) {
-    constexpr int NP = PPT / 2;
-    constexpr int NW = BLOCK / 64;
-    if (__ballot(keepm != 0u) == 0ull) return;
-    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-    const uint64_t room = (cap > excl) ? cap - excl : 0ull;
-    const uint32_t capr = room > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)room;
-    const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + excl, 4u * (capr < span ? capr : span));
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const unsigned long long b0 = __ballot((keepm >> (2 * j)) & 1u);
-        const unsigned long long b1 = __ballot((keepm >> (2 * j + 1)) & 1u);
-        if ((b0 | b1) == 0ull) continue;
-        const bool k0 = (keepm >> (2 * j)) & 1u, k1 = (keepm >> (2 * j + 1)) & 1u;
-        const uint32_t idx = vbase + 2u * (j * BLOCK + t);
-        const uint32_t r = rank_below(b0) + rank_below(b1);
-        const uint32_t cnt = (uint32_t)(__popcll(b0) + __popcll(b1));
-        if (k0) stage[r] = idx;
-        if (k1) stage[r + (k0 ? 1u : 0u)] = idx + 1u;
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t base = off[j * NW + wave];
-#pragma unroll
-        for (uint32_t h = 0; h < 2; ++h) {
-            const uint32_t w = lane + 64u * h;
-            if (w < cnt) {
-                const uint32_t pos = base + w;
-                const uint32_t val = stage[w];
-                if (pos < capr) __builtin_amdgcn_raw_buffer_store_b32(val, ro, (int)(4u * pos), 0, kAuxStore);
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-}
-
-// One whole tile (SUB = 1), not pipelined: used by the batched kernel.
-template <int BLOCK, int PPT, bool VEC4>
-__device__ __forceinline__ void filter_tile(const float2* __restrict__ pts, uint64_t lo, uint64_t hi, uint64_t al,
-                                            uint32_t tile, const Octagon* __restrict__ o, uint64_t* status,
-                                            uint32_t* __restrict__ out, uint64_t cap, uint64_t* count) {
-    constexpr int NP = PPT / 2;
-    constexpr int NW = BLOCK / 64;
-    constexpr int NS = NP * NW;
-    constexpr uint32_t T = BLOCK * PPT;
-    __shared__ uint32_t sh_cnt[NS];
-    __shared__ uint64_t sh_excl;
-    __shared__ uint32_t sh_stage[NW][128];
-    const uint64_t tb = al + (uint64_t)tile * T;
-    float4 q[NP];
-    const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, tb, q);
-    const uint32_t keepm = classify_sub<BLOCK, PPT>(o, pts, tb, q, validm);
-    count_sub<BLOCK, PPT>(keepm, sh_cnt);
-    __syncthreads();
-    if ((threadIdx.x >> 6) == 0) scan_lookback<NS>(sh_cnt, tile, status, &sh_excl, count);
-    __syncthreads();
-    const uint64_t excl = uniform_u64(sh_excl);
-    write_sub<BLOCK, PPT>(keepm, sh_cnt, excl, (uint32_t)(tb - lo), out, cap, T, sh_stage[threadIdx.x >> 6]);
-    __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // kernels: one point set
 // ---------------------------------------------------------------------------
 
 constexpr int kRBlock = 256;
 constexpr int kRG = 4;   // pairs per thread per chunk: 8 points
-
-__global__ void k_init_slots(ReduceSlots* s, uint32_t count) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) {
-        reset_slots(&s[i]);
-        s[i].ticket = 0u;
-        s[i].ready = 0u;
-    }
-}
 
 // One point set, pass 1.  Every block writes its packed candidates to its
 // own partial record with plain stores.  There is deliberately no
@@ -854,14 +651,7 @@ __global__ void k_init_slots(ReduceSlots* s, uint32_t count) {
 // the records; the kernel boundary makes them visible.
 template <bool VEC4>
 __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_reduce(
-    const float2* __restrict__ pts, uint64_t n, ReduceSlots* slots,
-    unsigned long long* __restrict__ part, uint64_t* tile_status, uint32_t num_tiles) {
-    // clear the look-back state of the compaction kernel that follows
-    for (uint64_t i = (uint64_t)blockIdx.x * kRBlock + threadIdx.x; i < num_tiles;
-         i += (uint64_t)gridDim.x * kRBlock)
-        tile_status[i] = 0ull;
-    if (blockIdx.x == 0 && threadIdx.x == 0) slots->ticket = 0u;
-
+    const float2* __restrict__ pts, uint64_t n, unsigned long long* __restrict__ part) {
     constexpr uint32_t CH = kRBlock * kRG * 2;
     const uint32_t nch = (uint32_t)((n + CH - 1) / CH);
     __shared__ unsigned long long rec[9];
@@ -908,67 +698,6 @@ __global__ __launch_bounds__(256) void k_setup(const float2* __restrict__ pts, u
             nf |= sh_m[8][w];
         }
         (void)setup_octagon(pts, 0, n, key, (uint32_t)nf, oct);
-    }
-}
-
-// One point set, inside test + compaction.  Persistent blocks take tiles
-// (SUB sub-tiles each) from an atomic ticket; the next tile's ticket is
-// taken and its first sub-tile's loads issued before this tile's look-back,
-// so the look-back wait overlaps memory traffic.
-template <int BLOCK, int PPT, bool VEC4>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_filter(
-    const float2* __restrict__ pts, uint64_t n, const Octagon* __restrict__ oct, ReduceSlots* slots,
-    uint64_t* tile_status, uint32_t num_tiles, uint32_t* __restrict__ surv, uint64_t cap, uint64_t* count) {
-    constexpr int NP = PPT / 2;
-    constexpr int NW = BLOCK / 64;
-    constexpr int SUB = 64 / PPT;   // the keep bits of a whole tile fit one 64-bit mask
-    constexpr int NSS = NP * NW;    // segments per sub-tile
-    constexpr uint32_t ST = BLOCK * PPT;
-    constexpr uint32_t T = ST * SUB;
-    if (oct->status != 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            *count = (oct->status == 1) ? kCountNonFinite : kCountInternal;
-        return;
-    }
-    __shared__ uint32_t sh_cnt[SUB * NSS];
-    __shared__ uint64_t sh_excl;
-    __shared__ uint32_t sh_tk;
-    __shared__ uint32_t sh_stage[NW][128];
-    const uint32_t wave = threadIdx.x >> 6;
-
-    if (threadIdx.x == 0) sh_tk = atomicAdd(&slots->ticket, 1u);
-    __syncthreads();
-    uint32_t tile = __builtin_amdgcn_readfirstlane(sh_tk);
-    float4 q[NP];
-    uint32_t validm = 0;
-    if (tile < num_tiles) validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, (uint64_t)tile * T, q);
-    while (tile < num_tiles) {
-        const uint64_t tb = (uint64_t)tile * T;
-        uint64_t keep = 0;   // PPT bits per sub-tile
-#pragma unroll 1
-        for (int sidx = 0; sidx < SUB; ++sidx) {
-            const uint64_t sb = tb + (uint64_t)sidx * ST;
-            if (sidx > 0) validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q);
-            const uint32_t k = classify_sub<BLOCK, PPT>(oct, pts, sb, q, validm);
-            count_sub<BLOCK, PPT>(k, &sh_cnt[sidx * NSS]);
-            keep |= (uint64_t)k << (sidx * PPT);
-        }
-        if (threadIdx.x == 0) sh_tk = atomicAdd(&slots->ticket, 1u);
-        __syncthreads();
-        const uint32_t next = __builtin_amdgcn_readfirstlane(sh_tk);
-        if (next < num_tiles) validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, (uint64_t)next * T, q);
-        if (wave == 0)
-            scan_lookback<SUB * NSS>(sh_cnt, tile, tile_status, &sh_excl, tile == num_tiles - 1 ? count : nullptr);
-        __syncthreads();
-        const uint64_t excl = uniform_u64(sh_excl);
-#pragma unroll 1
-        for (int sidx = 0; sidx < SUB; ++sidx) {
-            const uint32_t k = (uint32_t)(keep >> (sidx * PPT)) & (PPT >= 32 ? 0xFFFFFFFFu : ((1u << PPT) - 1u));
-            write_sub<BLOCK, PPT>(k, &sh_cnt[sidx * NSS], excl, (uint32_t)(tb + (uint64_t)sidx * ST), surv, cap, T,
-                                  sh_stage[wave]);
-        }
-        __syncthreads();
-        tile = next;
     }
 }
 
@@ -1252,8 +981,8 @@ __device__ __forceinline__ void set_span(const uint64_t* __restrict__ a, uint32_
 template <bool SEG>
 __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict__ off, uint32_t S,
                                                      SetInfo* sets, BatchTotals* tot, uint64_t* counts,
-                                                     uint64_t* tile_status, uint32_t max_ftiles,
-                                                     uint32_t max_rtiles, uint64_t n_total, uint32_t ft) {
+                                                     uint32_t max_ftiles, uint32_t max_rtiles, uint64_t n_total,
+                                                     uint32_t ft) {
     __shared__ uint32_t sh_scan[1024];
     __shared__ uint32_t sh_carry[2];
     const uint32_t t = threadIdx.x;
@@ -1314,8 +1043,6 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
     }
     const uint32_t rtiles = sh_carry[0], ftiles = sh_carry[1];
     const bool fits = ftiles <= max_ftiles && rtiles <= max_rtiles;
-    if (tile_status)
-        for (uint32_t i = t; i < ftiles && i < max_ftiles; i += 1024) tile_status[i] = 0ull;
     if (t == 0) {
         tot->r_tiles = fits ? rtiles : 0u;
         tot->f_tiles = fits ? ftiles : 0u;
@@ -1506,57 +1233,6 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(uint32_t S, const SetIn
     }
 }
 
-template <int BLOCK, int PPT, bool VEC4>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_batch_filter(
-    const float2* __restrict__ pts, uint32_t S, const SetInfo* __restrict__ sets,
-    const Octagon* __restrict__ octs, BatchTotals* tot, uint64_t* tile_status, uint32_t* __restrict__ surv,
-    uint64_t* counts) {
-    __shared__ uint32_t sh_tk;
-    const uint32_t ftiles = tot->f_tiles;
-    for (;;) {
-        if (threadIdx.x == 0) sh_tk = atomicAdd(&tot->ticket, 1u);
-        __syncthreads();
-        const uint32_t tk = __builtin_amdgcn_readfirstlane(sh_tk);
-        if (tk >= ftiles) break;
-        const uint32_t s = set_of(sets, S, tk, true);
-        const uint32_t local = tk - sets[s].f_tile0;
-        const uint64_t b = sets[s].begin, n = sets[s].n;
-        const Octagon* o = &octs[s];
-        if (o->status == 0) {
-            filter_tile<BLOCK, PPT, VEC4>(pts, b, b + n, b & ~1ull, local, o, tile_status + sets[s].f_tile0,
-                                          surv + b, n, local == sets[s].f_tiles - 1 ? &counts[s] : nullptr);
-        } else {
-            __syncthreads();
-        }
-    }
-}
-
-template <int BLOCK, int PPT>
-hipError_t launch_filter_t(const float2* pts, uint64_t n, const Octagon* oct, ReduceSlots* slots,
-                           uint64_t* tile_status, uint32_t num_tiles, uint32_t* surv, uint64_t cap,
-                           uint64_t* count, bool vec4, int grid, hipStream_t stream) {
-    if (vec4)
-        hipLaunchKernelGGL((k_filter<BLOCK, PPT, true>), dim3(grid), dim3(BLOCK), 0, stream, pts, n,
-                           oct, slots, tile_status, num_tiles, surv, cap, count);
-    else
-        hipLaunchKernelGGL((k_filter<BLOCK, PPT, false>), dim3(grid), dim3(BLOCK), 0, stream, pts, n,
-                           oct, slots, tile_status, num_tiles, surv, cap, count);
-    return hipGetLastError();
-}
-
-template <int BLOCK, int PPT>
-hipError_t launch_batch_filter_t(const float2* pts, uint32_t S, const SetInfo* sets, const Octagon* octs,
-                                 BatchTotals* tot, uint64_t* tile_status, uint32_t* surv, uint64_t* counts,
-                                 bool vec4, int grid, hipStream_t stream) {
-    if (vec4)
-        hipLaunchKernelGGL((k_batch_filter<BLOCK, PPT, true>), dim3(grid), dim3(BLOCK), 0, stream, pts, S,
-                           sets, octs, tot, tile_status, surv, counts);
-    else
-        hipLaunchKernelGGL((k_batch_filter<BLOCK, PPT, false>), dim3(grid), dim3(BLOCK), 0, stream, pts, S,
-                           sets, octs, tot, tile_status, surv, counts);
-    return hipGetLastError();
-}
-
 bool is_vec4(const float2* p) { return ((uintptr_t)p & 15u) == 0u; }
 
 }  // namespace
@@ -1567,26 +1243,15 @@ bool is_vec4(const float2* p) { return ((uintptr_t)p & 15u) == 0u; }
 
 uint32_t reduce_chunk_points() { return kRBlock * kRG * 2; }
 
-uint32_t filter_tile_points(Shape s) { return (uint32_t)(s.block * 64); }   // 64/ppt sub-tiles
-
 bool shape_supported(Shape s) {
     return (s.block == 256 || s.block == 512) && (s.ppt == 8 || s.ppt == 16);
 }
 
-hipError_t launch_init_slots(ReduceSlots* slots, uint32_t count, hipStream_t stream) {
-    if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_init_slots, dim3((count + 255) / 256), dim3(256), 0, stream, slots, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce(const float2* pts, uint64_t n, ReduceSlots* slots, unsigned long long* part,
-                         uint64_t* tile_status, uint32_t num_tiles, int grid, hipStream_t stream) {
+hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, int grid, hipStream_t stream) {
     if (is_vec4(pts))
-        hipLaunchKernelGGL(k_reduce<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, slots, part,
-                           tile_status, num_tiles);
+        hipLaunchKernelGGL(k_reduce<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part);
     else
-        hipLaunchKernelGGL(k_reduce<false>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, slots, part,
-                           tile_status, num_tiles);
+        hipLaunchKernelGGL(k_reduce<false>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part);
     return hipGetLastError();
 }
 
@@ -1594,21 +1259,6 @@ hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsig
                         uint32_t nblocks, hipStream_t stream) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, stream, pts, n, oct, part, nblocks);
     return hipGetLastError();
-}
-
-#define HULLF_SHAPES(X) X(256, 8) X(256, 16) X(512, 8) X(512, 16)
-
-hipError_t launch_filter(const float2* pts, uint64_t n, const Octagon* oct, ReduceSlots* slots,
-                         uint64_t* tile_status, uint32_t num_tiles, uint32_t* surv, uint64_t cap,
-                         uint64_t* count, Shape shape, int grid, hipStream_t stream) {
-    const bool v = is_vec4(pts);
-#define X(B, P)                                                                                   \
-    if (shape.block == B && shape.ppt == P)                                                       \
-        return launch_filter_t<B, P>(pts, n, oct, slots, tile_status, num_tiles, surv, cap, count, \
-                                     v, grid, stream);
-    HULLF_SHAPES(X)
-#undef X
-    return hipErrorInvalidValue;
 }
 
 uint32_t compact_span_points() { return kSpan; }
@@ -1669,12 +1319,6 @@ hipError_t launch_gather(const float2* pts, const uint32_t* surv, const uint64_t
     return hipGetLastError();
 }
 
-uint64_t batch_max_tiles(uint64_t n_total, uint32_t S, Shape shape) {
-    // each non-empty set needs at most n/T + 2 tiles (one for the pair
-    // alignment of its first point)
-    return n_total / (uint64_t)(shape.block * shape.ppt) + 2ull * S + 1ull;
-}
-
 uint64_t batch_max_items(uint64_t n_total, uint32_t S) { return n_total / kBatchItem + 2ull * S + 1ull; }
 
 uint32_t batch_item_words() { return kBatchItem / 64; }
@@ -1695,19 +1339,15 @@ uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S) { return n_total / kBatc
 
 hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
                         SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
-                        Octagon* octs, uint64_t* tile_status, uint64_t* bits, uint32_t* blkcnt,
-                        uint32_t max_ftiles, uint32_t* surv, uint64_t* counts, Shape shape, int cus,
-                        hipStream_t stream) {
+                        Octagon* octs, uint64_t* bits, uint32_t* blkcnt, uint32_t max_items, uint32_t* surv,
+                        uint64_t* counts, Shape shape, int cus, hipStream_t stream) {
     if (!shape_supported(shape)) return hipErrorInvalidValue;
-    const bool two = bits != nullptr;
-    const uint32_t ft = two ? kBatchItem : (uint32_t)(shape.block * shape.ppt);
-    uint64_t* ts = two ? nullptr : tile_status;
     if (seg)
-        hipLaunchKernelGGL(k_batch_plan<true>, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts,
-                           ts, max_ftiles, max_rtiles, n_total, ft);
+        hipLaunchKernelGGL(k_batch_plan<true>, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts, max_items,
+                           max_rtiles, n_total, kBatchItem);
     else
         hipLaunchKernelGGL(k_batch_plan<false>, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts,
-                           ts, max_ftiles, max_rtiles, n_total, ft);
+                           max_items, max_rtiles, n_total, kBatchItem);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const bool v = is_vec4(pts);
@@ -1722,27 +1362,17 @@ hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32
     hipLaunchKernelGGL(k_batch_setup, dim3(sblocks), dim3(256), 0, stream, pts, S, sets, part, octs, counts);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (two) {
-        const int fgrid = cus * (shape.block >= 512 ? 3 : 6);
-        bool done = false;
-        HULLF_BATCH_CLASSIFY(256, 8)
-        HULLF_BATCH_CLASSIFY(256, 16)
-        HULLF_BATCH_CLASSIFY(512, 8)
-        HULLF_BATCH_CLASSIFY(512, 16)
-        if (!done) return hipErrorInvalidValue;
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_batch_compact<256>, dim3(cus * 8), dim3(256), 0, stream, S, sets, octs, tot, bits,
-                           blkcnt, surv, counts);
-        return hipGetLastError();
-    }
     const int fgrid = cus * (shape.block >= 512 ? 3 : 6);
-#define X(B, P)                                                                                          \
-    if (shape.block == B && shape.ppt == P)                                                              \
-        return launch_batch_filter_t<B, P>(pts, S, sets, octs, tot, tile_status, surv, counts, v, fgrid, \
-                                           stream);
-    HULLF_SHAPES(X)
-#undef X
-    return hipErrorInvalidValue;
+    bool done = false;
+    HULLF_BATCH_CLASSIFY(256, 8)
+    HULLF_BATCH_CLASSIFY(256, 16)
+    HULLF_BATCH_CLASSIFY(512, 8)
+    HULLF_BATCH_CLASSIFY(512, 16)
+    if (!done) return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_compact<256>, dim3(cus * 8), dim3(256), 0, stream, S, sets, octs, tot, bits, blkcnt,
+                       surv, counts);
+    return hipGetLastError();
 }
 
 }  // namespace hullf

@@ -44,11 +44,8 @@ struct hullf_ctx {
     int device = 0;
     int cus = 256;
     // one point set
-    ReduceSlots* slots = nullptr;
     Octagon* oct = nullptr;
     unsigned long long* part = nullptr;   // 9 * kReduceMaxGrid
-    uint64_t* status = nullptr;
-    uint64_t status_cap = 0;
     uint64_t* count = nullptr;
     uint32_t* surv = nullptr;
     uint64_t surv_cap = 0;
@@ -75,7 +72,6 @@ struct hullf_ctx {
     uint64_t h_fv_cap = 0;
     uint32_t* h_total = nullptr;
     Shape filter_shape{512, 16};
-    bool two_pass = true;                  // classify + compact (else single-pass look-back)
     bool host_finish = false;              // hull finishing always on the host
     int classify_per_cu = 0;               // classify blocks per CU (0: what occupancy allows)
     int compact_block = 512;               // threads per compaction block
@@ -89,8 +85,6 @@ struct hullf_ctx {
     BatchTotals* b_tot = nullptr;
     unsigned long long* b_part = nullptr;
     uint64_t b_part_cap = 0;   // records (9 words each)
-    uint64_t* b_status = nullptr;
-    uint64_t b_status_cap = 0;
     uint64_t* b_bits = nullptr;            // two-pass: keep bits per work item
     uint32_t* b_blkcnt = nullptr;          // two-pass: survivors per work item
     uint64_t b_items_cap = 0;
@@ -218,22 +212,6 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
                             uint64_t cap, uint64_t* d_count, hipStream_t s) {
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
     const int rg = reduce_grid(c, n);
-    if (!c->two_pass) {
-        const uint64_t T = filter_tile_points(c->filter_shape);
-        const uint64_t tiles = (n + T - 1) / T;
-        CHECK_HIP(grow_device(&c->status, &c->status_cap, tiles, s));
-        CHECK_HIP(timed(c, 0, s, [&] {
-            return launch_reduce(pts, n, c->slots, c->part, c->status, (uint32_t)tiles, rg, s);
-        }));
-        CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
-        const int per_cu = c->filter_shape.block >= 512 ? 4 : 8;
-        const int fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)c->cus * per_cu));
-        CHECK_HIP(timed(c, 1, s, [&] {
-            return launch_filter(pts, n, c->oct, c->slots, c->status, (uint32_t)tiles, d_surv, cap,
-                                 d_count, c->filter_shape, fg, s);
-        }));
-        return HULLF_OK;
-    }
     Shape sh = c->filter_shape;
     if (!classify_shape_supported(sh)) sh = Shape{512, 16};
     const uint64_t span = compact_span_points();
@@ -243,7 +221,7 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
     const uint64_t spans = (nspans + target - 1) / target;
     const int grid = (int)((nspans + spans - 1) / spans);
     CHECK_HIP(grow_device(&c->bits, &c->bits_cap, 2 * ((n + 127) / 128), s));
-    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->slots, c->part, nullptr, 0, rg, s); }));
+    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, rg, s); }));
     CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
     CHECK_HIP(timed(c, 1, s, [&] {
         return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, sh, grid, s);
@@ -376,7 +354,7 @@ hullf_status hull_of(hullf_ctx* c, const float2* pts, uint64_t n, const uint32_t
     return HULLF_OK;
 }
 
-hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, Shape shape, hipStream_t s) {
+hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, hipStream_t s) {
     bool realloc = false;
     if (S > c->b_sets_cap) {
         CHECK_HIP(hipStreamSynchronize(s));
@@ -391,25 +369,20 @@ hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, Shape shap
         c->b_sets_cap = cap;
         realloc = true;
     }
-    const uint64_t ftiles = c->two_pass ? batch_max_items(n_total, S) : batch_max_tiles(n_total, S, shape);
+    const uint64_t items = batch_max_items(n_total, S);
     const uint64_t rtiles = batch_max_rtiles(n_total, S);
-    if (ftiles > 0xFFFFFFFFull || rtiles > 0xFFFFFFFFull) return HULLF_EINVAL;
-    if (c->two_pass) {
-        if (ftiles > c->b_items_cap || !c->b_bits || !c->b_blkcnt) {
-            CHECK_HIP(hipStreamSynchronize(s));
-            (void)hipFree(c->b_bits);
-            (void)hipFree(c->b_blkcnt);
-            c->b_bits = nullptr;
-            c->b_blkcnt = nullptr;
-            c->b_items_cap = 0;
-            const uint64_t cap = ftiles + ftiles / 4 + 64;
-            CHECK_HIP(hipMalloc((void**)&c->b_bits, cap * batch_item_words() * sizeof(uint64_t)));
-            CHECK_HIP(hipMalloc((void**)&c->b_blkcnt, cap * sizeof(uint32_t)));
-            c->b_items_cap = cap;
-            realloc = true;
-        }
-    } else if (ftiles > c->b_status_cap || !c->b_status) {
-        CHECK_HIP(grow_device(&c->b_status, &c->b_status_cap, ftiles, s));
+    if (items > 0xFFFFFFFFull || rtiles > 0xFFFFFFFFull) return HULLF_EINVAL;
+    if (items > c->b_items_cap || !c->b_bits || !c->b_blkcnt) {
+        CHECK_HIP(hipStreamSynchronize(s));
+        (void)hipFree(c->b_bits);
+        (void)hipFree(c->b_blkcnt);
+        c->b_bits = nullptr;
+        c->b_blkcnt = nullptr;
+        c->b_items_cap = 0;
+        const uint64_t cap = items + items / 4 + 64;
+        CHECK_HIP(hipMalloc((void**)&c->b_bits, cap * batch_item_words() * sizeof(uint64_t)));
+        CHECK_HIP(hipMalloc((void**)&c->b_blkcnt, cap * sizeof(uint32_t)));
+        c->b_items_cap = cap;
         realloc = true;
     }
     if (rtiles > c->b_part_cap || !c->b_part) {
@@ -426,12 +399,10 @@ hullf_status enqueue_batched(hullf_ctx* c, const hullf_pt* d_pts, const uint64_t
                              uint64_t n_total, uint32_t* d_surv, uint64_t* d_counts, Shape shape,
                              hipStream_t s, bool seg = false) {
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
-    const uint64_t fcap = c->two_pass ? c->b_items_cap : c->b_status_cap;
     CHECK_HIP(launch_batch(pts, d_off, seg, S, n_total, c->b_sets, c->b_tot, c->b_part,
-                           (uint32_t)std::min<uint64_t>(c->b_part_cap, 0xFFFFFFFFull), c->b_octs, c->b_status,
-                           c->two_pass ? c->b_bits : nullptr, c->b_blkcnt,
-                           (uint32_t)std::min<uint64_t>(fcap, 0xFFFFFFFFull), d_surv, d_counts, shape, c->cus,
-                           s));
+                           (uint32_t)std::min<uint64_t>(c->b_part_cap, 0xFFFFFFFFull), c->b_octs, c->b_bits,
+                           c->b_blkcnt, (uint32_t)std::min<uint64_t>(c->b_items_cap, 0xFFFFFFFFull), d_surv,
+                           d_counts, shape, c->cus, s));
     return HULLF_OK;
 }
 
@@ -478,7 +449,6 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
         Shape sh{0, 0};
         if (std::sscanf(e, "%d,%d", &sh.block, &sh.ppt) == 2 && shape_supported(sh)) c->filter_shape = sh;
     }
-    if (const char* e = std::getenv("HULLF_COMPACTION")) c->two_pass = std::strcmp(e, "single") != 0;
     if (const char* e = std::getenv("HULLF_FINISH")) c->host_finish = std::strcmp(e, "host") == 0;
     if (const char* e = std::getenv("HULLF_CLASSIFY_PER_CU")) c->classify_per_cu = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("HULLF_COMPACT_BLOCK")) {
@@ -486,7 +456,6 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
         if (b == 256 || b == 512 || b == 1024) c->compact_block = b;
     }
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = hipMalloc((void**)&c->slots, sizeof(ReduceSlots));
     if (e == hipSuccess) e = hipMalloc((void**)&c->oct, sizeof(Octagon));
     if (e == hipSuccess) e = hipMalloc((void**)&c->part, 9ull * kReduceMaxGrid * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&c->count, sizeof(uint64_t));
@@ -495,7 +464,6 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_count, sizeof(uint64_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_oct, sizeof(Octagon), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
-    if (e == hipSuccess) e = launch_init_slots(c->slots, 1, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         hullf_destroy(c);
@@ -515,8 +483,8 @@ void hullf_destroy(hullf_ctx_t c) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
-    void* dev[] = {c->slots, c->oct, c->part, c->status, c->count, c->surv, c->gather, c->bits, c->blkcnt,
-                   c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_status, c->b_bits, c->b_blkcnt};
+    void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt,
+                   c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* fin[] = {c->fk[0], c->fk[1], c->fk[2], c->fv[0], c->fv[1], c->fv[2], c->fchain, c->fcnt, c->fhist,
@@ -537,7 +505,7 @@ hullf_status hullf_octagon(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uin
     hipStream_t s = (hipStream_t)stream;
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
     const int rg = reduce_grid(c, n);
-    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->slots, c->part, nullptr, 0, rg, s); }));
+    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, rg, s); }));
     CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
     CHECK_HIP(hipMemcpyAsync(c->h_oct, c->oct, sizeof(Octagon), hipMemcpyDeviceToHost, s));
     CHECK_HIP(hipStreamSynchronize(s));
@@ -568,7 +536,7 @@ hullf_status hullf_flags(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint8
     hipStream_t s = (hipStream_t)stream;
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
     const int rg = reduce_grid(c, n);
-    CHECK_HIP(launch_reduce(pts, n, c->slots, c->part, nullptr, 0, rg, s));
+    CHECK_HIP(launch_reduce(pts, n, c->part, rg, s));
     CHECK_HIP(launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s));
     const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, (uint64_t)c->cus * 16));
     CHECK_HIP(launch_flags(pts, n, c->oct, d_flags, grid, s));
@@ -628,7 +596,7 @@ hullf_status hull_filter_batched_shape(hullf_ctx_t c, const hullf_pt* d_pts, con
     if (!shape_supported(shape)) return HULLF_EINVAL;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    st = ensure_batch(c, S, n_total, shape, s);
+    st = ensure_batch(c, S, n_total, s);
     if (st != HULLF_OK) return st;
     hullf_status r = HULLF_OK;
     CHECK_HIP(timed(c, 2, s, [&] {
@@ -645,7 +613,7 @@ hullf_status hull_filter_segments(hullf_ctx_t c, const hullf_pt* d_pts, const ui
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     const Shape shape = c->batch_shape;
-    st = ensure_batch(c, S, n_total, shape, s);
+    st = ensure_batch(c, S, n_total, s);
     if (st != HULLF_OK) return st;
     hullf_status r = HULLF_OK;
     CHECK_HIP(timed(c, 2, s, [&] {
@@ -662,7 +630,7 @@ hullf_status hull_filter_batched(hullf_ctx_t c, const hullf_pt* d_pts, const uin
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     const Shape shape = c->batch_shape;
-    st = ensure_batch(c, S, n_total, shape, s);
+    st = ensure_batch(c, S, n_total, s);
     if (st != HULLF_OK) return st;
     GraphEntry* hit = nullptr;
     for (auto& ge : c->graphs)
@@ -713,7 +681,7 @@ hullf_status hullf_autotune_batched(hullf_ctx_t c, const hullf_pt* d_pts, const 
     float bms = 0.0f;
     hullf_status r = HULLF_OK;
     for (const Shape& sh : shapes) {
-        r = ensure_batch(c, S, n_total, sh, s);
+        r = ensure_batch(c, S, n_total, s);
         if (r != HULLF_OK) break;
         r = enqueue_batched(c, d_pts, d_off, S, n_total, d_surv, d_counts, sh, s);   // warm-up
         if (r != HULLF_OK) break;
