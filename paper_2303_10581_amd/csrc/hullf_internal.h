@@ -29,6 +29,12 @@ struct alignas(16) Octagon {
     float cx, cy, pad0, pad1;
     float A[8], NB[8], C0[8];
     double ax[8], ay[8], ex[8], ey[8];
+    // Region skip (skip == 1): a box whose four corners all have binary64
+    // edge values above sm[e] on every edge lies strictly inside the rule's
+    // discard region, with the margin of the quick-accept box proof.
+    double sm[8];
+    int32_t skip;
+    int32_t pad2[3];
 };
 
 // Per-set bookkeeping of the batched launch (written by the plan kernel).
@@ -61,9 +67,11 @@ struct Shape {
 
 // Launchers (all asynchronous on `stream`; return the launch error).
 // Extremes of one set in two launches: launch_reduce writes 9 * grid
-// uint64 partial records to `part`; launch_setup merges them and writes the
-// octagon.
-hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, int grid, hipStream_t stream);
+// uint64 partial records to `part` and, if box is not null, 4 boxes per
+// reduce_chunk_points() points (box_count(n) float4); launch_setup merges
+// the records and writes the octagon.
+hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, float4* box, int grid,
+                         hipStream_t stream);
 hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsigned long long* part,
                         uint32_t nblocks, hipStream_t stream);
 constexpr int kReduceMaxGrid = 4096;
@@ -83,8 +91,14 @@ bool shape_supported(Shape shape);
 // bits: 2 * ceil(n / 128) words; blkcnt: grid words.
 uint32_t compact_span_points();
 bool classify_shape_supported(Shape shape);
+// Region skip: launch_boxmap sets bit i of skipbits (ceil(nbox/64) words)
+// iff reduction box i lies inside the discard region of the octagon;
+// launch_classify does not read groups whose box bit is set (skipbits may be
+// null: no skipping).
+hipError_t launch_boxmap(const float4* box, uint32_t nbox, const Octagon* oct, uint64_t* skipbits,
+                         hipStream_t stream);
 hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
-                           uint32_t* blkcnt, Shape shape, int grid, hipStream_t stream);
+                           uint32_t* blkcnt, const uint64_t* skipbits, Shape shape, int grid, hipStream_t stream);
 // block: 256, 512 or 1024 threads (one span per wave and round).
 hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
                           const Octagon* oct, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,

@@ -84,6 +84,27 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
+// Minimum / maximum over the wave with DPP (fused into the ALU op, no LDS):
+// quad swaps, half-row and row mirrors, then the two row broadcasts; the
+// result is exact in lane 63 and returned as a wave-uniform value.
+template <bool MAX>
+__device__ __forceinline__ float wave_minmax_dpp(float x) {
+#define HULLF_DPP_STEP(CTRL, ROWS)                                                                          \
+    {                                                                                                      \
+        const float y = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),   \
+                                                                   CTRL, ROWS, 0xF, false));              \
+        x = MAX ? fmaxf(x, y) : fminf(x, y);                                                               \
+    }
+    HULLF_DPP_STEP(0xB1, 0xF)    // quad_perm [1,0,3,2]
+    HULLF_DPP_STEP(0x4E, 0xF)    // quad_perm [2,3,0,1]
+    HULLF_DPP_STEP(0x141, 0xF)   // row_half_mirror
+    HULLF_DPP_STEP(0x140, 0xF)   // row_mirror
+    HULLF_DPP_STEP(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
+    HULLF_DPP_STEP(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
+#undef HULLF_DPP_STEP
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Buffer resource (V#) over `bytes` bytes at a wave-uniform base: raw
@@ -210,10 +231,13 @@ __device__ __forceinline__ uint32_t opaque_tid() {
 // return (all threads), rec[j] (j < 8) holds the block's packed (key,
 // lowest index relative to lo) for direction j, or 0 if the block saw no
 // point, and rec[8] is 1 if a NaN was seen.
+// box (optional): box[c*NW + w] = (min x, max x, min y, max y) of the
+// points wave w read in chunk c -- groups 4k+w (k < G) of 128 points of the
+// chunk; NaN for a partial chunk.
 template <int BLOCK, int G, bool VEC4>
 __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, uint64_t lo, uint64_t hi, uint64_t al,
                                               uint32_t c0, uint32_t cstep, uint32_t nch,
-                                              unsigned long long* rec) {
+                                              unsigned long long* rec, float4* __restrict__ box) {
     constexpr uint32_t CH = BLOCK * G * 2;
     constexpr int NW = BLOCK / 64;
     __shared__ float sh_v[8][NW];
@@ -260,7 +284,16 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
             if (m5 < v[5]) { v[5] = m5; grp[5] = c; }
             if (m6 < v[6]) { v[6] = m6; grp[6] = c; }
             if (m7 > v[7]) { v[7] = m7; grp[7] = c; }
+            if (box) {
+                const float b0 = wave_minmax_dpp<false>(m4), b1 = wave_minmax_dpp<true>(m0);
+                const float b2 = wave_minmax_dpp<false>(m6), b3 = wave_minmax_dpp<true>(m2);
+                if (lane_id() == 0) box[(uint64_t)c * NW + (t >> 6)] = make_float4(b0, b1, b2, b3);
+            }
         } else {
+            if (box && lane_id() == 0) {
+                const float qn = __builtin_nanf("");
+                box[(uint64_t)c * NW + (t >> 6)] = make_float4(qn, qn, qn, qn);
+            }
             const RangeView rv = range_view(pts, cb, CH, lo, hi);
             const uint32_t tt = opaque_tid();
 #pragma unroll 1
@@ -377,6 +410,7 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
         o->mode = 0;
         o->fast = 0;
         o->m = 0;
+        o->skip = 0;
         o->bxl = kInfF;
         o->bxh = -kInfF;
         o->byl = kInfF;
@@ -439,7 +473,10 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
     const float cx = (float)(0.5 * (double)xmin + 0.5 * (double)xmax);
     const float cy = (float)(0.5 * (double)ymin + 0.5 * (double)ymax);
     const double M = (fabs(ex) * H + fabs(ey) * W) * up;
-    bool ok = isfinite(W) && isfinite(H) && (M > 0.0) && isfinite(M);
+    const bool mok = isfinite(W) && isfinite(H) && (M > 0.0) && isfinite(M);
+    if (lane < 8) o->sm[j] = 0x1p-48 * M;
+    const bool skipok = __ballot(lane < 8 && !mok) == 0ull;
+    bool ok = mok;
     int E = 0;
     (void)frexp(ok ? M * 0x1p-20 : 1.0, &E);   // 16 u M = f 2^E, f in [0.5, 1)
     const double sc = ldexp(1.0, -E);
@@ -487,6 +524,7 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
             o->byl = YL;
             o->byh = YH;
         }
+        o->skip = skipok ? 1 : 0;
         o->mode = 1;
     }
     return 0;
@@ -552,18 +590,28 @@ __device__ __forceinline__ bool keep_point(const Octagon* __restrict__ o, float 
 // with base sb covers points sb + 2*(j*BLOCK + t) + {0, 1}.  Masks hold bit
 // 2j+h for point h of pair slot j.
 
-// Load one sub-tile; returns the validity mask (bit 2j+h).
+// Load one sub-tile; returns the validity mask (bit 2j+h).  Pair slots with
+// bit j of skipm set (full sub-tiles only) are not read; their points are
+// marked invalid.
 template <int BLOCK, int PPT, bool VEC4>
 __device__ __forceinline__ uint32_t load_sub(const float2* __restrict__ pts, uint64_t lo, uint64_t hi,
-                                             uint64_t sb, float4 (&q)[PPT / 2]) {
+                                             uint64_t sb, float4 (&q)[PPT / 2], uint32_t skipm = 0u) {
     constexpr int NP = PPT / 2;
     constexpr uint32_t ST = BLOCK * PPT;
     const uint32_t t = threadIdx.x;
     if (sb >= lo && sb + ST <= hi) {
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + sb, ST * 8u);
+        uint32_t validm = 0;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) q[j] = load_pair_buf<VEC4>(rs, 16u * t, 16u * j * BLOCK);
-        return (NP >= 16) ? 0xFFFFFFFFu : ((1u << (2 * NP)) - 1u);
+        for (int j = 0; j < NP; ++j) {
+            if ((skipm >> j) & 1u) {   // wave-uniform
+                q[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            } else {
+                q[j] = load_pair_buf<VEC4>(rs, 16u * t, 16u * j * BLOCK);
+                validm |= 3u << (2 * j);
+            }
+        }
+        return validm;
     }
     const RangeView rv = range_view(pts, sb, ST, lo, hi);
     const uint32_t tt = opaque_tid();
@@ -651,11 +699,11 @@ constexpr int kRG = 4;   // pairs per thread per chunk: 8 points
 // the records; the kernel boundary makes them visible.
 template <bool VEC4>
 __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_reduce(
-    const float2* __restrict__ pts, uint64_t n, unsigned long long* __restrict__ part) {
+    const float2* __restrict__ pts, uint64_t n, unsigned long long* __restrict__ part, float4* __restrict__ box) {
     constexpr uint32_t CH = kRBlock * kRG * 2;
     const uint32_t nch = (uint32_t)((n + CH - 1) / CH);
     __shared__ unsigned long long rec[9];
-    reduce_points<kRBlock, kRG, VEC4>(pts, 0, n, 0, blockIdx.x, gridDim.x, nch, rec);
+    reduce_points<kRBlock, kRG, VEC4>(pts, 0, n, 0, blockIdx.x, gridDim.x, nch, rec, box);
     if (threadIdx.x < 9) part[(uint64_t)blockIdx.x * 9 + threadIdx.x] = rec[threadIdx.x];
 }
 
@@ -720,10 +768,45 @@ constexpr uint32_t kSpan = 8192;
 constexpr uint32_t kSpanGroups = kSpan / 128;
 static_assert(kSpanGroups == 64, "one group per lane");
 
+// Region skip.  k_boxmap tests every reduction box against the octagon:
+// bit i of skipbits is set iff all four corners of box i have a binary64
+// edge value above sm[e] on every edge e -- the test the quick-accept box
+// passes in the octagon set-up, so every point in the box is discarded by
+// the rule.  k_classify then does not read groups whose box bit is set.
+// Group g of a set was read in the reduction by wave g % 4 of chunk g / 16:
+// its box is 4 * (g / 16) + g % 4.
+static_assert(kRBlock * kRG * 2 == 16 * 128 && kRBlock / 64 == 4, "box of group g: chunk g/16, wave g%4");
+typedef const __attribute__((address_space(4))) uint64_t SkipK;
+
+__global__ __launch_bounds__(256) void k_boxmap(const float4* __restrict__ box, uint32_t nbox,
+                                                const Octagon* __restrict__ oct, uint64_t* __restrict__ skipbits) {
+    OctagonK* ok = as_const(oct);
+    const bool on = ok->status == 0 && ok->mode == 1 && ok->skip != 0;
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    bool pass = false;
+    if (on && i < nbox) {
+        const float4 b = box[i];
+        pass = true;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const double ax = ok->ax[e], ay = ok->ay[e], ex = ok->ex[e], ey = ok->ey[e], sm = ok->sm[e];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double qx = (double)((k & 1) ? b.y : b.x);
+                const double qy = (double)((k & 2) ? b.w : b.z);
+                const double D = ex * (qy - ay) - ey * (qx - ax);
+                pass = pass && (D > sm);   // false for NaN boxes
+            }
+        }
+    }
+    const unsigned long long m = __ballot(pass);
+    if (lane_id() == 0 && (uint64_t)(i & ~63u) < (uint64_t)nbox) skipbits[i >> 6] = m;
+}
+
 template <int BLOCK, int PPT, bool VEC4>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_classify(
     const float2* __restrict__ pts, uint64_t n, const Octagon* __restrict__ oct, uint32_t spans,
-    uint64_t* __restrict__ bits, uint32_t* __restrict__ blkcnt) {
+    uint64_t* __restrict__ bits, uint32_t* __restrict__ blkcnt, const uint64_t* __restrict__ skipbits) {
     constexpr int NP = PPT / 2;
     constexpr int NW = BLOCK / 64;
     constexpr uint32_t ST = BLOCK * PPT;
@@ -731,14 +814,27 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     static_assert(NP <= 64, "one lane per pair slot stores the bits");
     __shared__ uint32_t sh_w[NW];
     if (oct->status != 0) return;
-    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform_u32(threadIdx.x >> 6);   // keeps wave-derived addresses scalar
     const uint64_t r0 = (uint64_t)blockIdx.x * spans * kSpan;
     const uint64_t r1 = min<uint64_t>(n, r0 + (uint64_t)spans * kSpan);
     const uint64_t ngroups = (n + 127) / 128;
+    SkipK* sk = (SkipK*)skipbits;
     uint32_t total = 0;
     for (uint64_t sb = r0; sb < r1; sb += ST) {
+        uint32_t skipm = 0;
+        if (sk && sb + ST <= n) {
+            // this sub-tile's boxes are 4*ST/2048 consecutive bits of one word
+            const uint64_t word = sk[(sb >> 11) >> 4];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const uint64_t gg = (sb >> 7) + (uint64_t)(j * NW) + wave;
+                const uint64_t bi = (gg >> 4) * 4 + (gg & 3);
+                skipm |= (uint32_t)((word >> (bi & 63)) & 1ull) << j;
+            }
+        }
         float4 q[NP];
-        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q);
+        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q, skipm);
         const uint32_t k = classify_sub<BLOCK, PPT>(oct, pts, sb, q, validm);
         // lane j keeps the two ballots of pair slot j, then all NP groups
         // of this wave are stored by one instruction
@@ -1060,7 +1156,7 @@ __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
         const uint64_t b = sets[s].begin, n = sets[s].n;
         const uint64_t tb = (b & ~1ull) + (uint64_t)(r - sets[s].r_tile0) * kBatchRT;
         __shared__ unsigned long long rec[9];
-        reduce_points<kRBlock, kRG, VEC4>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec);
+        reduce_points<kRBlock, kRG, VEC4>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec, nullptr);
         if (threadIdx.x < 9) part[(uint64_t)r * 9 + threadIdx.x] = rec[threadIdx.x];
     }
 }
@@ -1247,11 +1343,12 @@ bool shape_supported(Shape s) {
     return (s.block == 256 || s.block == 512) && (s.ppt == 8 || s.ppt == 16);
 }
 
-hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, int grid, hipStream_t stream) {
+hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, float4* box, int grid,
+                         hipStream_t stream) {
     if (is_vec4(pts))
-        hipLaunchKernelGGL(k_reduce<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part);
+        hipLaunchKernelGGL(k_reduce<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part, box);
     else
-        hipLaunchKernelGGL(k_reduce<false>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part);
+        hipLaunchKernelGGL(k_reduce<false>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part, box);
     return hipGetLastError();
 }
 
@@ -1269,17 +1366,24 @@ bool classify_shape_supported(Shape s) {
 
 #define HULLF_CLASSIFY_SHAPES(X) X(256, 8) X(256, 16) X(512, 8) X(512, 16)
 
+hipError_t launch_boxmap(const float4* box, uint32_t nbox, const Octagon* oct, uint64_t* skipbits,
+                         hipStream_t stream) {
+    if (nbox == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_boxmap, dim3((nbox + 255) / 256), dim3(256), 0, stream, box, nbox, oct, skipbits);
+    return hipGetLastError();
+}
+
 hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
-                           uint32_t* blkcnt, Shape shape, int grid, hipStream_t stream) {
+                           uint32_t* blkcnt, const uint64_t* skipbits, Shape shape, int grid, hipStream_t stream) {
     const bool v = is_vec4(pts);
 #define X(B, P)                                                                                           \
     if (shape.block == B && shape.ppt == P) {                                                             \
         if (v)                                                                                            \
             hipLaunchKernelGGL((k_classify<B, P, true>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
-                               bits, blkcnt);                                                             \
+                               bits, blkcnt, skipbits);                                                   \
         else                                                                                              \
             hipLaunchKernelGGL((k_classify<B, P, false>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
-                               bits, blkcnt);                                                             \
+                               bits, blkcnt, skipbits);                                                   \
         return hipGetLastError();                                                                         \
     }
     HULLF_CLASSIFY_SHAPES(X)

@@ -78,6 +78,11 @@ struct hullf_ctx {
     uint64_t* bits = nullptr;              // keep bits, 2 words per 128 points
     uint64_t bits_cap = 0;
     uint32_t* blkcnt = nullptr;            // kMaxBlocks survivor counts
+    float4* boxes = nullptr;               // reduction boxes (region skip), 4 per 2048 points
+    uint64_t boxes_cap = 0;
+    uint64_t* skipbits = nullptr;          // one bit per box
+    uint64_t skipbits_cap = 0;
+    bool region_skip = true;
     // batched
     uint32_t b_sets_cap = 0;
     SetInfo* b_sets = nullptr;
@@ -221,10 +226,25 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
     const uint64_t spans = (nspans + target - 1) / target;
     const int grid = (int)((nspans + spans - 1) / spans);
     CHECK_HIP(grow_device(&c->bits, &c->bits_cap, 2 * ((n + 127) / 128), s));
-    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, rg, s); }));
-    CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
+    float4* box = nullptr;
+    uint64_t* skipbits = nullptr;
+    uint64_t nbox = 0;
+    if (c->region_skip) {
+        const uint64_t ch = reduce_chunk_points();
+        nbox = 4 * ((n + ch - 1) / ch);
+        CHECK_HIP(grow_device(&c->boxes, &c->boxes_cap, nbox, s));
+        CHECK_HIP(grow_device(&c->skipbits, &c->skipbits_cap, (nbox + 63) / 64, s));
+        box = c->boxes;
+        skipbits = c->skipbits;
+    }
+    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, box, rg, s); }));
+    CHECK_HIP(timed(c, 3, s, [&] {
+        hipError_t e = launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s);
+        if (e == hipSuccess && box) e = launch_boxmap(box, (uint32_t)nbox, c->oct, skipbits, s);
+        return e;
+    }));
     CHECK_HIP(timed(c, 1, s, [&] {
-        return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, sh, grid, s);
+        return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, skipbits, sh, grid, s);
     }));
     CHECK_HIP(timed(c, 4, s, [&] {
         return launch_compact(c->bits, c->blkcnt, n, (uint32_t)spans, c->oct, d_surv, cap, d_count,
@@ -450,6 +470,7 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
         if (std::sscanf(e, "%d,%d", &sh.block, &sh.ppt) == 2 && shape_supported(sh)) c->filter_shape = sh;
     }
     if (const char* e = std::getenv("HULLF_FINISH")) c->host_finish = std::strcmp(e, "host") == 0;
+    if (const char* e = std::getenv("HULLF_REGION_SKIP")) c->region_skip = std::atoi(e) != 0;
     if (const char* e = std::getenv("HULLF_CLASSIFY_PER_CU")) c->classify_per_cu = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("HULLF_COMPACT_BLOCK")) {
         const int b = std::atoi(e);
@@ -483,7 +504,7 @@ void hullf_destroy(hullf_ctx_t c) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
-    void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt,
+    void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt, c->boxes, c->skipbits,
                    c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -505,7 +526,7 @@ hullf_status hullf_octagon(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uin
     hipStream_t s = (hipStream_t)stream;
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
     const int rg = reduce_grid(c, n);
-    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, rg, s); }));
+    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, nullptr, rg, s); }));
     CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
     CHECK_HIP(hipMemcpyAsync(c->h_oct, c->oct, sizeof(Octagon), hipMemcpyDeviceToHost, s));
     CHECK_HIP(hipStreamSynchronize(s));
@@ -536,7 +557,7 @@ hullf_status hullf_flags(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint8
     hipStream_t s = (hipStream_t)stream;
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
     const int rg = reduce_grid(c, n);
-    CHECK_HIP(launch_reduce(pts, n, c->part, rg, s));
+    CHECK_HIP(launch_reduce(pts, n, c->part, nullptr, rg, s));
     CHECK_HIP(launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s));
     const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, (uint64_t)c->cus * 16));
     CHECK_HIP(launch_flags(pts, n, c->oct, d_flags, grid, s));

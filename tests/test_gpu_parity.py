@@ -144,6 +144,17 @@ def test_repeated_calls_same_context(ctx, torch_dev):
             assert np.array_equal(survivors_np(ctx, t), oracle.survivors(xy)), (kind, seed)
 
 
+@pytest.mark.parametrize("kind", ["normal", "normal_far", "displaced_tiny"])
+def test_region_skip_with_scattered_near_edge_points(ctx, torch_dev, kind):
+    """Groups whose reduction box lies inside the discard region are not
+    read by the inside test; near-edge points scattered through the set put
+    some of them in boxes that must not be skipped."""
+    base = cases.named_sets(1_000_003, 37)[kind]
+    xy = cases.with_near_edge_points(base, oracle.extremes, per_edge=300, seed=11)
+    xy = xy[np.random.default_rng(5).permutation(xy.shape[0])]
+    _check_all(ctx, torch_dev, xy, "scattered near-edge " + kind, hull=False)
+
+
 def test_config_small_normal_1e6(ctx, torch_dev):
     xy = workloads.normal(1_000_000, 1)
     _check_all(ctx, torch_dev, xy, "normal 1e6 seed 1")
