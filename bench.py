@@ -67,14 +67,16 @@ def make_sets():
     return out
 
 
-def algorithmic_bytes(n: int, survivors: int, two_pass: bool = True):
-    """Bytes each kernel must move.  Reduction: 8 B/pt read.  Two-pass
-    compaction: the inside test reads 8 B/pt and writes the keep bits
-    (1 bit/pt); the compaction reads the bits and writes 4 B per survivor.
-    Single pass: 8 B/pt read + 4 B per survivor written."""
-    if two_pass:
-        return {"reduce": 8 * n, "filter": 8 * n + n // 8, "compact": n // 8 + 4 * survivors}
-    return {"reduce": 8 * n, "filter": 8 * n + 4 * survivors, "compact": 0}
+def algorithmic_bytes(n: int, survivors: int, read_frac: float = 1.0, boxes: bool = True):
+    """Bytes each kernel must move.  Reduction: 8 B/pt read (+ 16 B of
+    bounding box per 512 points written for the region skip).  Inside test:
+    the fraction read_frac of the points it must read (8 B/pt; the region
+    skip leaves out groups inside the discard region) and the keep bits
+    written (1 bit/pt).  Compaction: the bits read and 4 B per survivor
+    written."""
+    return {"reduce": 8 * n + (n // 32 if boxes else 0),
+            "filter": int(8 * n * read_frac) + n // 8,
+            "compact": n // 8 + 4 * survivors}
 
 
 def cpu_baseline(sets, budget_s: float = 15.0):
@@ -144,11 +146,12 @@ def run_bench(args):
     kt = ctx.timing_read()
     ctx.timing(False)
 
-    two_pass = kt["compact"][0] > 0
-    names = {"reduce": "k_reduce", "filter": "k_classify" if two_pass else "k_filter", "compact": "k_compact"}
+    names = {"reduce": "k_reduce", "filter": "k_classify", "compact": "k_compact"}
 
     # per-pass, per-set breakdown (one instrumented pass per set)
     per_set = {}
+    read_frac = []
+    ctx.skip_stats()
     for i, (kind, _, _) in enumerate(sets):
         ctx.timing(True)
         ctx.timing_read()
@@ -156,10 +159,13 @@ def run_bench(args):
             ctx.hull_filter(dpts[i], surv=surv[i], count=cnt[i], stream=stream)
         r = ctx.timing_read()
         ctx.timing(False)
-        ab = algorithmic_bytes(N_SET, survivors[i], two_pass)
+        g_read, g_total = ctx.skip_stats()
+        read_frac.append(g_read / g_total if g_total else 1.0)
+        ab = algorithmic_bytes(N_SET, survivors[i], read_frac[-1])
         ms = {k: (r[k][1] / r[k][0] if r[k][0] else 0.0) for k in ("reduce", "setup", "filter", "compact")}
         dev_ms = sum(ms.values())
-        entry = {"survivors": survivors[i], "setup_us": round(ms["setup"] * 1e3, 2)}
+        entry = {"survivors": survivors[i], "setup_us": round(ms["setup"] * 1e3, 2),
+                 "inside_test_read_frac": round(read_frac[-1], 4)}
         for k in ("reduce", "filter", "compact"):
             if ms[k] > 0:
                 entry[f"{names[k]}_us"] = round(ms[k] * 1e3, 2)
@@ -174,7 +180,7 @@ def run_bench(args):
 
     # dominant kernel: the one with the largest summed device time
     dom = max(("reduce", "filter", "compact"), key=lambda k: kt[k][1])
-    bytes_per_step = sum(algorithmic_bytes(N_SET, s, two_pass)[dom] for s in survivors)
+    bytes_per_step = sum(algorithmic_bytes(N_SET, s, f)[dom] for s, f in zip(survivors, read_frac))
     launches, total_ms = kt[dom]
     per_launch_bytes = bytes_per_step / len(sets)
     avg_ms = total_ms / launches
@@ -183,7 +189,7 @@ def run_bench(args):
     st = stored_traffic()
     if st and names[dom] in st.get("bytes_per_dispatch", {}):
         traffic = st["bytes_per_dispatch"][names[dom]]
-    all_bytes = sum(sum(algorithmic_bytes(N_SET, s, two_pass).values()) for s in survivors)
+    all_bytes = sum(sum(algorithmic_bytes(N_SET, s, f).values()) for s, f in zip(survivors, read_frac))
     step_hbm_frac = all_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS
     per_kernel = {names[k]: {"launches": kt[k][0], "avg_us": round(kt[k][1] / kt[k][0] * 1e3, 2)}
                   for k in ("reduce", "setup", "filter", "compact") if kt[k][0] and k in names}

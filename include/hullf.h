@@ -198,6 +198,15 @@ hullf_status hullf_timing_enable(hullf_ctx_t ctx, int enable);
 hullf_status hullf_timing_read(hullf_ctx_t ctx, uint64_t *launches,
                                double *total_ms);
 
+/* Region-skip statistics (the inside test does not read 128-point groups
+ * whose bounding box, recorded by the extremes reduction, lies inside the
+ * discard region).  Returns, summed over this context's hull_filter and
+ * convex_hull calls since the previous call, the groups the inside test read
+ * and the groups it would have read without the skip, then resets both.
+ * Synchronises the device. */
+hullf_status hullf_skip_stats(hullf_ctx_t ctx, uint64_t *groups_read,
+                              uint64_t *groups_total);
+
 #ifdef __cplusplus
 }
 #endif

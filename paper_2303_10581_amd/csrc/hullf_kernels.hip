@@ -105,6 +105,12 @@ __device__ __forceinline__ float wave_minmax_dpp(float x) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, uint32_t l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Buffer resource (V#) over `bytes` bytes at a wave-uniform base: raw
@@ -806,13 +812,14 @@ __global__ __launch_bounds__(256) void k_boxmap(const float4* __restrict__ box, 
 template <int BLOCK, int PPT, bool VEC4>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_classify(
     const float2* __restrict__ pts, uint64_t n, const Octagon* __restrict__ oct, uint32_t spans,
-    uint64_t* __restrict__ bits, uint32_t* __restrict__ blkcnt, const uint64_t* __restrict__ skipbits) {
+    uint64_t* __restrict__ bits, uint32_t* __restrict__ blkcnt, const uint64_t* __restrict__ skipbits,
+    unsigned long long* loaded) {
     constexpr int NP = PPT / 2;
     constexpr int NW = BLOCK / 64;
     constexpr uint32_t ST = BLOCK * PPT;
     static_assert(kSpan % ST == 0, "sub-tiles tile a span");
     static_assert(NP <= 64, "one lane per pair slot stores the bits");
-    __shared__ uint32_t sh_w[NW];
+    __shared__ uint32_t sh_w[NW], sh_g[NW];
     if (oct->status != 0) return;
     const uint32_t lane = lane_id();
     const uint32_t wave = uniform_u32(threadIdx.x >> 6);   // keeps wave-derived addresses scalar
@@ -820,12 +827,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     const uint64_t r1 = min<uint64_t>(n, r0 + (uint64_t)spans * kSpan);
     const uint64_t ngroups = (n + 127) / 128;
     SkipK* sk = (SkipK*)skipbits;
-    uint32_t total = 0;
+    // skip word i covers points [i*32768, (i+1)*32768); lane l preloads word
+    // w0 + l of this block's range so that the loop does not wait on them
+    const uint64_t w0 = r0 >> 15;
+    const uint64_t nwords = (4 * ((n + 2047) / 2048) + 63) / 64;
+    unsigned long long wpre = 0ull;
+    if (skipbits && w0 + lane < nwords && ((w0 + lane) << 15) < r1) wpre = skipbits[w0 + lane];
+    uint32_t total = 0, groups = 0;
     for (uint64_t sb = r0; sb < r1; sb += ST) {
         uint32_t skipm = 0;
         if (sk && sb + ST <= n) {
             // this sub-tile's boxes are 4*ST/2048 consecutive bits of one word
-            const uint64_t word = sk[(sb >> 11) >> 4];
+            const uint64_t rel = (sb >> 15) - w0;
+            const uint64_t word = rel < 64 ? readlane_u64(wpre, (uint32_t)rel) : sk[sb >> 15];
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
                 const uint64_t gg = (sb >> 7) + (uint64_t)(j * NW) + wave;
@@ -833,6 +847,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
                 skipm |= (uint32_t)((word >> (bi & 63)) & 1ull) << j;
             }
         }
+        groups += (uint32_t)(NP - __popc(skipm));
         float4 q[NP];
         const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q, skipm);
         const uint32_t k = classify_sub<BLOCK, PPT>(oct, pts, sb, q, validm);
@@ -857,21 +872,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
             *reinterpret_cast<ulonglong2*>(bits + 2 * g) = v;
         }
     }
-    if (lane == 0) sh_w[wave] = total;
+    if (lane == 0) {
+        sh_w[wave] = total;
+        sh_g[wave] = groups;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t sum = 0;
+        uint32_t sum = 0, g = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) sum += sh_w[w];
+        for (int w = 0; w < NW; ++w) {
+            sum += sh_w[w];
+            g += sh_g[w];
+        }
         blkcnt[blockIdx.x] = sum;
+        if (loaded) atomicAdd(loaded, (unsigned long long)g);   // groups of 128 points read
     }
 }
 
-__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, uint32_t l) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l);
-    return ((uint64_t)hi << 32) | lo;
-}
 
 // Survivors of one span: (w0, w1) are this lane's group words (lane = group),
 // written in ascending order to out[base ...] through the wave's LDS stage.
@@ -1374,16 +1391,17 @@ hipError_t launch_boxmap(const float4* box, uint32_t nbox, const Octagon* oct, u
 }
 
 hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
-                           uint32_t* blkcnt, const uint64_t* skipbits, Shape shape, int grid, hipStream_t stream) {
+                           uint32_t* blkcnt, const uint64_t* skipbits, unsigned long long* loaded, Shape shape,
+                           int grid, hipStream_t stream) {
     const bool v = is_vec4(pts);
 #define X(B, P)                                                                                           \
     if (shape.block == B && shape.ppt == P) {                                                             \
         if (v)                                                                                            \
             hipLaunchKernelGGL((k_classify<B, P, true>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
-                               bits, blkcnt, skipbits);                                                   \
+                               bits, blkcnt, skipbits, loaded);                                           \
         else                                                                                              \
             hipLaunchKernelGGL((k_classify<B, P, false>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
-                               bits, blkcnt, skipbits);                                                   \
+                               bits, blkcnt, skipbits, loaded);                                           \
         return hipGetLastError();                                                                         \
     }
     HULLF_CLASSIFY_SHAPES(X)

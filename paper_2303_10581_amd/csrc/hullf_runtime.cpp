@@ -82,6 +82,8 @@ struct hullf_ctx {
     uint64_t boxes_cap = 0;
     uint64_t* skipbits = nullptr;          // one bit per box
     uint64_t skipbits_cap = 0;
+    unsigned long long* groups_read = nullptr;   // device counter of groups the inside test read
+    uint64_t groups_total = 0;                   // groups it would read without the skip
     bool region_skip = true;
     // batched
     uint32_t b_sets_cap = 0;
@@ -244,8 +246,10 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
         return e;
     }));
     CHECK_HIP(timed(c, 1, s, [&] {
-        return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, skipbits, sh, grid, s);
+        return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, skipbits, c->groups_read, sh,
+                               grid, s);
     }));
+    c->groups_total += (n + 127) / 128;
     CHECK_HIP(timed(c, 4, s, [&] {
         return launch_compact(c->bits, c->blkcnt, n, (uint32_t)spans, c->oct, d_surv, cap, d_count,
                               c->compact_block, grid, s);
@@ -481,6 +485,8 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
     if (e == hipSuccess) e = hipMalloc((void**)&c->part, 9ull * kReduceMaxGrid * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&c->count, sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc((void**)&c->blkcnt, kMaxBlocks * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->groups_read, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(c->groups_read, 0, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&c->b_tot, sizeof(BatchTotals));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_count, sizeof(uint64_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_oct, sizeof(Octagon), hipHostMallocDefault);
@@ -505,6 +511,7 @@ void hullf_destroy(hullf_ctx_t c) {
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt, c->boxes, c->skipbits,
+                   c->groups_read,
                    c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -727,6 +734,19 @@ hullf_status hullf_autotune_batched(hullf_ctx_t c, const hullf_pt* d_pts, const 
     if (best_block) *best_block = best.block;
     if (best_ppt) *best_ppt = best.ppt;
     if (best_ms) *best_ms = bms;
+    return HULLF_OK;
+}
+
+hullf_status hullf_skip_stats(hullf_ctx_t c, uint64_t* groups_read, uint64_t* groups_total) {
+    if (!c || !groups_read || !groups_total) return HULLF_EINVAL;
+    DeviceGuard g(c->device);
+    CHECK_HIP(hipDeviceSynchronize());
+    unsigned long long v = 0;
+    CHECK_HIP(hipMemcpy(&v, c->groups_read, sizeof v, hipMemcpyDeviceToHost));
+    CHECK_HIP(hipMemset(c->groups_read, 0, sizeof v));
+    *groups_read = v;
+    *groups_total = c->groups_total;
+    c->groups_total = 0;
     return HULLF_OK;
 }
 

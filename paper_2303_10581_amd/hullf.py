@@ -51,6 +51,7 @@ def _load():
         "hull_filter_batched_shape": ([P, P, P, U32, U64, P, P, I, I, P], st),
         "hullf_autotune_batched": ([P, P, P, U32, U64, P, P, I, P, P, P, P], st),
         "hullf_timing_enable": ([P, I], st),
+        "hullf_skip_stats": ([P, ctypes.POINTER(U64), ctypes.POINTER(U64)], st),
         "hullf_timing_read": ([P, P, P], st),
         "hullf_server_create": ([I, P, ctypes.POINTER(P)], st),
         "hullf_server_destroy": ([P], None),
@@ -243,6 +244,13 @@ class Context:
     def timing(self, enable: bool):
         _check(_load().hullf_timing_enable(self.handle, 1 if enable else 0), "hullf_timing_enable")
 
+    def skip_stats(self):
+        """(groups read, groups without the region skip) of 128 points by the
+        inside test since the previous call (synchronous; resets)."""
+        r, t = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(_load().hullf_skip_stats(self.handle, ctypes.byref(r), ctypes.byref(t)), "hullf_skip_stats")
+        return r.value, t.value
+
     def timing_read(self):
         """{kind: (launches, total_ms)} for kinds reduce, filter (inside
         test), batched, setup, compact."""
@@ -369,5 +377,5 @@ def exported_symbols():
     return ["hullf_create", "hullf_destroy", "hullf_status_str", "hullf_octagon", "hull_filter",
             "convex_hull", "hullf_flags", "hull_from_survivors", "hull_filter_batched", "hull_filter_segments",
             "hull_filter_batched_shape", "hullf_autotune_batched", "hullf_timing_enable",
-            "hullf_timing_read", "hullf_server_create", "hullf_server_destroy", "hullf_server_submit",
+            "hullf_timing_read", "hullf_skip_stats", "hullf_server_create", "hullf_server_destroy", "hullf_server_submit",
             "hullf_server_wait", "hullf_server_stats"]
