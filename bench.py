@@ -484,7 +484,7 @@ def traffic_summary(fetch_dir, write_dir, out_path=TRAFFIC_JSON):
     kernel of the same run; the result is tagged with the kernel source hash
     so that bench.py reports it only while the kernels are unchanged."""
     def kind(name):
-        for k in ("k_reduce", "k_setup", "k_filter", "k_classify", "k_compact"):
+        for k in ("k_reduce", "k_setup", "k_boxmap", "k_classify", "k_compact"):
             if "::" + k in name or name.startswith(k):
                 return k
         return None
