@@ -341,17 +341,21 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
         for (int w = 1; w < NW; ++w) best = is_max ? fmaxf(best, sh_v[j][w]) : fminf(best, sh_v[j][w]);
         uint32_t cand = 0xFFFFFFFFu;
         if (v[j] == best && grp[j] < nch) {
-            // the lanes in here may hold different chunks: per-lane addresses
+            // the lanes in here may hold different chunks: per-lane
+            // addresses.  All 2G points are loaded before any is compared,
+            // so the reload costs one memory round trip.
             const uint64_t cb = al + (uint64_t)grp[j] * CH;
-#pragma unroll 1
+            float2 q[2 * G];
+#pragma unroll
             for (uint32_t k = 0; k < 2 * G; ++k) {
                 const uint64_t g = cb + 2u * ((k >> 1) * BLOCK + t) + (k & 1u);
-                if (g < lo || g >= hi) continue;
-                const float2 q = pts[g];
-                if (key_of(j, q.x, q.y) == best) {
-                    cand = (uint32_t)(g - lo);
-                    break;
-                }
+                q[k] = (g >= lo && g < hi) ? pts[g] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+            }
+            // ascending point order: the first match is the lowest index
+#pragma unroll
+            for (int k = 2 * G - 1; k >= 0; --k) {
+                const uint64_t g = cb + 2u * (((uint32_t)k >> 1) * BLOCK + t) + ((uint32_t)k & 1u);
+                if (key_of(j, q[k].x, q[k].y) == best) cand = (uint32_t)(g - lo);
             }
         }
         cand = wave_min_u32(cand);
