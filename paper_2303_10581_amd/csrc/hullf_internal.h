@@ -66,10 +66,12 @@ struct Shape {
 
 
 // Launchers (all asynchronous on `stream`; return the launch error).
-// Extremes of one set in two launches: launch_reduce writes 9 * grid
-// uint64 partial records to `part` and, if box is not null, 4 boxes per
-// reduce_chunk_points() points (box_count(n) float4); launch_setup merges
-// the records and writes the octagon.
+// Extremes of one set in two launches: launch_reduce (grid <=
+// kReduceMaxGrid) writes 9 uint64 partial records per block to `part`
+// (9 * kReduceMaxGrid words, direction-major: part[j * kReduceMaxGrid + b])
+// and, if box is not null, 4 boxes per reduce_chunk_points() points
+// (box_count(n) float4); launch_setup merges the records and writes the
+// octagon.
 hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, float4* box, int grid,
                          hipStream_t stream);
 hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsigned long long* part,

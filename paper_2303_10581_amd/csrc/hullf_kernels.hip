@@ -151,10 +151,14 @@ __device__ __forceinline__ float4 load_pair_buf(__amdgpu_buffer_rsrc_t r, uint32
 //
 // The hot loop keeps only the running value of each key and the chunk in
 // which it last strictly improved (so the first chunk that reached it).
-// After the loop, the threads whose value equals the block's best reload
-// that one chunk and pick the first point attaining it; their minimum index
-// is the block's candidate.  This keeps the streaming loop at about 8 VALU
-// operations per point instead of 24 for per-point index selects.
+// After the loop, the lowest such chunk over the threads whose value equals
+// the block's best holds the block's lowest index attaining it.  One point
+// set: the block records that chunk, and k_setup scans only the chunk that
+// wins over all blocks (8 chunks per set instead of up to 8 per block, whose
+// scattered reloads at the end of the grid were costly on sets with many
+// ties).  Batches: the block reloads the winning threads' points itself.
+// Either way the streaming loop stays at about 8 VALU operations per point
+// instead of 24 for per-point index selects.
 
 __device__ __forceinline__ float key_of(int j, float x, float y) {
     switch (j) {
@@ -163,6 +167,16 @@ __device__ __forceinline__ float key_of(int j, float x, float y) {
         case 2: case 6: return y;
         default: return x - y;
     }
+}
+
+// key_of for a j known only at run time, without branches: x + 0, 0 + y,
+// x + y and x + (-y) are exactly x, y, fl32(x+y) and fl32(x-y) (up to the
+// sign of a zero, which equality ignores).
+__device__ __forceinline__ float key_select(int j, float x, float y) {
+    const int m = j & 3;
+    const float a = (m == 2) ? 0.0f : x;
+    const float b = (m == 0) ? 0.0f : ((m == 3) ? -y : y);
+    return a + b;
 }
 
 // IEEE-754 2019 maximum/minimum (NaN-propagating) lower to gfx950's
@@ -233,21 +247,23 @@ __device__ __forceinline__ uint32_t opaque_tid() {
 }
 
 // Reduction of points [lo, hi) over chunks c = c0, c0+cstep, ... < nch of
-// CH = BLOCK*G*2 points starting at the pair-aligned base al <= lo.  On
-// return (all threads), rec[j] (j < 8) holds the block's packed (key,
-// lowest index relative to lo) for direction j, or 0 if the block saw no
-// point, and rec[8] is 1 if a NaN was seen.
+// CH = BLOCK*G*2 points starting at the pair-aligned base al (lo - 1 <= al
+// <= lo).  On return (all threads), rec[j] (j < 8) holds the block's packed
+// (key, position) for direction j, or 0 if the block saw no point, and
+// rec[8] is 1 if a NaN was seen.  The position is the lowest index relative
+// to lo attaining the key (DEFER false), or, with DEFER, the chunk holding
+// that index, as its first point + 1 - lo: the block then skips the reload
+// and the consumer scans the one chunk that wins across blocks.
 // box (optional): box[c*NW + w] = (min x, max x, min y, max y) of the
 // points wave w read in chunk c -- groups 4k+w (k < G) of 128 points of the
 // chunk; NaN for a partial chunk.
-template <int BLOCK, int G, bool VEC4>
+template <int BLOCK, int G, bool VEC4, bool DEFER>
 __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, uint64_t lo, uint64_t hi, uint64_t al,
                                               uint32_t c0, uint32_t cstep, uint32_t nch,
                                               unsigned long long* rec, float4* __restrict__ box) {
     constexpr uint32_t CH = BLOCK * G * 2;
     constexpr int NW = BLOCK / 64;
     __shared__ float sh_v[8][NW];
-    __shared__ uint32_t sh_i[8][NW];
 
     const uint32_t t = threadIdx.x;
     float v[8] = {-kInfF, -kInfF, -kInfF, kInfF, kInfF, kInfF, kInfF, -kInfF};
@@ -323,9 +339,7 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
         }
     }
 
-    // block best per key, then the lowest index attaining it: the threads
-    // holding the best reload the one chunk where they first reached it.
-    // Done key by key so that few values are live at once.
+    // Block best per key.
     const uint32_t lane = lane_id(), wave = t >> 6;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -333,49 +347,99 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
         const float w = is_max ? wave_max(v[j]) : wave_min(v[j]);
         if (lane == 0) sh_v[j][wave] = w;
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    auto block_best = [&](int j) {
         const bool is_max = (j == 0 || j == 1 || j == 2 || j == 7);
         float best = sh_v[j][0];
         for (int w = 1; w < NW; ++w) best = is_max ? fmaxf(best, sh_v[j][w]) : fminf(best, sh_v[j][w]);
-        uint32_t cand = 0xFFFFFFFFu;
-        if (v[j] == best && grp[j] < nch) {
-            // the lanes in here may hold different chunks: per-lane
-            // addresses.  All 2G points are loaded before any is compared,
-            // so the reload costs one memory round trip.
-            const uint64_t cb = al + (uint64_t)grp[j] * CH;
+        return best;
+    };
+    // A thread "holds" key j if its own best equals the block's; grp[j] is
+    // the first chunk where it reached that value, and the lowest such chunk
+    // over the holders contains the block's lowest index attaining it (the
+    // chunks are disjoint and ascending).
+    __shared__ uint32_t sh_cm[8];
+    if (t < 8) sh_cm[t] = 0xFFFFFFFFu;
+    __syncthreads();
+    uint32_t holdm = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (v[j] == block_best(j) && grp[j] < nch) holdm |= 1u << j;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t cw = wave_min_u32((holdm >> j) & 1u ? grp[j] : 0xFFFFFFFFu);
+        if (lane == 0 && cw != 0xFFFFFFFFu) atomicMin(&sh_cm[j], cw);
+    }
+    if constexpr (DEFER) {
+        // Record the chunk itself: rec[j] packs (key, al + c*CH + 1 - lo),
+        // a value >= 0 because al >= lo - 1.  The consumer scans that chunk.
+        const int any_bad = __syncthreads_or(bad ? 1 : 0);
+        if (t < 8) {
+            const int j = (int)t;
+            const bool is_max = (j == 0 || j == 1 || j == 2 || j == 7);
+            const float best = block_best(j);
+            const uint32_t c = sh_cm[j];
+            rec[j] = (c != 0xFFFFFFFFu) ? pack_key(is_max ? best : -best, (uint32_t)(al + (uint64_t)c * CH + 1u - lo))
+                                        : 0ull;
+        } else if (t == 8) {
+            rec[8] = any_bad ? 1ull : 0ull;
+        }
+        __syncthreads();
+    } else {
+        // The holders in that chunk queue (chunk, key, thread) requests and
+        // the whole block serves them: each request reloads the 2G points
+        // the thread read in the chunk, so most blocks pay one memory round
+        // trip here however the holders are spread over waves and keys.
+        static_assert(BLOCK == 256, "a request packs the thread index into 8 bits");
+        __shared__ uint32_t sh_q[8 * BLOCK];
+        __shared__ uint32_t sh_n;
+        __shared__ uint32_t sh_lo[8];
+        if (t == 0) sh_n = 0;
+        if (t < 8) sh_lo[t] = 0xFFFFFFFFu;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (grp[j] != sh_cm[j]) holdm &= ~(1u << j);
+        if (holdm) {
+            uint32_t slot = atomicAdd(&sh_n, (uint32_t)__builtin_popcount(holdm));
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (holdm & (1u << j)) sh_q[slot++] = (grp[j] << 11) | ((uint32_t)j << 8) | t;
+        }
+        __syncthreads();
+        const uint32_t nreq = sh_n;
+        for (uint32_t r = t; r < nreq; r += BLOCK) {
+            const uint32_t e = sh_q[r];
+            const uint32_t tt = e & 0xFFu;
+            const int j = (int)((e >> 8) & 7u);
+            const uint64_t cb = al + (uint64_t)(e >> 11) * CH;
+            const float best = block_best(j);
             float2 q[2 * G];
 #pragma unroll
             for (uint32_t k = 0; k < 2 * G; ++k) {
-                const uint64_t g = cb + 2u * ((k >> 1) * BLOCK + t) + (k & 1u);
+                const uint64_t g = cb + 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
                 q[k] = (g >= lo && g < hi) ? pts[g] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
             }
-            // ascending point order: the first match is the lowest index
+            // descending point order: the last match kept is the lowest index
+            uint32_t cand = 0xFFFFFFFFu;
 #pragma unroll
             for (int k = 2 * G - 1; k >= 0; --k) {
-                const uint64_t g = cb + 2u * (((uint32_t)k >> 1) * BLOCK + t) + ((uint32_t)k & 1u);
-                if (key_of(j, q[k].x, q[k].y) == best) cand = (uint32_t)(g - lo);
+                const uint64_t g = cb + 2u * (((uint32_t)k >> 1) * BLOCK + tt) + ((uint32_t)k & 1u);
+                if (key_select(j, q[k].x, q[k].y) == best) cand = (uint32_t)(g - lo);
             }
+            if (cand != 0xFFFFFFFFu) atomicMin(&sh_lo[j], cand);
         }
-        cand = wave_min_u32(cand);
-        if (lane == 0) sh_i[j][wave] = cand;
-    }
-    const int any_bad = __syncthreads_or(bad ? 1 : 0);
-    if (t < 8) {
-        const int j = (int)t;
-        const bool is_max = (j == 0 || j == 1 || j == 2 || j == 7);
-        float best = sh_v[j][0];
-        uint32_t idx = sh_i[j][0];
-        for (int w = 1; w < NW; ++w) {
-            best = is_max ? fmaxf(best, sh_v[j][w]) : fminf(best, sh_v[j][w]);
-            idx = min(idx, sh_i[j][w]);
+        const int any_bad = __syncthreads_or(bad ? 1 : 0);
+        if (t < 8) {
+            const int j = (int)t;
+            const bool is_max = (j == 0 || j == 1 || j == 2 || j == 7);
+            const float best = block_best(j);
+            const uint32_t idx = sh_lo[j];
+            rec[j] = (idx != 0xFFFFFFFFu) ? pack_key(is_max ? best : -best, idx) : 0ull;
+        } else if (t == 8) {
+            rec[8] = any_bad ? 1ull : 0ull;
         }
-        rec[j] = (idx != 0xFFFFFFFFu) ? pack_key(is_max ? best : -best, idx) : 0ull;
-    } else if (t == 8) {
-        rec[8] = any_bad ? 1ull : 0ull;
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -406,10 +470,12 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
 // Executed by all 64 lanes of one wave; lane l works on vertex/edge l & 7,
 // and lanes 0..31 check one (edge, box corner) pair each.
 // `p` is the merged packed key of direction lane & 7 (0 if none), `nf` the
-// merged NaN flag.
+// merged NaN flag; `known`, if not null, holds the 8 vertices' coordinates
+// (else they are read from pts).
 // Returns the status it wrote (0 ok, 1 non-finite, 3 internal), uniform.
 __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uint64_t lo, uint64_t n,
-                                             unsigned long long p, uint32_t nf, Octagon* o) {
+                                             unsigned long long p, uint32_t nf, Octagon* o,
+                                             const float2* known = nullptr) {
 #pragma clang fp contract(off)
     const uint32_t lane = lane_id();
     const int j = (int)(lane & 7u);
@@ -426,11 +492,12 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
         o->byl = kInfF;
         o->byh = -kInfF;
     }
-    if (__ballot(miss) != 0ull) {   // no candidate for some direction: never expected
-        if (lane == 0) o->status = 3;
-        return 3;
+    if (__ballot(miss) != 0ull) {   // no candidate for some direction: only if NaN hid every point
+        const int st = nf ? 1 : 3;
+        if (lane == 0) o->status = st;
+        return st;
     }
-    const float2 q = pts[lo + id];
+    const float2 q = known ? known[j] : pts[lo + id];
     const float vx = q.x, vy = q.y;
     // bounding box: E0 max x, E4 min x, E2 max y, E6 min y
     const float xmax = __shfl(vx, 0, 64), xmin = __shfl(vx, 4, 64);
@@ -665,9 +732,9 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
             if (fast) {
                 const float mn0 = edge_min(ok, q[j].x, q[j].y);
                 const float mn1 = edge_min(ok, q[j].z, q[j].w);
-                k2 = (need0 & (mn0 < -1.0f) ? 1u : 0u) | (need1 & (mn1 < -1.0f) ? 2u : 0u);
-                p2 = (need0 & !(mn0 < -1.0f) & !(mn0 > 2.0f) ? 1u : 0u) |
-                     (need1 & !(mn1 < -1.0f) & !(mn1 > 2.0f) ? 2u : 0u);
+                k2 = ((need0 & (mn0 < -1.0f)) ? 1u : 0u) | ((need1 & (mn1 < -1.0f)) ? 2u : 0u);
+                p2 = ((need0 & !(mn0 < -1.0f) & !(mn0 > 2.0f)) ? 1u : 0u) |
+                     ((need1 & !(mn1 < -1.0f) & !(mn1 > 2.0f)) ? 2u : 0u);
             } else {
                 p2 = (need0 ? 1u : 0u) | (need1 ? 2u : 0u);
             }
@@ -700,6 +767,7 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
 
 constexpr int kRBlock = 256;
 constexpr int kRG = 4;   // pairs per thread per chunk: 8 points
+constexpr uint32_t kRChunk = kRBlock * kRG * 2;
 
 // One point set, pass 1.  Every block writes its packed candidates to its
 // own partial record with plain stores.  There is deliberately no
@@ -713,26 +781,92 @@ __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
     constexpr uint32_t CH = kRBlock * kRG * 2;
     const uint32_t nch = (uint32_t)((n + CH - 1) / CH);
     __shared__ unsigned long long rec[9];
-    reduce_points<kRBlock, kRG, VEC4>(pts, 0, n, 0, blockIdx.x, gridDim.x, nch, rec, box);
-    if (threadIdx.x < 9) part[(uint64_t)blockIdx.x * 9 + threadIdx.x] = rec[threadIdx.x];
+    reduce_points<kRBlock, kRG, VEC4, true>(pts, 0, n, 0, blockIdx.x, gridDim.x, nch, rec, box);
+    if (threadIdx.x < 9) part[(uint64_t)threadIdx.x * kReduceMaxGrid + blockIdx.x] = rec[threadIdx.x];
 }
 
-// One point set, pass 2 (one block of 256 threads): merge the `nblocks`
-// partial records (max per direction, OR of the NaN flags), then build the
-// octagon with wave 0.
-__global__ __launch_bounds__(256) void k_setup(const float2* __restrict__ pts, uint64_t n, Octagon* oct,
-                                               const unsigned long long* __restrict__ part,
-                                               uint32_t nblocks) {
-    __shared__ unsigned long long sh_m[9][4];
+// Inverse of ordered_bits (for a value it produced).
+__device__ __forceinline__ float from_ordered(uint32_t o) {
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+// The lowest index (relative to lo) in [lo, hi) of a point of chunk
+// position p (first point lo + p - 1, kRChunk points) whose key j equals
+// `best`, or 0xFFFFFFFF; one wave, every lane gets the result, and the
+// lane that found it stores the point to *pt.  The window scanned starts at
+// the chunk's first point in range and may run one point past the chunk:
+// the lowest index attaining `best` lies in the chunk, so the first match in
+// the window is still that index.
+__device__ __forceinline__ uint32_t scan_chunk(const float2* __restrict__ pts, uint64_t lo, uint64_t hi,
+                                               uint32_t p, int j, float best, float2* pt) {
+    constexpr uint32_t K = kRChunk / 64;
+    const uint32_t lane = lane_id();
+    // wave-uniform window [st, st + w) as a buffer: loads past w return 0
+    // without a branch or an access, and are masked to NaN, which equals no key
+    const uint64_t st = uniform_u64(lo + (uint64_t)max(p, 1u) - 1u);
+    const uint32_t w = uniform_u32(st < hi ? (uint32_t)min<uint64_t>(hi - st, kRChunk) : 0u);
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(pts + st, 8u * w);
+    float2 q[K];
+#pragma unroll
+    for (uint32_t i = 0; i < K; ++i) {
+        const uint32_t e = lane + 64u * i;
+        const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(8u * e), 0, 0);
+        q[i] = (e < w) ? make_float2(__uint_as_float(a.x), __uint_as_float(a.y))
+                       : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    }
+    uint32_t cand = 0xFFFFFFFFu;
+    float2 qc = make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int i = (int)K - 1; i >= 0; --i)
+        if (key_select(j, q[i].x, q[i].y) == best) {
+            cand = (uint32_t)(st + lane + 64u * (uint32_t)i - lo);
+            qc = q[i];
+        }
+    const uint32_t lowest = wave_min_u32(cand);
+    if (lowest != 0xFFFFFFFFu && cand == lowest) *pt = qc;
+    return lowest;
+}
+
+// One point set, pass 2 (one block of 8 waves): merge the `nblocks` partial
+// records (max per direction, OR of the NaN flags); wave j then finds the
+// lowest index attaining E_j in the chunk that won direction j, and wave 0
+// builds the octagon.
+constexpr int kSetupBlock = 512;
+__global__ __launch_bounds__(kSetupBlock) void k_setup(const float2* __restrict__ pts, uint64_t n, Octagon* oct,
+                                                       const unsigned long long* __restrict__ part,
+                                                       uint32_t nblocks) {
+    constexpr int NW = kSetupBlock / 64;
+    static_assert(NW == 8, "one wave per direction");
+    __shared__ unsigned long long sh_m[9][NW];
+    __shared__ unsigned long long sh_k[8];
+    __shared__ float2 sh_pt[8];
     const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
     unsigned long long m[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) m[j] = 0ull;
-    for (uint32_t b = t; b < nblocks; b += 256) {
+    // Records are direction-major (part[j * kReduceMaxGrid + block]): thread
+    // t reads blocks 4t..4t+3 of every direction as two 16-byte loads, all
+    // issued before any is used (one memory round trip for 2048 blocks).
+    // Words past nblocks (stale records of earlier launches) are replaced
+    // by 0, the identity of both the maximum and the OR.
+    static_assert(kReduceMaxGrid % (4 * kSetupBlock) == 0, "whole rounds of records");
+    const uint32_t rounds = (nblocks + 4u * kSetupBlock - 1u) / (4u * kSetupBlock);
+    for (uint32_t r = 0; r < rounds; ++r) {
+        const uint32_t b0 = 4u * (r * kSetupBlock + t);
+        ulonglong2 w[9][2];
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            const unsigned long long v = part[(uint64_t)b * 9 + j];
-            m[j] = (j == 8) ? (m[j] | v) : max(m[j], v);
+            const ulonglong2* src = reinterpret_cast<const ulonglong2*>(part + (uint64_t)j * kReduceMaxGrid + b0);
+            w[j][0] = src[0];
+            w[j][1] = src[1];
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const unsigned long long e0 = (b0 + 0u < nblocks) ? w[j][0].x : 0ull;
+            const unsigned long long e1 = (b0 + 1u < nblocks) ? w[j][0].y : 0ull;
+            const unsigned long long e2 = (b0 + 2u < nblocks) ? w[j][1].x : 0ull;
+            const unsigned long long e3 = (b0 + 3u < nblocks) ? w[j][1].y : 0ull;
+            m[j] = (j == 8) ? (m[j] | e0 | e1 | e2 | e3) : max(max(m[j], max(e0, e1)), max(e2, e3));
         }
     }
 #pragma unroll
@@ -748,14 +882,24 @@ __global__ __launch_bounds__(256) void k_setup(const float2* __restrict__ pts, u
         if (lane == 0) sh_m[j][wave] = v;
     }
     __syncthreads();
-    if (t < 64) {
-        const uint32_t j = lane & 7u;
-        unsigned long long key = 0ull, nf = 0ull;
-        for (int w = 0; w < 4; ++w) {
-            key = max(key, sh_m[j][w]);
-            nf |= sh_m[8][w];
+    {
+        const int j = (int)wave;
+        unsigned long long key = 0ull;
+        for (int w = 0; w < NW; ++w) key = max(key, sh_m[j][w]);
+        unsigned long long res = 0ull;
+        if (key != 0ull) {
+            const bool is_max = (j == 0 || j == 1 || j == 2 || j == 7);
+            const float kv = from_ordered((uint32_t)(key >> 32));
+            const uint32_t idx = scan_chunk(pts, 0, n, unpack_idx(key), j, is_max ? kv : -kv, &sh_pt[j]);
+            if (idx != 0xFFFFFFFFu) res = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - idx);
         }
-        (void)setup_octagon(pts, 0, n, key, (uint32_t)nf, oct);
+        if (lane == 0) sh_k[j] = res;
+    }
+    __syncthreads();
+    if (t < 64) {
+        unsigned long long nf = 0ull;
+        for (int w = 0; w < NW; ++w) nf |= sh_m[8][w];
+        (void)setup_octagon(pts, 0, n, sh_k[lane & 7u], (uint32_t)nf, oct, sh_pt);
     }
 }
 
@@ -1177,7 +1321,7 @@ __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
         const uint64_t b = sets[s].begin, n = sets[s].n;
         const uint64_t tb = (b & ~1ull) + (uint64_t)(r - sets[s].r_tile0) * kBatchRT;
         __shared__ unsigned long long rec[9];
-        reduce_points<kRBlock, kRG, VEC4>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec, nullptr);
+        reduce_points<kRBlock, kRG, VEC4, false>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec, nullptr);
         if (threadIdx.x < 9) part[(uint64_t)r * 9 + threadIdx.x] = rec[threadIdx.x];
     }
 }
@@ -1358,7 +1502,7 @@ bool is_vec4(const float2* p) { return ((uintptr_t)p & 15u) == 0u; }
 // launchers
 // ---------------------------------------------------------------------------
 
-uint32_t reduce_chunk_points() { return kRBlock * kRG * 2; }
+uint32_t reduce_chunk_points() { return kRChunk; }
 
 bool shape_supported(Shape s) {
     return (s.block == 256 || s.block == 512) && (s.ppt == 8 || s.ppt == 16);
@@ -1366,6 +1510,7 @@ bool shape_supported(Shape s) {
 
 hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, float4* box, int grid,
                          hipStream_t stream) {
+    if (grid < 1 || grid > kReduceMaxGrid) return hipErrorInvalidValue;
     if (is_vec4(pts))
         hipLaunchKernelGGL(k_reduce<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part, box);
     else
@@ -1375,7 +1520,8 @@ hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part
 
 hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsigned long long* part,
                         uint32_t nblocks, hipStream_t stream) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, stream, pts, n, oct, part, nblocks);
+    if (nblocks < 1 || nblocks > (uint32_t)kReduceMaxGrid) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupBlock), 0, stream, pts, n, oct, part, nblocks);
     return hipGetLastError();
 }
 

@@ -113,6 +113,29 @@ def test_nonfinite_set_is_isolated(ctx, torch_dev):
         assert int(cn[s]) == want.size and np.array_equal(sv[a:a + want.size], want)
 
 
+def test_all_nan_and_tied_sets(ctx, torch_dev):
+    """A set of NaN only is reported non-finite; sets whose extremes tie at
+    many positions (equal points, a grid) keep exact survivors."""
+    pts, off = _mixed_batch(6, 30)
+    big = [s for s in range(30) if off[s + 1] - off[s] > 3000][:3]
+    pts = pts.copy()
+    a, b = int(off[big[0]]), int(off[big[0] + 1])
+    pts[a:b] = np.nan
+    a, b = int(off[big[1]]), int(off[big[1] + 1])
+    pts[a:b] = (2.5, -1.0)
+    a, b = int(off[big[2]]), int(off[big[2] + 1])
+    g = np.arange(b - a)
+    pts[a:b, 0], pts[a:b, 1] = g % 37, g // 37
+    sv, cn = _run(ctx, torch_dev, pts, off)
+    assert int(cn[big[0]]) == hullf.COUNT_NONFINITE
+    for s in range(30):
+        if s == big[0]:
+            continue
+        a, b = int(off[s]), int(off[s + 1])
+        want = oracle.survivors(pts[a:b]) if b > a else np.zeros(0, np.uint32)
+        assert int(cn[s]) == want.size and np.array_equal(sv[a:a + want.size], want), s
+
+
 def test_bad_offsets_are_reported(ctx, torch_dev):
     pts, off = _mixed_batch(5, 10)
     off = off.copy()

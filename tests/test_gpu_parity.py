@@ -66,6 +66,39 @@ def test_small_and_ragged_sizes(ctx, torch_dev, n):
         _check_all(ctx, torch_dev, xy, f"{kind} n={n}")
 
 
+def _tie_set(n: int, seed: int) -> np.ndarray:
+    """A normal cloud folded to x <= 0 in which every extreme is attained at
+    300 positions spread over the whole array: max x = 0 by planted +0 and
+    -0, the other seven by planted copies of four far points."""
+    rng = np.random.default_rng(seed)
+    xy = workloads.normal(n, seed)
+    xy[:, 0] = -np.abs(xy[:, 0])
+    k = 300
+    pos = rng.choice(n, 5 * k, replace=False).reshape(5, k)
+    xy[pos[0], 0] = np.where(np.arange(k) % 2 == 0, np.float32(0.0), np.float32(-0.0))
+    xy[pos[1]] = (-3.0, 12.0)
+    xy[pos[2]] = (-12.0, -12.0)
+    xy[pos[3]] = (-14.0, 1.0)
+    xy[pos[4]] = (-1.0, -13.0)
+    return xy
+
+
+@pytest.mark.parametrize("n", [300_007, 9_000_011])
+def test_extreme_ties_take_lowest_index(ctx, torch_dev, n):
+    # 9e6 points: more chunks than reduction blocks, so a block meets the
+    # tied values in several chunks and many blocks tie with each other
+    _check_all(ctx, torch_dev, _tie_set(n, 31), f"ties n={n}")
+
+
+def test_all_nan_is_nonfinite(ctx, torch_dev):
+    t = upload(np.full((50_001, 2), np.nan, np.float32), torch_dev)
+    surv, count = ctx.hull_filter(t)
+    assert (int(count.item()) & ((1 << 64) - 1)) == hullf.COUNT_NONFINITE
+    with pytest.raises(hullf.HullfError) as e:
+        ctx.octagon(t)
+    assert e.value.status == hullf.ENONFINITE
+
+
 def test_misaligned_pointer(ctx, torch_dev):
     xy = workloads.displaced(100001, 5)
     _check_all(ctx, torch_dev, xy, "displaced misaligned", offset=1)
