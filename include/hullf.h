@@ -82,8 +82,16 @@ typedef enum {
 #define HULLF_COUNT_INTERNAL (UINT64_MAX - 2)
 
 /* Create a context on HIP device `device`; it owns the scratch memory
- * (look-back tile status, reduction slots, octagon record, survivor staging)
- * and the tuned launch shapes.  *out is set only on HULLF_OK. */
+ * (partial extreme records, octagon record, region-skip boxes, keep bits,
+ * survivor staging, hull-finishing buffers) and the tuned launch shapes.
+ * *out is set only on HULLF_OK.  Launch settings read from the environment
+ * at creation (all optional; results do not depend on them):
+ *   HULLF_FILTER_SHAPE=block,ppt  inside-test shape (256|512, 8|16)
+ *   HULLF_REGION_SKIP=0           no region skip (every group is read)
+ *   HULLF_CLASSIFY_PER_CU=k       inside-test blocks per compute unit
+ *   HULLF_COMPACT_BLOCK=b         compaction block size (256|512|1024)
+ *   HULLF_REDUCE_GRID=g           reduction blocks, 1..4096 (default 8 per CU)
+ *   HULLF_FINISH=host             hull finishing always on the host */
 hullf_status hullf_create(int device, hullf_ctx_t *out);
 
 /* Release the context and its device memory.  NULL is ignored. */

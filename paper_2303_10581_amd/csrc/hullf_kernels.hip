@@ -271,6 +271,21 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
 #pragma unroll
     for (int j = 0; j < 8; ++j) grp[j] = c0;
     bool bad = false;
+    // Boxes of this wave's chunks, lane k holding the k-th chunk it read,
+    // stored 64 at a time: a store per chunk would make the next chunk's
+    // loads wait for its write acknowledgement (vector loads and stores
+    // share one completion counter).
+    const uint32_t wv = t >> 6;
+    float4 bacc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint32_t nb = 0, cfirst = c0;
+    auto put_box = [&](uint32_t c, float4 b) {
+        if (lane_id() == nb) bacc = b;
+        if (++nb == 64u) {
+            box[(uint64_t)(cfirst + lane_id() * cstep) * NW + wv] = bacc;
+            nb = 0;
+            cfirst = c + cstep;
+        }
+    };
 
     for (uint32_t c = c0; c < nch; c += cstep) {
         const uint64_t cb = al + (uint64_t)c * CH;
@@ -309,12 +324,12 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
             if (box) {
                 const float b0 = wave_minmax_dpp<false>(m4), b1 = wave_minmax_dpp<true>(m0);
                 const float b2 = wave_minmax_dpp<false>(m6), b3 = wave_minmax_dpp<true>(m2);
-                if (lane_id() == 0) box[(uint64_t)c * NW + (t >> 6)] = make_float4(b0, b1, b2, b3);
+                put_box(c, make_float4(b0, b1, b2, b3));
             }
         } else {
-            if (box && lane_id() == 0) {
+            if (box) {
                 const float qn = __builtin_nanf("");
-                box[(uint64_t)c * NW + (t >> 6)] = make_float4(qn, qn, qn, qn);
+                put_box(c, make_float4(qn, qn, qn, qn));
             }
             const RangeView rv = range_view(pts, cb, CH, lo, hi);
             const uint32_t tt = opaque_tid();
@@ -338,6 +353,8 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
             }
         }
     }
+
+    if (box && nb != 0u && lane_id() < nb) box[(uint64_t)(cfirst + lane_id() * cstep) * NW + wv] = bacc;
 
     // Block best per key.
     const uint32_t lane = lane_id(), wave = t >> 6;

@@ -75,6 +75,7 @@ struct hullf_ctx {
     bool host_finish = false;              // hull finishing always on the host
     int classify_per_cu = 0;               // classify blocks per CU (0: what occupancy allows)
     int compact_block = 512;               // threads per compaction block
+    int reduce_grid_max = 0;               // reduction blocks (0: 8 per CU)
     uint64_t* bits = nullptr;              // keep bits, 2 words per 128 points
     uint64_t bits_cap = 0;
     uint32_t* blkcnt = nullptr;            // kMaxBlocks survivor counts
@@ -200,7 +201,8 @@ hipError_t timed(hullf_ctx* c, int kind, hipStream_t s, F launch) {
 int reduce_grid(const hullf_ctx* c, uint64_t n) {
     const uint64_t ch = reduce_chunk_points();
     const uint64_t nch = (n + ch - 1) / ch;
-    const uint64_t g = std::min<uint64_t>((uint64_t)c->cus * 8, (uint64_t)kReduceMaxGrid);
+    const uint64_t want = c->reduce_grid_max > 0 ? (uint64_t)c->reduce_grid_max : (uint64_t)c->cus * 8;
+    const uint64_t g = std::min<uint64_t>(want, (uint64_t)kReduceMaxGrid);
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(nch, g));
 }
 
@@ -476,6 +478,7 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
     if (const char* e = std::getenv("HULLF_FINISH")) c->host_finish = std::strcmp(e, "host") == 0;
     if (const char* e = std::getenv("HULLF_REGION_SKIP")) c->region_skip = std::atoi(e) != 0;
     if (const char* e = std::getenv("HULLF_CLASSIFY_PER_CU")) c->classify_per_cu = std::max(0, std::atoi(e));
+    if (const char* e = std::getenv("HULLF_REDUCE_GRID")) c->reduce_grid_max = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("HULLF_COMPACT_BLOCK")) {
         const int b = std::atoi(e);
         if (b == 256 || b == 512 || b == 1024) c->compact_block = b;

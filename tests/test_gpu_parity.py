@@ -188,6 +188,23 @@ def test_region_skip_with_scattered_near_edge_points(ctx, torch_dev, kind):
     _check_all(ctx, torch_dev, xy, "scattered near-edge " + kind, hull=False)
 
 
+@pytest.mark.parametrize("grid", [1, 7, 64])
+def test_small_reduce_grid(torch_dev, monkeypatch, grid):
+    """Few reduction blocks: every wave reads many chunks (its region-skip
+    boxes are written 64 at a time), and k_setup merges few records."""
+    monkeypatch.setenv("HULLF_REDUCE_GRID", str(grid))
+    c = hullf.Context(0)
+    try:
+        base = cases.named_sets(2_000_003, 41)["normal"]
+        xy = cases.with_near_edge_points(base, oracle.extremes, per_edge=200, seed=13)
+        xy = xy[np.random.default_rng(7).permutation(xy.shape[0])]
+        _check_all(c, torch_dev, xy, f"reduce grid {grid}", hull=False)
+        read, total = c.skip_stats()
+        assert 0 < read < total, (read, total)
+    finally:
+        c.close()
+
+
 def test_config_small_normal_1e6(ctx, torch_dev):
     xy = workloads.normal(1_000_000, 1)
     _check_all(ctx, torch_dev, xy, "normal 1e6 seed 1")
