@@ -1056,7 +1056,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
 
 
 // Survivors of one span: (w0, w1) are this lane's group words (lane = group),
-// written in ascending order to out[base ...] through the wave's LDS stage.
+// written in ascending order to out[base ...] through the wave's LDS stage;
+// a span whose 64 groups are all full is stored directly.
 __device__ __forceinline__ void compact_span(unsigned long long w0, unsigned long long w1, uint64_t sb,
                                              uint64_t base, uint64_t cap, uint32_t idx_shift,
                                              uint32_t* __restrict__ out, uint32_t* stage) {
@@ -1072,6 +1073,24 @@ __device__ __forceinline__ void compact_span(unsigned long long w0, unsigned lon
     const uint64_t room = cap > base ? cap - base : 0ull;
     const uint32_t lim = room < (uint64_t)kSpan ? (uint32_t)room : kSpan;
     const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + base, 4u * lim);
+    if (__ballot(c == 128u) == ~0ull && lim == kSpan) {
+        // every group full: the survivors are the kSpan consecutive indices
+        // from sb, stored as h single words up to a 16-byte boundary, then
+        // aligned 16-byte quads, then the remaining words
+        const uint32_t i0 = (uint32_t)sb - idx_shift;
+        const uint32_t h = (uint32_t)((16u - ((uint32_t)reinterpret_cast<uintptr_t>(out + base) & 15u)) & 15u) >> 2;
+        if (lane < h) __builtin_amdgcn_raw_buffer_store_b32(i0 + lane, ro, (int)(4u * lane), 0, kAuxStore);
+        const uint32_t nq = (kSpan - h) >> 2;
+        for (uint32_t u = lane; u < nq; u += 64u) {
+            const uint32_t q = i0 + h + 4u * u;
+            __builtin_amdgcn_raw_buffer_store_b128((u32x4){q, q + 1u, q + 2u, q + 3u}, ro, (int)(4u * (h + 4u * u)),
+                                                   0, kAuxStore);
+        }
+        const uint32_t t0 = h + 4u * nq;
+        if (t0 + lane < kSpan)
+            __builtin_amdgcn_raw_buffer_store_b32(i0 + t0 + lane, ro, (int)(4u * (t0 + lane)), 0, kAuxStore);
+        return;
+    }
     unsigned long long live = __ballot(c != 0u);
     while (live) {
         const uint32_t g = (uint32_t)__builtin_ctzll(live);

@@ -136,6 +136,17 @@ def test_all_nan_and_tied_sets(ctx, torch_dev):
         assert int(cn[s]) == want.size and np.array_equal(sv[a:a + want.size], want), s
 
 
+def test_dense_sets_at_odd_offsets(ctx, torch_dev):
+    """Circle sets (nearly every point survives) starting at odd offsets:
+    their dense spans are stored at every output alignment."""
+    parts = [workloads.circle(n, 70 + n % 7) for n in (1, 3, 40_001, 2, 70_003, 5, 33_333)]
+    off = np.zeros(len(parts) + 1, np.uint64)
+    off[1:] = np.cumsum([p.shape[0] for p in parts])
+    pts = np.concatenate(parts, axis=0)
+    sv, cn = _run(ctx, torch_dev, pts, off)
+    _check(pts, off, sv, cn, "dense sets at odd offsets")
+
+
 def test_bad_offsets_are_reported(ctx, torch_dev):
     pts, off = _mixed_batch(5, 10)
     off = off.copy()

@@ -205,6 +205,16 @@ def test_small_reduce_grid(torch_dev, monkeypatch, grid):
         c.close()
 
 
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 5])
+def test_dense_spans_at_every_output_alignment(ctx, torch_dev, k):
+    """Points on a circle survive, so spans of 8192 of them are stored as
+    runs of consecutive indices; k centre points at the front (discarded)
+    shift every run's output offset, covering each 16-byte alignment."""
+    ring = workloads.circle(100_003, 53)
+    xy = np.concatenate([np.zeros((k, 2), np.float32), ring], axis=0)
+    _check_all(ctx, torch_dev, xy, f"dense spans, {k} centre points", hull=False)
+
+
 def test_config_small_normal_1e6(ctx, torch_dev):
     xy = workloads.normal(1_000_000, 1)
     _check_all(ctx, torch_dev, xy, "normal 1e6 seed 1")
