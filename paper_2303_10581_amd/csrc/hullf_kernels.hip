@@ -733,6 +733,7 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
     const uint32_t t = threadIdx.x;
     OctagonK* ok = as_const(o);
     if (ok->mode == 0) return validm;
+    if (__ballot(validm != 0u) == 0ull) return 0u;   // every group of the wave skipped
     uint32_t keepm = 0, pendm = 0;
     const float bxl = ok->bxl, bxh = ok->bxh, byl = ok->byl, byh = ok->byh;
     const bool fast = ok->fast != 0;
@@ -998,6 +999,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     const uint64_t nwords = (4 * ((n + 2047) / 2048) + 63) / 64;
     unsigned long long wpre = 0ull;
     if (skipbits && w0 + lane < nwords && ((w0 + lane) << 15) < r1) wpre = skipbits[w0 + lane];
+    // Wait for it here, once: a first use inside the loop would make the
+    // compiler drain the whole vector-memory counter there on every
+    // iteration (it cannot tell this load from the loop's own), and with
+    // it the previous sub-tile's keep-bit stores.
+    asm volatile("" ::"v"(wpre));
     uint32_t total = 0, groups = 0;
     for (uint64_t sb = r0; sb < r1; sb += ST) {
         uint32_t skipm = 0;
@@ -1019,15 +1025,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
         // lane j keeps the two ballots of pair slot j, then all NP groups
         // of this wave are stored by one instruction
         unsigned long long m0 = 0ull, m1 = 0ull;
+        if (__ballot(k != 0u) != 0ull) {   // else the wave kept nothing: zero words
 #pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
-            const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
-            if (lane == (uint32_t)j) {
-                m0 = b0;
-                m1 = b1;
+            for (int j = 0; j < NP; ++j) {
+                const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
+                const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
+                if (lane == (uint32_t)j) {
+                    m0 = b0;
+                    m1 = b1;
+                }
+                total += (uint32_t)(__popcll(b0) + __popcll(b1));
             }
-            total += (uint32_t)(__popcll(b0) + __popcll(b1));
         }
         const uint64_t g = (sb >> 7) + (uint64_t)(lane * NW + wave);
         if (lane < (uint32_t)NP && g < ngroups) {
@@ -1435,15 +1443,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
                 const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, b, hi, sb, q);
                 const uint32_t k = classify_sub<BLOCK, PPT>(o, pts, sb, q, validm);
                 unsigned long long m0 = 0ull, m1 = 0ull;
+                if (__ballot(k != 0u) != 0ull) {   // else the wave kept nothing: zero words
 #pragma unroll
-                for (int j = 0; j < NP; ++j) {
-                    const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
-                    const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
-                    if (lane == (uint32_t)j) {
-                        m0 = b0;
-                        m1 = b1;
+                    for (int j = 0; j < NP; ++j) {
+                        const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
+                        const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
+                        if (lane == (uint32_t)j) {
+                            m0 = b0;
+                            m1 = b1;
+                        }
+                        total += (uint32_t)(__popcll(b0) + __popcll(b1));
                     }
-                    total += (uint32_t)(__popcll(b0) + __popcll(b1));
                 }
                 const uint32_t g = (uint32_t)((sb - r0) >> 7) + lane * NW + wave;
                 if (lane < (uint32_t)NP) {
