@@ -663,14 +663,53 @@ __device__ __forceinline__ float edge_min(OctagonK* __restrict__ o, float x, flo
     return min8(d);
 }
 
-// 1 = the point survives.  Decision-equivalent to the binary64 rule.
-__device__ __forceinline__ bool keep_point(const Octagon* __restrict__ o, float x, float y) {
+// The octagon fields of the FP32 fast paths, read once per kernel (or per
+// set) into registers: read inside the sub-tile loop they were reloaded by
+// every pair slot's branch, each reload a scalar-memory wait, and C0 copied
+// into vector registers again each time (an FMA reads one scalar operand).
+struct EdgeRegs {
+    float A[8], NB[8], C0[8];
+    float cx, cy, bxl, bxh, byl, byh;
+    int mode, fast;
+};
+__device__ __forceinline__ EdgeRegs load_edges(const Octagon* __restrict__ o) {
     OctagonK* ok = as_const(o);
-    if (ok->mode == 0) return true;
-    const bool inbox = (ok->bxl < x) & (x < ok->bxh) & (ok->byl < y) & (y < ok->byh);
+    EdgeRegs r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        r.A[e] = ok->A[e];
+        r.NB[e] = ok->NB[e];
+        // held in a vector register: the inner FMA's other scalar operand
+        // is the coefficient A or NB
+        float c = ok->C0[e];
+        asm volatile("" : "+v"(c));
+        r.C0[e] = c;
+    }
+    r.cx = ok->cx;
+    r.cy = ok->cy;
+    r.bxl = ok->bxl;
+    r.bxh = ok->bxh;
+    r.byl = ok->byl;
+    r.byh = ok->byh;
+    r.mode = ok->mode;
+    r.fast = ok->fast;
+    return r;
+}
+__device__ __forceinline__ float edge_min(const EdgeRegs& k, float x, float y) {
+    const float qx = x - k.cx, qy = y - k.cy;
+    float d[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = fmaf(k.A[e], qy, fmaf(k.NB[e], qx, k.C0[e]));
+    return min8(d);
+}
+
+// 1 = the point survives.  Decision-equivalent to the binary64 rule.
+__device__ __forceinline__ bool keep_point(const Octagon* __restrict__ o, const EdgeRegs& ek, float x, float y) {
+    if (ek.mode == 0) return true;
+    const bool inbox = (ek.bxl < x) & (x < ek.bxh) & (ek.byl < y) & (y < ek.byh);
     if (inbox) return false;
-    if (ok->fast) {
-        const float mn = edge_min(ok, x, y);
+    if (ek.fast) {
+        const float mn = edge_min(ek, x, y);
         if (mn < -1.0f) return true;
         if (mn > 2.0f) return false;
     }
@@ -727,16 +766,16 @@ __device__ __forceinline__ uint32_t load_sub(const float2* __restrict__ pts, uin
 // Points in the uncertain band are re-read by index and take the binary64
 // rule itself.
 template <int BLOCK, int PPT>
-__device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, const float2* __restrict__ pts,
-                                                 uint64_t sb, const float4 (&q)[PPT / 2], uint32_t validm) {
+__device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, const EdgeRegs& ek,
+                                                 const float2* __restrict__ pts, uint64_t sb,
+                                                 const float4 (&q)[PPT / 2], uint32_t validm) {
     constexpr int NP = PPT / 2;
     const uint32_t t = threadIdx.x;
-    OctagonK* ok = as_const(o);
-    if (ok->mode == 0) return validm;
+    if (ek.mode == 0) return validm;
     if (__ballot(validm != 0u) == 0ull) return 0u;   // every group of the wave skipped
     uint32_t keepm = 0, pendm = 0;
-    const float bxl = ok->bxl, bxh = ok->bxh, byl = ok->byl, byh = ok->byh;
-    const bool fast = ok->fast != 0;
+    const float bxl = ek.bxl, bxh = ek.bxh, byl = ek.byl, byh = ek.byh;
+    const bool fast = ek.fast != 0;
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const bool ok0 = (validm >> (2 * j)) & 1u, ok1 = (validm >> (2 * j + 1)) & 1u;
@@ -748,8 +787,8 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
         if (__ballot(need0 | need1) != 0ull) {
             uint32_t k2 = 0, p2 = 0;
             if (fast) {
-                const float mn0 = edge_min(ok, q[j].x, q[j].y);
-                const float mn1 = edge_min(ok, q[j].z, q[j].w);
+                const float mn0 = edge_min(ek, q[j].x, q[j].y);
+                const float mn1 = edge_min(ek, q[j].z, q[j].w);
                 k2 = ((need0 & (mn0 < -1.0f)) ? 1u : 0u) | ((need1 & (mn1 < -1.0f)) ? 2u : 0u);
                 p2 = ((need0 & !(mn0 < -1.0f) & !(mn0 > 2.0f)) ? 1u : 0u) |
                      ((need1 & !(mn1 < -1.0f) & !(mn1 > 2.0f)) ? 2u : 0u);
@@ -987,6 +1026,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     static_assert(NP <= 64, "one lane per pair slot stores the bits");
     __shared__ uint32_t sh_w[NW], sh_g[NW];
     if (oct->status != 0) return;
+    const EdgeRegs ek = load_edges(oct);
     const uint32_t lane = lane_id();
     const uint32_t wave = uniform_u32(threadIdx.x >> 6);   // keeps wave-derived addresses scalar
     const uint64_t r0 = (uint64_t)blockIdx.x * spans * kSpan;
@@ -1021,7 +1061,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
         groups += (uint32_t)(NP - __popc(skipm));
         float4 q[NP];
         const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q, skipm);
-        const uint32_t k = classify_sub<BLOCK, PPT>(oct, pts, sb, q, validm);
+        const uint32_t k = classify_sub<BLOCK, PPT>(oct, ek, pts, sb, q, validm);
         // lane j keeps the two ballots of pair slot j, then all NP groups
         // of this wave are stored by one instruction
         unsigned long long m0 = 0ull, m1 = 0ull;
@@ -1198,13 +1238,14 @@ template <bool VEC4>
 __global__ __launch_bounds__(256) void k_flags(const float2* __restrict__ pts, uint64_t n,
                                                const Octagon* __restrict__ oct, uint8_t* flags) {
     const bool bad = oct->status != 0;
+    const EdgeRegs ek = load_edges(oct);
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
         if (bad) {
             flags[i] = 2;
             continue;
         }
         const float2 p = pts[i];
-        flags[i] = keep_point(oct, p.x, p.y) ? 1 : 0;
+        flags[i] = keep_point(oct, ek, p.x, p.y) ? 1 : 0;
     }
 }
 
@@ -1432,6 +1473,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
         const uint32_t s = set_of(sets, S, it, true);
         const Octagon* o = &octs[s];
+        const EdgeRegs ek = load_edges(o);
         uint32_t total = 0;
         if (o->status == 0) {
             const uint64_t b = sets[s].begin, hi = b + sets[s].n;
@@ -1441,7 +1483,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
             for (uint64_t sb = r0; sb < r1; sb += ST) {
                 float4 q[NP];
                 const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, b, hi, sb, q);
-                const uint32_t k = classify_sub<BLOCK, PPT>(o, pts, sb, q, validm);
+                const uint32_t k = classify_sub<BLOCK, PPT>(o, ek, pts, sb, q, validm);
                 unsigned long long m0 = 0ull, m1 = 0ull;
                 if (__ballot(k != 0u) != 0ull) {   // else the wave kept nothing: zero words
 #pragma unroll

@@ -215,6 +215,27 @@ def test_dense_spans_at_every_output_alignment(ctx, torch_dev, k):
     _check_all(ctx, torch_dev, xy, f"dense spans, {k} centre points", hull=False)
 
 
+@pytest.mark.parametrize("shape,compact,skip,per_cu", [
+    ("256,8", "256", "1", "0"), ("256,16", "1024", "1", "5"),
+    ("512,8", "512", "0", "2"), ("512,16", "256", "0", "1"), ("512,16", "1024", "1", "0")])
+def test_launch_settings(torch_dev, monkeypatch, shape, compact, skip, per_cu):
+    """Every inside-test shape, compaction block size, region skip on and
+    off, and several blocks per compute unit give the oracle's results."""
+    for k, v in (("HULLF_FILTER_SHAPE", shape), ("HULLF_COMPACT_BLOCK", compact),
+                 ("HULLF_REGION_SKIP", skip), ("HULLF_CLASSIFY_PER_CU", per_cu)):
+        monkeypatch.setenv(k, v)
+    c = hullf.Context(0)
+    try:
+        sets = cases.named_sets(300_007, 43)
+        for kind in ("normal", "circle", "displaced", "grid"):
+            _check_all(c, torch_dev, sets[kind], f"{kind} shape {shape} compact {compact} skip {skip}", hull=False)
+        xy = cases.with_near_edge_points(sets["normal"], oracle.extremes, per_edge=500, seed=17)
+        xy = xy[np.random.default_rng(9).permutation(xy.shape[0])]
+        _check_all(c, torch_dev, xy, f"near-edge normal shape {shape}", hull=False)
+    finally:
+        c.close()
+
+
 def test_config_small_normal_1e6(ctx, torch_dev):
     xy = workloads.normal(1_000_000, 1)
     _check_all(ctx, torch_dev, xy, "normal 1e6 seed 1")
