@@ -818,6 +818,25 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
     return keepm;
 }
 
+// Keep words of a wave's NP pair slots: bit 2j+h of k (per lane) is point h
+// of slot j.  Lane j receives slot j's two ballots (word for the even points,
+// word for the odd ones); `total` (uniform) gains the number of kept points.
+template <int NP>
+__device__ __forceinline__ void keep_words(uint32_t k, unsigned long long& m0, unsigned long long& m1,
+                                           uint32_t& total) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
+        const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
+        if (lane == (uint32_t)j) {
+            m0 = b0;
+            m1 = b1;
+        }
+        total += (uint32_t)(__popcll(b0) + __popcll(b1));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // kernels: one point set
 // ---------------------------------------------------------------------------
@@ -1065,18 +1084,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
         // lane j keeps the two ballots of pair slot j, then all NP groups
         // of this wave are stored by one instruction
         unsigned long long m0 = 0ull, m1 = 0ull;
-        if (__ballot(k != 0u) != 0ull) {   // else the wave kept nothing: zero words
-#pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
-                const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
-                if (lane == (uint32_t)j) {
-                    m0 = b0;
-                    m1 = b1;
-                }
-                total += (uint32_t)(__popcll(b0) + __popcll(b1));
-            }
-        }
+        if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);   // else the wave kept nothing
         const uint64_t g = (sb >> 7) + (uint64_t)(lane * NW + wave);
         if (lane < (uint32_t)NP && g < ngroups) {
             ulonglong2 v;
@@ -1485,18 +1493,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
                 const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, b, hi, sb, q);
                 const uint32_t k = classify_sub<BLOCK, PPT>(o, ek, pts, sb, q, validm);
                 unsigned long long m0 = 0ull, m1 = 0ull;
-                if (__ballot(k != 0u) != 0ull) {   // else the wave kept nothing: zero words
-#pragma unroll
-                    for (int j = 0; j < NP; ++j) {
-                        const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
-                        const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
-                        if (lane == (uint32_t)j) {
-                            m0 = b0;
-                            m1 = b1;
-                        }
-                        total += (uint32_t)(__popcll(b0) + __popcll(b1));
-                    }
-                }
+                if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);   // else the wave kept nothing
                 const uint32_t g = (uint32_t)((sb - r0) >> 7) + lane * NW + wave;
                 if (lane < (uint32_t)NP) {
                     ulonglong2 v;
