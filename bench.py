@@ -71,11 +71,11 @@ def algorithmic_bytes(n: int, survivors: int, read_frac: float = 1.0, boxes: boo
     """Bytes each kernel must move.  Reduction: 8 B/pt read (+ 16 B of
     bounding box per 512 points written for the region skip).  Inside test:
     the fraction read_frac of the points it must read (8 B/pt; the region
-    skip leaves out groups inside the discard region) and the keep bits
-    written (1 bit/pt).  Compaction: the bits read and 4 B per survivor
-    written."""
+    skip leaves out groups inside the discard region), the boxes of its
+    range read (16 B per 512 points) and the keep bits written (1 bit/pt).
+    Compaction: the bits read and 4 B per survivor written."""
     return {"reduce": 8 * n + (n // 32 if boxes else 0),
-            "filter": int(8 * n * read_frac) + n // 8,
+            "filter": int(8 * n * read_frac) + n // 8 + (n // 32 if boxes else 0),
             "compact": n // 8 + 4 * survivors}
 
 
@@ -484,7 +484,7 @@ def traffic_summary(fetch_dir, write_dir, out_path=TRAFFIC_JSON):
     kernel of the same run; the result is tagged with the kernel source hash
     so that bench.py reports it only while the kernels are unchanged."""
     def kind(name):
-        for k in ("k_reduce", "k_setup", "k_boxmap", "k_classify", "k_compact"):
+        for k in ("k_reduce", "k_setup", "k_classify", "k_compact"):
             if "::" + k in name or name.startswith(k):
                 return k
         return None

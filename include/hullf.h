@@ -198,10 +198,11 @@ hullf_status hullf_autotune_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
  * launches is bracketed by HIP events on its stream.  hullf_timing_read
  * waits for those events and returns, per kernel kind, the number of
  * launches and their summed duration in milliseconds, then clears them.
- * kinds: 0 = extremes reduction, 1 = inside test (the classify pass, or
- * the single-pass test + compaction), 2 = batched launch (plan + persistent
- * kernels), 3 = octagon set-up (merge of the reduction's per-block
- * records), 4 = compaction pass.  Arrays hold at least 5 entries. */
+ * kinds: 0 = extremes reduction, 1 = inside test (the classify pass, with
+ * its region-skip box test), 2 = batched launch (plan + persistent
+ * kernels), 3 = octagon set-up (merge of the reduction's per-block records,
+ * scan of the winning chunks), 4 = compaction pass.  Arrays hold at least
+ * 5 entries. */
 hullf_status hullf_timing_enable(hullf_ctx_t ctx, int enable);
 hullf_status hullf_timing_read(hullf_ctx_t ctx, uint64_t *launches,
                                double *total_ms);

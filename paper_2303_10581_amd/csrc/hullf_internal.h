@@ -93,16 +93,13 @@ bool shape_supported(Shape shape);
 // bits: 2 * ceil(n / 128) words; blkcnt: grid words.
 uint32_t compact_span_points();
 bool classify_shape_supported(Shape shape);
-// Region skip: launch_boxmap sets bit i of skipbits (ceil(nbox/64) words)
-// iff reduction box i lies inside the discard region of the octagon;
-// launch_classify does not read groups whose box bit is set (skipbits may be
-// null: no skipping).
-hipError_t launch_boxmap(const float4* box, uint32_t nbox, const Octagon* oct, uint64_t* skipbits,
-                         hipStream_t stream);
+// Region skip: box (nbox = box_count(n) boxes from launch_reduce, or null:
+// no skipping); launch_classify does not read groups whose reduction box
+// lies inside the discard region of the octagon.
 // loaded (may be null): incremented by the number of 128-point groups read.
 hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
-                           uint32_t* blkcnt, const uint64_t* skipbits, unsigned long long* loaded, Shape shape,
-                           int grid, hipStream_t stream);
+                           uint32_t* blkcnt, const float4* box, uint64_t nbox, unsigned long long* loaded,
+                           Shape shape, int grid, hipStream_t stream);
 // block: 256, 512 or 1024 threads (one span per wave and round).
 hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
                           const Octagon* oct, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,

@@ -998,45 +998,42 @@ constexpr uint32_t kSpan = 8192;
 constexpr uint32_t kSpanGroups = kSpan / 128;
 static_assert(kSpanGroups == 64, "one group per lane");
 
-// Region skip.  k_boxmap tests every reduction box against the octagon:
-// bit i of skipbits is set iff all four corners of box i have a binary64
+// Region skip.  Each k_classify block tests the reduction boxes of its range
+// against the octagon: a box passes iff all four corners have a binary64
 // edge value above sm[e] on every edge e -- the test the quick-accept box
 // passes in the octagon set-up, so every point in the box is discarded by
-// the rule.  k_classify then does not read groups whose box bit is set.
+// the rule.  The block then does not read groups whose box passed.
 // Group g of a set was read in the reduction by wave g % 4 of chunk g / 16:
 // its box is 4 * (g / 16) + g % 4.
 static_assert(kRBlock * kRG * 2 == 16 * 128 && kRBlock / 64 == 4, "box of group g: chunk g/16, wave g%4");
-typedef const __attribute__((address_space(4))) uint64_t SkipK;
 
-__global__ __launch_bounds__(256) void k_boxmap(const float4* __restrict__ box, uint32_t nbox,
-                                                const Octagon* __restrict__ oct, uint64_t* __restrict__ skipbits) {
-    OctagonK* ok = as_const(oct);
-    const bool on = ok->status == 0 && ok->mode == 1 && ok->skip != 0;
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    bool pass = false;
-    if (on && i < nbox) {
-        const float4 b = box[i];
-        pass = true;
+// True iff all four corners of box b have a binary64 edge value above sm[e]
+// on every edge e (false for a NaN box).
+__device__ __forceinline__ bool box_inside(float4 b, OctagonK* __restrict__ ok) {
+    bool pass = true;
+#pragma unroll 1
+    for (int e = 0; e < 8; ++e) {   // one edge's data live at a time
+        const double ax = ok->ax[e], ay = ok->ay[e], ex = ok->ex[e], ey = ok->ey[e], sm = ok->sm[e];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const double ax = ok->ax[e], ay = ok->ay[e], ex = ok->ex[e], ey = ok->ey[e], sm = ok->sm[e];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double qx = (double)((k & 1) ? b.y : b.x);
-                const double qy = (double)((k & 2) ? b.w : b.z);
-                const double D = ex * (qy - ay) - ey * (qx - ax);
-                pass = pass && (D > sm);   // false for NaN boxes
-            }
+        for (int k = 0; k < 4; ++k) {
+            const double qx = (double)((k & 1) ? b.y : b.x);
+            const double qy = (double)((k & 2) ? b.w : b.z);
+            const double D = ex * (qy - ay) - ey * (qx - ax);
+            pass = pass && (D > sm);
         }
     }
-    const unsigned long long m = __ballot(pass);
-    if (lane_id() == 0 && (uint64_t)(i & ~63u) < (uint64_t)nbox) skipbits[i >> 6] = m;
+    return pass;
 }
+
+// Skip words held per inside-test block: one bit per reduction box of the
+// block's range (64 boxes, 32768 points, per word).  A range longer than
+// kSkipWords words is not skipped past them.
+constexpr uint32_t kSkipWords = 1024;
 
 template <int BLOCK, int PPT, bool VEC4>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_classify(
     const float2* __restrict__ pts, uint64_t n, const Octagon* __restrict__ oct, uint32_t spans,
-    uint64_t* __restrict__ bits, uint32_t* __restrict__ blkcnt, const uint64_t* __restrict__ skipbits,
+    uint64_t* __restrict__ bits, uint32_t* __restrict__ blkcnt, const float4* __restrict__ box, uint64_t nbox,
     unsigned long long* loaded) {
     constexpr int NP = PPT / 2;
     constexpr int NW = BLOCK / 64;
@@ -1044,32 +1041,38 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     static_assert(kSpan % ST == 0, "sub-tiles tile a span");
     static_assert(NP <= 64, "one lane per pair slot stores the bits");
     __shared__ uint32_t sh_w[NW], sh_g[NW];
+    __shared__ unsigned long long sh_skip[kSkipWords];
     if (oct->status != 0) return;
-    const EdgeRegs ek = load_edges(oct);
     const uint32_t lane = lane_id();
     const uint32_t wave = uniform_u32(threadIdx.x >> 6);   // keeps wave-derived addresses scalar
     const uint64_t r0 = (uint64_t)blockIdx.x * spans * kSpan;
     const uint64_t r1 = min<uint64_t>(n, r0 + (uint64_t)spans * kSpan);
     const uint64_t ngroups = (n + 127) / 128;
-    SkipK* sk = (SkipK*)skipbits;
-    // skip word i covers points [i*32768, (i+1)*32768); lane l preloads word
-    // w0 + l of this block's range so that the loop does not wait on them
+    // Region skip: the block tests the reduction boxes of its own range
+    // against the octagon and keeps one bit per box in LDS (word i - w0 covers
+    // points [i*32768, (i+1)*32768)).  Each wave's 64 consecutive boxes make
+    // one ballot, so every lane of a wave takes the same loop trips.
+    OctagonK* ok = as_const(oct);
+    const bool skipon = box != nullptr && ok->mode == 1 && ok->skip != 0;
     const uint64_t w0 = r0 >> 15;
-    const uint64_t nwords = (4 * ((n + 2047) / 2048) + 63) / 64;
-    unsigned long long wpre = 0ull;
-    if (skipbits && w0 + lane < nwords && ((w0 + lane) << 15) < r1) wpre = skipbits[w0 + lane];
-    // Wait for it here, once: a first use inside the loop would make the
-    // compiler drain the whole vector-memory counter there on every
-    // iteration (it cannot tell this load from the loop's own), and with
-    // it the previous sub-tile's keep-bit stores.
-    asm volatile("" ::"v"(wpre));
+    const uint32_t nw = (uint32_t)min<uint64_t>(((r1 + 32767u) >> 15) - w0, kSkipWords);
+    if (skipon) {
+        for (uint32_t i = threadIdx.x; i < nw * 64u; i += BLOCK) {
+            const uint64_t bi = (w0 << 6) + i;
+            const bool pass = bi < nbox && box_inside(box[bi], ok);
+            const unsigned long long m = __ballot(pass);
+            if (lane == 0) sh_skip[i >> 6] = m;
+        }
+        __syncthreads();
+    }
+    const EdgeRegs ek = load_edges(oct);
     uint32_t total = 0, groups = 0;
     for (uint64_t sb = r0; sb < r1; sb += ST) {
         uint32_t skipm = 0;
-        if (sk && sb + ST <= n) {
+        const uint64_t rel = (sb >> 15) - w0;
+        if (skipon && sb + ST <= n && rel < nw) {
             // this sub-tile's boxes are 4*ST/2048 consecutive bits of one word
-            const uint64_t rel = (sb >> 15) - w0;
-            const uint64_t word = rel < 64 ? readlane_u64(wpre, (uint32_t)rel) : sk[sb >> 15];
+            const uint64_t word = sh_skip[rel];
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
                 const uint64_t gg = (sb >> 7) + (uint64_t)(j * NW) + wave;
@@ -1618,25 +1621,18 @@ bool classify_shape_supported(Shape s) {
 
 #define HULLF_CLASSIFY_SHAPES(X) X(256, 8) X(256, 16) X(512, 8) X(512, 16)
 
-hipError_t launch_boxmap(const float4* box, uint32_t nbox, const Octagon* oct, uint64_t* skipbits,
-                         hipStream_t stream) {
-    if (nbox == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_boxmap, dim3((nbox + 255) / 256), dim3(256), 0, stream, box, nbox, oct, skipbits);
-    return hipGetLastError();
-}
-
 hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
-                           uint32_t* blkcnt, const uint64_t* skipbits, unsigned long long* loaded, Shape shape,
-                           int grid, hipStream_t stream) {
+                           uint32_t* blkcnt, const float4* box, uint64_t nbox, unsigned long long* loaded,
+                           Shape shape, int grid, hipStream_t stream) {
     const bool v = is_vec4(pts);
 #define X(B, P)                                                                                           \
     if (shape.block == B && shape.ppt == P) {                                                             \
         if (v)                                                                                            \
             hipLaunchKernelGGL((k_classify<B, P, true>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
-                               bits, blkcnt, skipbits, loaded);                                           \
+                               bits, blkcnt, box, nbox, loaded);                                          \
         else                                                                                              \
             hipLaunchKernelGGL((k_classify<B, P, false>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
-                               bits, blkcnt, skipbits, loaded);                                           \
+                               bits, blkcnt, box, nbox, loaded);                                          \
         return hipGetLastError();                                                                         \
     }
     HULLF_CLASSIFY_SHAPES(X)

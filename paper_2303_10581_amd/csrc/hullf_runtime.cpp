@@ -81,8 +81,6 @@ struct hullf_ctx {
     uint32_t* blkcnt = nullptr;            // kMaxBlocks survivor counts
     float4* boxes = nullptr;               // reduction boxes (region skip), 4 per 2048 points
     uint64_t boxes_cap = 0;
-    uint64_t* skipbits = nullptr;          // one bit per box
-    uint64_t skipbits_cap = 0;
     unsigned long long* groups_read = nullptr;   // device counter of groups the inside test read
     uint64_t groups_total = 0;                   // groups it would read without the skip
     bool region_skip = true;
@@ -231,24 +229,17 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
     const int grid = (int)((nspans + spans - 1) / spans);
     CHECK_HIP(grow_device(&c->bits, &c->bits_cap, 2 * ((n + 127) / 128), s));
     float4* box = nullptr;
-    uint64_t* skipbits = nullptr;
     uint64_t nbox = 0;
     if (c->region_skip) {
         const uint64_t ch = reduce_chunk_points();
         nbox = 4 * ((n + ch - 1) / ch);
         CHECK_HIP(grow_device(&c->boxes, &c->boxes_cap, nbox, s));
-        CHECK_HIP(grow_device(&c->skipbits, &c->skipbits_cap, (nbox + 63) / 64, s));
         box = c->boxes;
-        skipbits = c->skipbits;
     }
     CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, box, rg, s); }));
-    CHECK_HIP(timed(c, 3, s, [&] {
-        hipError_t e = launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s);
-        if (e == hipSuccess && box) e = launch_boxmap(box, (uint32_t)nbox, c->oct, skipbits, s);
-        return e;
-    }));
+    CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
     CHECK_HIP(timed(c, 1, s, [&] {
-        return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, skipbits, c->groups_read, sh,
+        return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, box, nbox, c->groups_read, sh,
                                grid, s);
     }));
     c->groups_total += (n + 127) / 128;
@@ -513,7 +504,7 @@ void hullf_destroy(hullf_ctx_t c) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
-    void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt, c->boxes, c->skipbits,
+    void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt, c->boxes,
                    c->groups_read,
                    c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
