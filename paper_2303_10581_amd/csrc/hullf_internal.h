@@ -51,8 +51,7 @@ struct alignas(16) SetInfo {
 struct alignas(16) BatchTotals {
     uint32_t r_tiles;
     uint32_t f_tiles;
-    uint32_t ticket;
-    uint32_t pad;
+    uint32_t pad[2];
 };
 
 constexpr uint64_t kCountNonFinite = ~0ull;
@@ -113,10 +112,13 @@ hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t
 hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
                         SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
                         Octagon* octs, uint64_t* bits, uint32_t* blkcnt, uint32_t max_items, uint32_t* surv,
-                        uint64_t* counts, Shape shape, int cus, hipStream_t stream);
+                        uint64_t* counts, float4* box, Shape shape, int cus, hipStream_t stream);
 uint64_t batch_max_items(uint64_t n_total, uint32_t S);
 uint32_t batch_item_words();
 uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S);
+// Region-skip boxes per reduction tile (box: max_rtiles * batch_tile_boxes()
+// float4, or null for no region skip).
+uint32_t batch_tile_boxes();
 
 // Hull finishing on the device (hullf_finish.hip).
 // keys: (ordered x << 32 | ordered y), vals: point indices.  The sort needs

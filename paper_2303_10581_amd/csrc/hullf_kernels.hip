@@ -1275,20 +1275,22 @@ __global__ __launch_bounds__(256) void k_gather(const float2* __restrict__ pts,
 }
 
 // ---------------------------------------------------------------------------
-// kernels: many sets in one graph of four launches
+// kernels: many sets in one graph of five launches
 // ---------------------------------------------------------------------------
-// Sets are CSR ranges of one point array.  Launch 1 (plan, one block) cuts
-// every set into reduction tiles of kBatchRT points and compaction tiles of
-// BLOCK*PPT points (both aligned to the pair grid of the array) and computes
-// their prefix counts.  Launch 2 streams all reduction tiles and writes one
-// partial record per tile; launch 3 merges each set's records and builds its
-// octagon (one wave per set); launch 4 runs the inside test + compaction on
-// all compaction tiles from one ticket counter, with a decoupled look-back
-// per set.  Cross-block results only flow across launch boundaries, so no
-// kernel needs a device-wide fence.
+// Sets are CSR ranges of one point array (or a list of (begin, count)
+// segments).  Launch 1 (plan, one block) cuts every set into reduction tiles
+// of kBatchRT points and work items of kBatchItem points (both counted from
+// the set's pair-aligned start) and computes their prefix counts.  Launch 2
+// streams all reduction tiles and writes one partial record per tile (and
+// the tiles' region-skip boxes); launch 3 merges each set's records and
+// builds its octagon (one wave per set); launch 4 runs the inside test on
+// every work item (keep bits + one count per item) and launch 5 compacts
+// every item at its offset inside its set.  Cross-block results only flow
+// across launch boundaries, so no kernel needs a device-wide fence.
 
 constexpr uint32_t kBatchRChunks = 4;
 constexpr uint32_t kBatchRT = kRBlock * kRG * 2 * kBatchRChunks;   // reduction tile (points)
+constexpr uint32_t kBatchTileBoxes = 4 * kBatchRChunks;             // region-skip boxes per tile
 
 // Last set s with start[s] <= k (start non-decreasing, start[0] == 0).
 __device__ __forceinline__ uint32_t set_of(const SetInfo* __restrict__ sets, uint32_t S, uint32_t k, bool f) {
@@ -1370,7 +1372,6 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
         if (t == 0) {
             tot->r_tiles = 0u;
             tot->f_tiles = 0u;
-            tot->ticket = 0u;
         }
         return;
     }
@@ -1403,21 +1404,21 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
     if (t == 0) {
         tot->r_tiles = fits ? rtiles : 0u;
         tot->f_tiles = fits ? ftiles : 0u;
-        tot->ticket = 0u;
     }
 }
 
 template <bool VEC4>
 __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_batch_reduce(
     const float2* __restrict__ pts, uint32_t S, const SetInfo* __restrict__ sets,
-    const BatchTotals* __restrict__ tot, unsigned long long* __restrict__ part) {
+    const BatchTotals* __restrict__ tot, unsigned long long* __restrict__ part, float4* __restrict__ box) {
     const uint32_t rtiles = tot->r_tiles;
     for (uint32_t r = blockIdx.x; r < rtiles; r += gridDim.x) {
         const uint32_t s = set_of(sets, S, r, false);
         const uint64_t b = sets[s].begin, n = sets[s].n;
         const uint64_t tb = (b & ~1ull) + (uint64_t)(r - sets[s].r_tile0) * kBatchRT;
         __shared__ unsigned long long rec[9];
-        reduce_points<kRBlock, kRG, VEC4, false>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec, nullptr);
+        reduce_points<kRBlock, kRG, VEC4, false>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec,
+                                                 box ? box + (uint64_t)r * kBatchTileBoxes : nullptr);
         if (threadIdx.x < 9) part[(uint64_t)r * 9 + threadIdx.x] = rec[threadIdx.x];
     }
 }
@@ -1473,11 +1474,12 @@ template <int BLOCK, int PPT, bool VEC4>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_batch_classify(
     const float2* __restrict__ pts, uint32_t S, const SetInfo* __restrict__ sets,
     const Octagon* __restrict__ octs, const BatchTotals* __restrict__ tot, uint64_t* __restrict__ bits,
-    uint32_t* __restrict__ blkcnt) {
+    uint32_t* __restrict__ blkcnt, const float4* __restrict__ box) {
     constexpr int NP = PPT / 2;
     constexpr int NW = BLOCK / 64;
     constexpr uint32_t ST = BLOCK * PPT;
     static_assert(kBatchItem % ST == 0, "sub-tiles tile an item");
+    static_assert(kBatchItem / kBatchRT * kBatchTileBoxes == 64, "one skip word per item");
     __shared__ uint32_t sh_w[NW];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint32_t items = tot->f_tiles;
@@ -1488,12 +1490,38 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
         uint32_t total = 0;
         if (o->status == 0) {
             const uint64_t b = sets[s].begin, hi = b + sets[s].n;
-            const uint64_t r0 = (b & ~1ull) + (uint64_t)(it - sets[s].f_tile0) * kBatchItem;
+            const uint32_t li = it - sets[s].f_tile0;
+            const uint64_t r0 = (b & ~1ull) + (uint64_t)li * kBatchItem;
             const uint64_t r1 = min<uint64_t>(hi, r0 + kBatchItem);
             uint64_t* ib = bits + (uint64_t)it * (kBatchItem / 64);
+            // Region skip: the item's 64 groups of 512 points have the 64
+            // consecutive boxes of its four reduction tiles; lane l tests
+            // box l.  The corner test uses the FP32 edge coefficients: d > 2
+            // at a point of the bounding box means an exact edge value above
+            // 24 u M there, and edge values are affine, so every point of a
+            // box whose corners all pass is discarded by the binary64 rule.
+            unsigned long long word = 0ull;
+            if (box != nullptr && ek.mode == 1 && ek.fast) {
+                const uint32_t bl = li * 64u + lane;
+                bool pass = false;
+                if (bl < sets[s].r_tiles * kBatchTileBoxes) {
+                    const float4 bx = box[(uint64_t)sets[s].r_tile0 * kBatchTileBoxes + bl];
+                    pass = (edge_min(ek, bx.x, bx.z) > 2.0f) & (edge_min(ek, bx.y, bx.z) > 2.0f) &
+                           (edge_min(ek, bx.x, bx.w) > 2.0f) & (edge_min(ek, bx.y, bx.w) > 2.0f);
+                }
+                word = __ballot(pass);
+            }
             for (uint64_t sb = r0; sb < r1; sb += ST) {
+                uint32_t skipm = 0;
+                if (word != 0ull) {
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) {
+                        const uint32_t gg = (uint32_t)((sb - r0) >> 7) + (uint32_t)(j * NW) + wave;
+                        skipm |= (uint32_t)((word >> ((gg >> 4) * 4u + (gg & 3u))) & 1ull) << j;
+                    }
+                }
                 float4 q[NP];
-                const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, b, hi, sb, q);
+                const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, b, hi, sb, q, skipm);
                 const uint32_t k = classify_sub<BLOCK, PPT>(o, ek, pts, sb, q, validm);
                 unsigned long long m0 = 0ull, m1 = 0ull;
                 if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);   // else the wave kept nothing
@@ -1678,14 +1706,16 @@ uint32_t batch_item_words() { return kBatchItem / 64; }
 
 uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S) { return n_total / kBatchRT + 2ull * S + 1ull; }
 
+uint32_t batch_tile_boxes() { return kBatchTileBoxes; }
+
 #define HULLF_BATCH_CLASSIFY(B, P)                                                                         \
     if (shape.block == B && shape.ppt == P) {                                                              \
         if (v)                                                                                             \
             hipLaunchKernelGGL((k_batch_classify<B, P, true>), dim3(fgrid), dim3(B), 0, stream, pts, S, sets, \
-                               octs, tot, bits, blkcnt);                                                  \
+                               octs, tot, bits, blkcnt, box);                                             \
         else                                                                                               \
             hipLaunchKernelGGL((k_batch_classify<B, P, false>), dim3(fgrid), dim3(B), 0, stream, pts, S,     \
-                               sets, octs, tot, bits, blkcnt);                                            \
+                               sets, octs, tot, bits, blkcnt, box);                                       \
         e = hipGetLastError();                                                                             \
         done = true;                                                                                       \
     }
@@ -1693,7 +1723,7 @@ uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S) { return n_total / kBatc
 hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
                         SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
                         Octagon* octs, uint64_t* bits, uint32_t* blkcnt, uint32_t max_items, uint32_t* surv,
-                        uint64_t* counts, Shape shape, int cus, hipStream_t stream) {
+                        uint64_t* counts, float4* box, Shape shape, int cus, hipStream_t stream) {
     if (!shape_supported(shape)) return hipErrorInvalidValue;
     if (seg)
         hipLaunchKernelGGL(k_batch_plan<true>, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts, max_items,
@@ -1706,9 +1736,11 @@ hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32
     const bool v = is_vec4(pts);
     const int rgrid = cus * 8;
     if (v)
-        hipLaunchKernelGGL(k_batch_reduce<true>, dim3(rgrid), dim3(kRBlock), 0, stream, pts, S, sets, tot, part);
+        hipLaunchKernelGGL(k_batch_reduce<true>, dim3(rgrid), dim3(kRBlock), 0, stream, pts, S, sets, tot, part,
+                           box);
     else
-        hipLaunchKernelGGL(k_batch_reduce<false>, dim3(rgrid), dim3(kRBlock), 0, stream, pts, S, sets, tot, part);
+        hipLaunchKernelGGL(k_batch_reduce<false>, dim3(rgrid), dim3(kRBlock), 0, stream, pts, S, sets, tot, part,
+                           box);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const uint32_t sblocks = (uint32_t)std::min<uint64_t>((S + 3) / 4, (uint64_t)cus * 8);

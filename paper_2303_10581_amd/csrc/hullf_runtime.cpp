@@ -91,6 +91,8 @@ struct hullf_ctx {
     BatchTotals* b_tot = nullptr;
     unsigned long long* b_part = nullptr;
     uint64_t b_part_cap = 0;   // records (9 words each)
+    float4* b_boxes = nullptr;   // region-skip boxes, batch_tile_boxes() per record
+    uint64_t b_boxes_cap = 0;
     uint64_t* b_bits = nullptr;            // two-pass: keep bits per work item
     uint32_t* b_blkcnt = nullptr;          // two-pass: survivors per work item
     uint64_t b_items_cap = 0;
@@ -408,6 +410,10 @@ hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, hipStream_
         c->b_part_cap = words / 9;
         realloc = true;
     }
+    if (c->region_skip && (c->b_boxes_cap < c->b_part_cap * batch_tile_boxes() || !c->b_boxes)) {
+        CHECK_HIP(grow_device(&c->b_boxes, &c->b_boxes_cap, c->b_part_cap * batch_tile_boxes(), s));
+        realloc = true;
+    }
     if (realloc) drop_graphs(c);
     return HULLF_OK;
 }
@@ -419,7 +425,7 @@ hullf_status enqueue_batched(hullf_ctx* c, const hullf_pt* d_pts, const uint64_t
     CHECK_HIP(launch_batch(pts, d_off, seg, S, n_total, c->b_sets, c->b_tot, c->b_part,
                            (uint32_t)std::min<uint64_t>(c->b_part_cap, 0xFFFFFFFFull), c->b_octs, c->b_bits,
                            c->b_blkcnt, (uint32_t)std::min<uint64_t>(c->b_items_cap, 0xFFFFFFFFull), d_surv,
-                           d_counts, shape, c->cus, s));
+                           d_counts, c->region_skip ? c->b_boxes : nullptr, shape, c->cus, s));
     return HULLF_OK;
 }
 
@@ -506,7 +512,7 @@ void hullf_destroy(hullf_ctx_t c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt, c->boxes,
                    c->groups_read,
-                   c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_bits, c->b_blkcnt};
+                   c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_boxes, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* fin[] = {c->fk[0], c->fk[1], c->fk[2], c->fv[0], c->fv[1], c->fv[2], c->fchain, c->fcnt, c->fhist,

@@ -147,6 +147,34 @@ def test_dense_sets_at_odd_offsets(ctx, torch_dev):
     _check(pts, off, sv, cn, "dense sets at odd offsets")
 
 
+@pytest.mark.parametrize("skip", ["1", "0"])
+def test_region_skip_in_batches(torch_dev, monkeypatch, skip):
+    """Large normal sets (most groups skipped by the region skip) mixed with
+    sets whose near-edge points are scattered through them (their boxes must
+    not be skipped), with the region skip on and off."""
+    from tests import cases
+    monkeypatch.setenv("HULLF_REGION_SKIP", skip)
+    c = hullf.Context(0)
+    try:
+        parts = []
+        for k, n in enumerate((300_007, 5, 120_001, 70_000, 250_003)):
+            xy = workloads.normal(n, 90 + k)
+            if k % 2 == 0 and n > 1000:
+                xy = cases.with_near_edge_points(xy, oracle.extremes, per_edge=150, seed=k)
+                xy = xy[np.random.default_rng(k).permutation(xy.shape[0])]
+            parts.append(xy)
+        off = np.zeros(len(parts) + 1, np.uint64)
+        off[1:] = np.cumsum([p.shape[0] for p in parts])
+        pts = np.concatenate(parts, axis=0)
+        say(f"[gpu] batched region skip {skip}: {len(parts)} sets, {pts.shape[0]} points")
+        sv, cn = _run(c, torch_dev, pts, off)
+        _check(pts, off, sv, cn, f"region skip {skip}")
+        sv, cn = _run(c, torch_dev, pts, off, offset=1)
+        _check(pts, off, sv, cn, f"region skip {skip}, misaligned")
+    finally:
+        c.close()
+
+
 def test_bad_offsets_are_reported(ctx, torch_dev):
     pts, off = _mixed_batch(5, 10)
     off = off.copy()
