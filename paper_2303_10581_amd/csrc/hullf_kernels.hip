@@ -160,18 +160,10 @@ __device__ __forceinline__ float4 load_pair_buf(__amdgpu_buffer_rsrc_t r, uint32
 // Either way the streaming loop stays at about 8 VALU operations per point
 // instead of 24 for per-point index selects.
 
-__device__ __forceinline__ float key_of(int j, float x, float y) {
-    switch (j) {
-        case 0: case 4: return x;
-        case 1: case 5: return x + y;
-        case 2: case 6: return y;
-        default: return x - y;
-    }
-}
-
-// key_of for a j known only at run time, without branches: x + 0, 0 + y,
-// x + y and x + (-y) are exactly x, y, fl32(x+y) and fl32(x-y) (up to the
-// sign of a zero, which equality ignores).
+// The value tracked for key j (x, fl32(x+y), y or fl32(x-y); the sign is
+// applied by the caller), without branches for a j known only at run time:
+// x + 0, 0 + y, x + y and x + (-y) are exactly x, y, fl32(x+y) and
+// fl32(x-y) (up to the sign of a zero, which equality ignores).
 __device__ __forceinline__ float key_select(int j, float x, float y) {
     const int m = j & 3;
     const float a = (m == 2) ? 0.0f : x;

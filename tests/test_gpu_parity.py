@@ -169,10 +169,11 @@ def test_capacity_smaller_than_count(ctx, torch_dev):
 
 
 def test_repeated_calls_same_context(ctx, torch_dev):
-    # the reduction slots and look-back state are reset between calls
-    for seed in range(4):
+    # larger and smaller sets in turn: an earlier call's per-block records,
+    # boxes, keep bits and counts must not leak into a later one
+    for seed, n in enumerate((300_007, 30_011, 120_001, 5_003)):
         for kind in ("normal", "circle", "displaced"):
-            xy = workloads.by_kind(kind, 30011 + 977 * seed, seed)
+            xy = workloads.by_kind(kind, n, seed)
             t = upload(xy, torch_dev)
             assert np.array_equal(survivors_np(ctx, t), oracle.survivors(xy)), (kind, seed)
 
