@@ -309,13 +309,19 @@ __device__ __forceinline__ int orient_dev(float ox, float oy, float ax, float ay
 // out[c*C ...], their number to cnt[c].  dedup: skip a point whose key
 // equals its predecessor's (the first level only; later levels have no
 // repeats).
+constexpr uint32_t kChainMaxC = 256;   // a stack entry is a one-byte offset into the chunk
+
 __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys, uint32_t m, uint32_t C, int sign,
                                               int dedup, uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
+    // Each thread's stack lives in LDS as offsets into its chunk (a push or
+    // pop in global memory cost a dependent round trip each); the chain is
+    // copied to out[c*C ...] at the end.
+    __shared__ uint8_t sh_st[kChainMaxC][64];
     const uint32_t c = blockIdx.x * 64u + threadIdx.x;
     const uint32_t nch = (m + C - 1) / C;
     if (c >= nch) return;
     const uint32_t b = c * C, e = min(m, b + C);
-    uint32_t* st = out + (uint64_t)b;
+    uint8_t* st = &sh_st[0][threadIdx.x];   // entry j at st[64 * j]: lanes hit distinct banks
     uint32_t len = 0;
     float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f;   // top (2) and below-top (1) of the stack
     uint64_t prev = (b > 0) ? keys[b - 1] : 0ull;
@@ -331,17 +337,20 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
             x2 = x1;
             y2 = y1;
             if (len >= 2) {
-                const uint64_t kb = keys[st[len - 2]];
+                const uint64_t kb = keys[b + st[64u * (len - 2)]];
                 x1 = key_x(kb);
                 y1 = key_y(kb);
             }
         }
-        st[len++] = i;
+        st[64u * len] = (uint8_t)(i - b);
+        ++len;
         x1 = x2;
         y1 = y2;
         x2 = x;
         y2 = y;
     }
+    uint32_t* o = out + (uint64_t)b;
+    for (uint32_t j = 0; j < len; ++j) o[j] = b + st[64u * j];
     cnt[c] = len;
 }
 
@@ -431,6 +440,7 @@ hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, u
 
 hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, int dedup, uint32_t* chain,
                         uint32_t* cnt, hipStream_t stream) {
+    if (C == 0 || C > kChainMaxC) return hipErrorInvalidValue;
     const uint32_t nch = (m + C - 1) / C;
     hipLaunchKernelGGL(k_chain, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup, chain, cnt);
     return hipGetLastError();
