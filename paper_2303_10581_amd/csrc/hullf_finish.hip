@@ -355,28 +355,48 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
 }
 
 // Exclusive scan of n counts in place (one block of 1024); the total goes
-// to *total.
+// to *total.  Each round scans 4096 counts: 4 consecutive per thread, a
+// shuffle scan inside each wave, and one LDS exchange of the 16 wave totals.
 __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ a, uint32_t n, uint32_t* total) {
-    __shared__ uint32_t s[1024];
+    constexpr int NW = 1024 / 64;
+    __shared__ uint32_t wsum[NW];
     __shared__ uint32_t carry;
-    const uint32_t t = threadIdx.x;
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
     if (t == 0) carry = 0u;
     __syncthreads();
-    for (uint32_t b = 0; b < n; b += 1024) {
-        const uint32_t i = b + t;
-        const uint32_t v = (i < n) ? a[i] : 0u;
-        s[t] = v;
-        __syncthreads();
-        for (uint32_t o = 1; o < 1024; o <<= 1) {
-            const uint32_t u = (t >= o) ? s[t - o] : 0u;
-            __syncthreads();
-            s[t] += u;
-            __syncthreads();
+    for (uint32_t b = 0; b < n; b += 4096u) {
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = b + 4u * t + (uint32_t)q;
+            v[q] = (i < n) ? a[i] : 0u;
+            s += v[q];
         }
-        if (i < n) a[i] = carry + s[t] - v;
-        const uint32_t tot = s[1023];
+        uint32_t incl = s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+            if ((int)lane >= o) incl += u;
+        }
+        if (lane == 63u) wsum[wave] = incl;
         __syncthreads();
-        if (t == 0) carry += tot;
+        uint32_t before = carry;
+        uint32_t all = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t x = wsum[w];
+            if (w < (int)wave) before += x;
+            all += x;
+        }
+        uint32_t e = before + incl - s;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = b + 4u * t + (uint32_t)q;
+            if (i < n) a[i] = e;
+            e += v[q];
+        }
+        __syncthreads();   // every thread has read carry and wsum
+        if (t == 0) carry += all;
         __syncthreads();
     }
     if (t == 0) *total = carry;
