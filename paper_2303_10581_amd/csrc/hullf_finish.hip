@@ -152,100 +152,102 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* __restr
                                                          const uint32_t* __restrict__ hist,
                                                          uint64_t* __restrict__ kout,
                                                          uint32_t* __restrict__ vout) {
+    // Wave w ranks the tile's items [w*IW, (w+1)*IW) by itself: in each round
+    // of 64, lanes with equal digits find each other with 8 ballots, and a
+    // running count per digit in the wave's own LDS row gives every item its
+    // rank among the wave's earlier items of that digit (LDS operations of
+    // one wave take effect in program order, so no barrier is needed).  The
+    // block then turns the per-wave counts into offsets once.  Within a
+    // digit, items keep their input order: the sort is stable.
     constexpr int NW = kRsBlock / 64;
+    constexpr uint32_t IW = kRsTile / NW;   // items per wave
+    constexpr int RW = (int)(IW / 64);      // rounds per wave
+    static_assert(kRsBins == kRsBlock, "one digit per thread");
     __shared__ uint64_t sk[kRsTile];
     __shared__ uint32_t sv[kRsTile];
-    __shared__ uint32_t cnt[kRsBins];    // tile digit counts, then their exclusive scan
-    __shared__ uint32_t gpos[kRsBins];   // output position of the tile's first item per digit
-    __shared__ uint32_t run[kRsBins];    // items of each digit placed so far
-    __shared__ uint32_t wc[NW][kRsBins];
+    __shared__ uint32_t wcnt[NW][kRsBins];   // per-wave digit counts, then their offsets in the tile
+    __shared__ uint32_t tofs[kRsBins];       // tile-level exclusive digit offsets
+    __shared__ uint32_t gpos[kRsBins];       // output position of the tile's first item per digit
+    __shared__ uint32_t wsum[NW];
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6, tile = blockIdx.x;
     const uint64_t base = (uint64_t)tile * kRsTile;
     const uint32_t nt = (uint32_t)min<uint64_t>(kRsTile, (uint64_t)m - base);
-    cnt[t] = 0u;
-    run[t] = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wcnt[w][t] = 0u;
     gpos[t] = hist[(uint64_t)t * tiles + tile];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) wc[w][t] = 0u;
     __syncthreads();
-    uint64_t k[kRsItems];
-    uint32_t v[kRsItems];
-#pragma unroll
-    for (int r = 0; r < kRsItems; ++r) {
-        const uint32_t i = (uint32_t)r * kRsBlock + t;
-        if (i < nt) {
-            k[r] = kin[base + i];
-            v[r] = vin[base + i];
-            atomicAdd(&cnt[(uint32_t)(k[r] >> shift) & 255u], 1u);
-        } else {
-            k[r] = 0ull;
-            v[r] = 0u;
-        }
-    }
-    __syncthreads();
-    // exclusive scan of the 256 digit counts by wave 0 (4 per lane)
-    if (wave == 0) {
-        uint32_t c[4], s = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            c[q] = cnt[lane * 4 + q];
-            s += c[q];
-        }
-        uint32_t incl = s;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
-            if ((int)lane >= o) incl += u;
-        }
-        uint32_t e = incl - s;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            cnt[lane * 4 + q] = e;
-            e += c[q];
-        }
-    }
-    __syncthreads();
+    uint64_t k[RW];
+    uint32_t v[RW], rk[RW];
+    uint32_t* wc = wcnt[wave];
     const unsigned long long below = (1ull << lane) - 1ull;
-#pragma unroll 1
-    for (int r = 0; r < kRsItems; ++r) {
-        const uint32_t i = (uint32_t)r * kRsBlock + t;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const uint32_t i = wave * IW + (uint32_t)r * 64u + lane;
+        const bool valid = i < nt;
+        k[r] = valid ? kin[base + i] : 0ull;
+        v[r] = valid ? vin[base + i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const uint32_t i = wave * IW + (uint32_t)r * 64u + lane;
         const bool valid = i < nt;
         const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const unsigned long long bb = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        for (int bb = 0; bb < 8; ++bb) {
+            const unsigned long long m1 = __ballot((d >> bb) & 1u);
+            peers &= ((d >> bb) & 1u) ? m1 : ~m1;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & below);
-        if (valid && rank == 0) wc[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pre = run[d];
-            for (uint32_t w = 0; w < wave; ++w) pre += wc[w][d];
-            const uint32_t q = cnt[d] + pre + rank;
+        const uint32_t prev = valid ? wc[d] : 0u;
+        rk[r] = prev + rank;
+        if (valid && rank == 0u) wc[d] = prev + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // digit t: total over the waves, exclusive scan over the digits
+    uint32_t c[NW], tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        c[w] = wcnt[w][t];
+        tot += c[w];
+    }
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+        if ((int)lane >= o) incl += u;
+    }
+    if (lane == 63u) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t ex = incl - tot;
+    for (uint32_t w = 0; w < wave; ++w) ex += wsum[w];
+    tofs[t] = ex;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        wcnt[w][t] = ex;
+        ex += c[w];
+    }
+    __syncthreads();
+    // the tile in digit order in LDS
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const uint32_t i = wave * IW + (uint32_t)r * 64u + lane;
+        if (i < nt) {
+            const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+            const uint32_t q = wc[d] + rk[r];
             if (q < kRsTile) {
                 sk[q] = k[r];
                 sv[q] = v[r];
             }
         }
-        __syncthreads();
-        uint32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            add += wc[w][t];
-            wc[w][t] = 0u;
-        }
-        run[t] += add;
-        __syncthreads();
     }
-    // LDS holds the tile in digit order; item q of digit d goes to
-    // gpos[d] + (q - cnt[d])
+    __syncthreads();
+    // item q of digit d goes to gpos[d] + (q - tofs[d])
 #pragma unroll 1
     for (uint32_t q = t; q < nt; q += kRsBlock) {
         const uint64_t key = sk[q];
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
-        const uint32_t o = gpos[d] + (q - cnt[d]);
+        const uint32_t o = gpos[d] + (q - tofs[d]);
         if (o < m) {
             kout[o] = key;
             vout[o] = sv[q];
