@@ -195,7 +195,9 @@ hullf_status hullf_autotune_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
                                     float *best_ms, void *stream);
 
 /* Per-kernel device timing.  When enabled, every kernel the library
- * launches is bracketed by HIP events on its stream.  hullf_timing_read
+ * launches is bracketed by HIP events on its stream (timestamp events
+ * without a system-scope fence, so recording them flushes no cache between
+ * the kernels they bracket).  hullf_timing_read
  * waits for those events and returns, per kernel kind, the number of
  * launches and their summed duration in milliseconds, then clears them.
  * kinds: 0 = extremes reduction, 1 = inside test (the classify pass, with

@@ -178,8 +178,11 @@ hipEvent_t take_event(hullf_ctx* c) {
         c->pool.pop_back();
         return e;
     }
+    // Timestamps only: without the system-scope fence an event record does
+    // not write back and invalidate the caches between the kernels it
+    // brackets (with it, each record adds a cache flush to the timed work).
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
