@@ -58,6 +58,15 @@ __device__ __forceinline__ uint32_t rank_below(unsigned long long mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// The 16 low bits of x moved to the even bit positions (bit i -> bit 2i).
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
@@ -988,6 +997,10 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const float2* __restrict_
 
 constexpr uint32_t kSpan = 8192;
 constexpr uint32_t kSpanGroups = kSpan / 128;
+// Per-wave LDS of the compaction: a stage of up to 1024 survivor indices,
+// then the span's keep bits in point order (64 groups x 4 words).
+constexpr uint32_t kStageIdx = 1024;
+constexpr uint32_t kStageWords = kStageIdx + 4 * 64;
 static_assert(kSpanGroups == 64, "one group per lane");
 
 // Region skip.  Each k_classify block tests the reduction boxes of its range
@@ -1114,13 +1127,6 @@ __device__ __forceinline__ void compact_span(unsigned long long w0, unsigned lon
                                              uint32_t* __restrict__ out, uint32_t* stage) {
     const uint32_t lane = lane_id();
     const uint32_t c = (uint32_t)(__popcll(w0) + __popcll(w1));
-    uint32_t incl = c;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
-        if ((int)lane >= o) incl += u;
-    }
-    const uint32_t excl = incl - c;
     const uint64_t room = cap > base ? cap - base : 0ull;
     const uint32_t lim = room < (uint64_t)kSpan ? (uint32_t)room : kSpan;
     const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + base, 4u * lim);
@@ -1142,29 +1148,64 @@ __device__ __forceinline__ void compact_span(unsigned long long w0, unsigned lon
             __builtin_amdgcn_raw_buffer_store_b32(i0 + t0 + lane, ro, (int)(4u * (t0 + lane)), 0, kAuxStore);
         return;
     }
-    unsigned long long live = __ballot(c != 0u);
-    while (live) {
-        const uint32_t g = (uint32_t)__builtin_ctzll(live);
-        live &= live - 1ull;
-        const unsigned long long B0 = readlane_u64(w0, g), B1 = readlane_u64(w1, g);
-        const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)excl, (int)g);
-        const bool k0 = (B0 >> lane) & 1ull, k1 = (B1 >> lane) & 1ull;
-        const uint32_t r = rank_below(B0) + rank_below(B1);
-        const uint32_t cnt = (uint32_t)(__popcll(B0) + __popcll(B1));
-        const uint32_t idx = (uint32_t)(sb + 128ull * g) - idx_shift + 2u * lane;
-        // through the stage, each store instruction writes consecutive
-        // indices (storing in place measured 1.7x slower)
-        if (k0) stage[r] = idx;
-        if (k1) stage[r + (k0 ? 1u : 0u)] = idx + 1u;
-        __builtin_amdgcn_wave_barrier();
+    // Partly full span: eight rounds of 1024 points (8 groups).  Each lane
+    // first interleaves its group's two words into the group's 128 keep bits
+    // in point order (four words in the wave's LDS table).  In round e lane l
+    // takes the 16 points [16l, 16l+16) of the round, i.e. half-word l & 7 of
+    // group 8e + (l >> 3); it writes the indices of its kept points to the
+    // stage at their rank, and the wave stores the stage's run with
+    // consecutive lanes.  Nothing is done group by group: a wave-wide step
+    // per group costs ~30 vector instructions and an LDS round trip.
+    uint32_t* mt = stage + kStageIdx;
+    {
+        const uint32_t a0 = (uint32_t)w0, a1 = (uint32_t)(w0 >> 32);
+        const uint32_t b0 = (uint32_t)w1, b1 = (uint32_t)(w1 >> 32);
+        uint4 m;
+        m.x = spread16(a0 & 0xFFFFu) | (spread16(b0 & 0xFFFFu) << 1);
+        m.y = spread16(a0 >> 16) | (spread16(b0 >> 16) << 1);
+        m.z = spread16(a1 & 0xFFFFu) | (spread16(b1 & 0xFFFFu) << 1);
+        m.w = spread16(a1 >> 16) | (spread16(b1 >> 16) << 1);
+        *reinterpret_cast<uint4*>(mt + 4u * lane) = m;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const unsigned long long roundm = __ballot(c != 0u);   // bit g: group g kept a point
+    uint32_t P = 0;
+    const uint32_t ib = (uint32_t)sb - idx_shift;
+#pragma unroll 1
+    for (uint32_t e = 0; e < 8u; ++e) {
+        if (((roundm >> (8u * e)) & 0xFFull) == 0ull) continue;   // uniform: round empty
+        uint32_t m = reinterpret_cast<const uint16_t*>(mt)[64u * e + lane];
+        const uint32_t cnt = (uint32_t)__popc(m);
+        // exclusive prefix of cnt (<= 16) over the lanes, one bit plane at a time
+        uint32_t r = 0, tot = 0;
 #pragma unroll
-        for (uint32_t h = 0; h < 2; ++h) {
-            const uint32_t w = lane + 64u * h;
-            const uint32_t pos = P + w;
-            if (w < cnt && pos < lim)
-                __builtin_amdgcn_raw_buffer_store_b32(stage[w], ro, (int)(4u * pos), 0, kAuxStore);
+        for (uint32_t b = 0; b < 5u; ++b) {
+            const unsigned long long bal = __ballot((cnt >> b) & 1u);
+            r += rank_below(bal) << b;
+            tot += (uint32_t)__popcll(bal) << b;
+        }
+        const uint32_t i0 = ib + 1024u * e + 16u * lane;
+        while (m) {
+            stage[r++] = i0 + (uint32_t)__builtin_ctz(m);
+            m &= m - 1u;
         }
         __builtin_amdgcn_wave_barrier();
+        for (uint32_t w = 0; w < tot; w += 256u) {
+            uint32_t v[4];
+#pragma unroll
+            for (uint32_t h = 0; h < 4u; ++h) {
+                const uint32_t k = w + 64u * h + lane;
+                v[h] = k < tot ? stage[k] : 0u;
+            }
+#pragma unroll
+            for (uint32_t h = 0; h < 4u; ++h) {
+                const uint32_t k = w + 64u * h + lane;
+                const uint32_t pos = P + k;
+                if (k < tot && pos < lim) __builtin_amdgcn_raw_buffer_store_b32(v[h], ro, (int)(4u * pos), 0, kAuxStore);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        P += tot;
     }
 }
 
@@ -1177,7 +1218,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const uint64_t* __restrict__ 
                                                    uint32_t spans, const Octagon* __restrict__ oct,
                                                    uint32_t* __restrict__ out, uint64_t cap, uint64_t* count) {
     constexpr int NW = BLOCK / 64;
-    __shared__ uint32_t sh_stage[NW][128];
+    __shared__ __attribute__((aligned(16))) uint32_t sh_stage[NW][kStageWords];
     __shared__ uint64_t sh_part[NW];
     __shared__ uint32_t sh_tot[2][NW];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
@@ -1549,7 +1590,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(uint32_t S, const SetIn
                                                          uint32_t* __restrict__ surv, uint64_t* counts) {
     constexpr int NW = BLOCK / 64;
     static_assert(NW * kSpan == kBatchItem, "one span per wave");
-    __shared__ uint32_t sh_stage[NW][128];
+    __shared__ __attribute__((aligned(16))) uint32_t sh_stage[NW][kStageWords];
     __shared__ uint64_t sh_part[NW];
     __shared__ uint32_t sh_tot[NW];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
@@ -1747,7 +1788,8 @@ hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32
     HULLF_BATCH_CLASSIFY(512, 16)
     if (!done) return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_compact<256>, dim3(cus * 8), dim3(256), 0, stream, S, sets, octs, tot, bits, blkcnt,
+    // 6 blocks per CU: each holds 4 x 5 KB of LDS (stage and keep-bit table)
+    hipLaunchKernelGGL(k_batch_compact<256>, dim3(cus * 6), dim3(256), 0, stream, S, sets, octs, tot, bits, blkcnt,
                        surv, counts);
     return hipGetLastError();
 }
