@@ -204,7 +204,10 @@ hullf_status hullf_autotune_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
  * its region-skip box test), 2 = batched launch (plan + persistent
  * kernels), 3 = octagon set-up (merge of the reduction's per-block records,
  * scan of the winning chunks), 4 = compaction pass.  Arrays hold at least
- * 5 entries. */
+ * 5 entries.  `enable` is a mask of the kinds to time (bit k = kind k;
+ * HULLF_TIMING_ALL = every kind, 0 = off); kernels of other kinds are
+ * launched without events. */
+#define HULLF_TIMING_ALL 0x1F
 hullf_status hullf_timing_enable(hullf_ctx_t ctx, int enable);
 hullf_status hullf_timing_read(hullf_ctx_t ctx, uint64_t *launches,
                                double *total_ms);

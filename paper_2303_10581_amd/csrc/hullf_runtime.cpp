@@ -100,7 +100,7 @@ struct hullf_ctx {
     hipStream_t capture = nullptr;
     std::vector<GraphEntry> graphs;
     // timing
-    bool timing = false;
+    uint32_t timing = 0;   // bit k: kernels of kind k are timed
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
     uint64_t launches[kKinds] = {0, 0, 0, 0, 0};
@@ -188,7 +188,7 @@ hipEvent_t take_event(hullf_ctx* c) {
 
 template <class F>
 hipError_t timed(hullf_ctx* c, int kind, hipStream_t s, F launch) {
-    if (!c->timing) return launch();
+    if (!((c->timing >> kind) & 1u)) return launch();
     hipEvent_t a = take_event(c), b = take_event(c);
     if (!a || !b) return hipErrorOutOfMemory;
     hipError_t e = hipEventRecord(a, s);
@@ -755,7 +755,7 @@ hullf_status hullf_skip_stats(hullf_ctx_t c, uint64_t* groups_read, uint64_t* gr
 
 hullf_status hullf_timing_enable(hullf_ctx_t c, int enable) {
     if (!c) return HULLF_EINVAL;
-    c->timing = enable != 0;
+    c->timing = (uint32_t)enable & ((1u << kKinds) - 1u);
     return HULLF_OK;
 }
 

@@ -241,8 +241,18 @@ class Context:
         return b.value, p.value, ms.value
 
     # -- timing --------------------------------------------------------------
-    def timing(self, enable: bool):
-        _check(_load().hullf_timing_enable(self.handle, 1 if enable else 0), "hullf_timing_enable")
+    _TIMING_KINDS = ("reduce", "filter", "batched", "setup", "compact")
+
+    def timing(self, enable: bool, kinds=None):
+        """Per-kernel HIP-event timing on or off; `kinds` (names as in
+        timing_read) limits it to those kernels, the others run without
+        events."""
+        mask = 0
+        if enable:
+            sel = self._TIMING_KINDS if kinds is None else kinds
+            for k in sel:
+                mask |= 1 << self._TIMING_KINDS.index(k)
+        _check(_load().hullf_timing_enable(self.handle, mask), "hullf_timing_enable")
 
     def skip_stats(self):
         """(groups read, groups without the region skip) of 128 points by the
