@@ -106,3 +106,31 @@ def named_sets(n: int, seed: int):
     out["collinear_diag"] = np.stack([line, line], axis=1)
     out["all_equal"] = np.full((n, 2), 3.25, dtype=np.float32)
     return out
+
+
+def keep_pattern_set(seed: int, lead: int = 0) -> np.ndarray:
+    """Points whose survivors form structured patterns span by span (8192
+    points per span): ring points (radius 1, kept) and points near the centre
+    (discarded) laid out as all kept, none kept, runs of 16, one kept per 1024
+    points, alternating full and empty 128-point groups, one full 1024-point
+    round, all but the last, only the first, then spans of random density,
+    and a ragged tail.  `lead` centre points in front shift every output
+    offset (16-byte alignment of the stored runs)."""
+    rng = np.random.default_rng(seed)
+    span = 8192
+    pats = [np.ones(span, bool), np.zeros(span, bool),
+            (np.arange(span) // 16) % 2 == 0,
+            (np.arange(span) % 1024) == 1023,
+            (np.arange(span) // 128) % 2 == 1,
+            (np.arange(span) // 1024) == 3,
+            np.arange(span) < span - 1,
+            np.arange(span) == 0]
+    for p in (0.01, 0.3, 0.5, 0.9, 0.99, 0.5, 0.999, 0.001):
+        pats.append(rng.random(span) < p)
+    pats.append(rng.random(1000) < 0.5)
+    keep = np.concatenate([np.zeros(lead, bool)] + pats)
+    n = keep.size
+    th = rng.uniform(0.0, 2.0 * np.pi, n)
+    ring = np.stack([np.cos(th), np.sin(th)], axis=1)
+    centre = rng.uniform(-0.01, 0.01, (n, 2))
+    return np.where(keep[:, None], ring, centre).astype(np.float32)

@@ -206,3 +206,17 @@ def test_full_batched_config(ctx, torch_dev):
     say(f"[gpu] batched full config S=4096 n={pts.shape[0]}")
     sv, cn = _run(ctx, torch_dev, pts, off)
     _check(pts, off, sv, cn, "full batched config")
+
+
+@pytest.mark.parametrize("block,ppt", SHAPES)
+def test_batched_structured_keep_patterns(ctx, torch_dev, block, ppt):
+    """Sets whose survivors form structured patterns, at odd set offsets."""
+    from tests import cases
+    parts = [cases.keep_pattern_set(70 + k, lead) for k, lead in enumerate((0, 1, 3, 5))]
+    parts.insert(2, workloads.request("normal", 77, 5))
+    off = np.zeros(len(parts) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([p.shape[0] for p in parts])
+    pts = np.concatenate(parts, axis=0).astype(np.float32)
+    say(f"[gpu] batched structured keep patterns block={block} ppt={ppt}")
+    sv, cn = _run(ctx, torch_dev, pts, off, block=block, ppt=ppt)
+    _check(pts, off, sv, cn, f"structured {block}x{ppt}")

@@ -216,6 +216,15 @@ def test_dense_spans_at_every_output_alignment(ctx, torch_dev, k):
     _check_all(ctx, torch_dev, xy, f"dense spans, {k} centre points", hull=False)
 
 
+@pytest.mark.parametrize("lead", [0, 1, 3])
+def test_structured_keep_patterns(ctx, torch_dev, lead):
+    """Compaction rounds see every shape of span: full, empty, runs of 16,
+    single survivors per round, alternating groups, one full round, random
+    densities, a ragged tail, at several output alignments."""
+    xy = cases.keep_pattern_set(61, lead)
+    _check_all(ctx, torch_dev, xy, f"structured keep patterns, lead {lead}", hull=False)
+
+
 @pytest.mark.parametrize("shape,compact,skip,per_cu", [
     ("256,8", "256", "1", "0"), ("256,16", "1024", "1", "5"),
     ("512,8", "512", "0", "2"), ("512,16", "256", "0", "1"), ("512,16", "1024", "1", "0")])
