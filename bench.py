@@ -94,8 +94,17 @@ def cpu_baseline(sets, budget_s: float = 15.0):
         oracle.survivors(xy[:m])
         pts += m
     dt = time.perf_counter() - t0
+    # the 1e6-point N(0,1) set (seed 1): filter and exact hull, single thread
+    from paper_2303_10581_amd import workloads
+    small = workloads.normal(1_000_000, 1)
+    t0 = time.perf_counter()
+    sv = oracle.survivors(small)
+    t1 = time.perf_counter()
+    oracle.hull(small, sv)
+    t2 = time.perf_counter()
     return {"value": pts / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m} points of each of the 3 sets ({pts} points, {dt:.1f} s, single thread)"}
+            "sample": f"first {m} points of each of the 3 sets ({pts} points, {dt:.1f} s, single thread)",
+            "small_set_1e6": {"filter_us": round((t1 - t0) * 1e6, 1), "hull_us": round((t2 - t1) * 1e6, 1)}}
 
 
 def stored_traffic():
@@ -248,6 +257,9 @@ def run_bench(args):
     if not args.no_batched:
         result["batched"] = bench_batched(ctx, dev)
 
+    if not args.no_e2e:
+        result["small_set_1e6"] = bench_small(ctx, dev)
+
     ctx.close()
     del dpts, surv
     torch.cuda.empty_cache()
@@ -259,6 +271,38 @@ def run_bench(args):
         log("[bench] timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(sets)
     return result
+
+
+def bench_small(ctx, dev, reps: int = 50):
+    """The 1e6-point N(0,1) set (seed 1): 8 MB, so it sits in the device's
+    last-level cache and the call is latency-bound.  Per call: hull_filter
+    (asynchronous, timed to a stream synchronisation) and convex_hull
+    (synchronous, finishing included), medians over `reps` calls.  The
+    oracle's time on the same set is part of the cpu_baseline leg."""
+    import torch
+    from paper_2303_10581_amd import workloads
+    xy = workloads.normal(1_000_000, 1)
+    t = torch.from_numpy(xy).to(dev)
+    s = torch.empty(xy.shape[0], dtype=torch.int32, device=dev)
+    c = torch.empty(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        ctx.hull_filter(t, surv=s, count=c, stream=stream)
+    torch.cuda.synchronize()
+    f_us, h_us = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ctx.hull_filter(t, surv=s, count=c, stream=stream)
+        torch.cuda.synchronize()
+        f_us.append((time.perf_counter() - t0) * 1e6)
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        h = ctx.convex_hull(t)
+        h_us.append((time.perf_counter() - t0) * 1e6)
+    out = {"workload": "1e6 points N(0,1), seed 1", "survivors": int(c.item()), "hull_vertices": int(h.size),
+           "hull_filter_us_p50": round(float(np.median(f_us)), 1),
+           "convex_hull_us_p50": round(float(np.median(h_us)), 1)}
+    return out
 
 
 def bench_batched(ctx, dev):
