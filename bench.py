@@ -259,6 +259,7 @@ def run_bench(args):
 
     if not args.no_e2e:
         result["small_set_1e6"] = bench_small(ctx, dev)
+        result["library_compaction"] = bench_library_compaction(ctx, dpts, surv, cnt, [k for k, _, _ in sets])
 
     ctx.close()
     del dpts, surv
@@ -303,6 +304,43 @@ def bench_small(ctx, dev, reps: int = 50):
            "hull_filter_us_p50": round(float(np.median(f_us)), 1),
            "convex_hull_us_p50": round(float(np.median(h_us)), 1)}
     return out
+
+
+def bench_library_compaction(ctx, dpts, surv, cnt, kinds, reps: int = 5):
+    """The paper's library variants on this GPU: the inside test writes one
+    flag byte per point (hullf_flags: reduction, set-up, flag kernel) and a
+    library stream compaction turns the flags into indices (torch.nonzero,
+    which runs rocPRIM/hipCUB select and copies the count to the host),
+    against hull_filter (the same reduction and set-up, then the inside test
+    fused with the keep-bit ballots and the two-pass compaction).  Medians of
+    `reps` calls, HIP events on the current stream; indices compared."""
+    import torch
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        ms = []
+        out = None
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            out = fn()
+            b.record(stream)
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms[1:])) * 1e3, out
+
+    res = {}
+    for i, kind in enumerate(kinds):
+        ours_us, _ = timed(lambda: ctx.hull_filter(dpts[i], surv=surv[i], count=cnt[i], stream=stream))
+        flags_us, flags = timed(lambda: ctx.flags(dpts[i], stream=stream))
+        nz_us, idx = timed(lambda: torch.nonzero(flags == 1).squeeze(1))
+        c = int(cnt[i].item())
+        same = idx.numel() == c and bool(torch.equal(idx.to(torch.int32), surv[i][:c]))
+        res[kind] = {"hull_filter_us": round(ours_us, 1), "flags_us": round(flags_us, 1),
+                     "library_nonzero_us": round(nz_us, 1),
+                     "library_total_us": round(flags_us + nz_us, 1), "indices_match": same}
+        del flags, idx
+    return res
 
 
 def bench_batched(ctx, dev):
