@@ -601,6 +601,61 @@ def traffic_summary(fetch_dir, write_dir, out_path=TRAFFIC_JSON):
     print(json.dumps(out["bytes_per_dispatch"]))
 
 
+# Discarded fraction printed in the paper's table of the displaced
+# circumference (sizes 1e7 and 1e9 give the same figures to two decimals),
+# quoted as context: the generator reading used here (radius 1 + U[-p, p])
+# does not reproduce its values beyond p = 0.02.
+PAPER_TABLE1_DISCARD_PCT = {0.02: 13.08, 0.04: 28.58, 0.06: 48.48, 0.08: 81.88, 0.10: 97.16}
+
+
+def p_sweep(args):
+    """Displaced circumference, radius 1 + U[-p, p]: discarded fraction,
+    hull_filter time (median of 5, HIP events) and, at 1e7 points, the
+    synchronous convex_hull time, for p in [0, 0.25] at 1e7 and the paper's
+    p values at 1e9 points."""
+    import torch
+    from paper_2303_10581_amd import hullf, workloads
+    dev = torch.device("cuda:0")
+    ctx = hullf.Context(0)
+    stream = torch.cuda.current_stream()
+    rows = []
+    plan = [(10_000_000, p) for p in (0.0, 0.01, 0.02, 0.04, 0.06, 0.08, 0.10, 0.15, 0.20, 0.25)]
+    plan += [(1_000_000_000, p) for p in (0.02, 0.04, 0.06, 0.08, 0.10)]
+    for n, p in plan:
+        t0 = time.time()
+        xy = workloads.displaced(n, 8, p)
+        t = torch.from_numpy(xy).to(dev)
+        del xy
+        sv = torch.empty(n, dtype=torch.int32, device=dev)
+        c = torch.empty(1, dtype=torch.int64, device=dev)
+        ms = []
+        for _ in range(6):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.hull_filter(t, surv=sv, count=c, stream=stream)
+            b.record(stream)
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        surv = int(c.item())
+        row = {"n": n, "p": p, "discarded_pct": round(100.0 * (n - surv) / n, 2),
+               "hull_filter_ms": round(float(np.median(ms[1:])), 3),
+               "Gpoints_s": round(n / float(np.median(ms[1:])) / 1e6, 1)}
+        if n <= 10_000_000:
+            t1 = time.perf_counter()
+            h = ctx.convex_hull(t)
+            row["convex_hull_ms"] = round((time.perf_counter() - t1) * 1e3, 2)
+            row["hull_vertices"] = int(h.size)
+        if p in PAPER_TABLE1_DISCARD_PCT:
+            row["paper_discarded_pct"] = PAPER_TABLE1_DISCARD_PCT[p]
+        rows.append(row)
+        log(f"[p-sweep] n={n:.0e} p={p}: {row} ({time.time() - t0:.1f}s)")
+        del t, sv
+        torch.cuda.empty_cache()
+    ctx.close()
+    return {"workload": "displaced circumference, radius 1 + U[-p, p], theta U[0, 2pi), seed 8",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -617,6 +672,8 @@ def main():
     ap.add_argument("--serve-arena", type=int, default=1 << 30)
     ap.add_argument("--serve-finish", type=int, default=4)
     ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--p-sweep", action="store_true",
+                    help="discarded fraction and filter time against the displacement p (not a bench line)")
     ap.add_argument("--parse-pmc", default=None)
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None)
     args = ap.parse_args()
@@ -634,6 +691,9 @@ def main():
         return 2
     if args.profile_pass:
         profile_pass(args)
+        return 0
+    if args.p_sweep:
+        print(json.dumps(p_sweep(args)), flush=True)
         return 0
     res = run_bench(args)
     print(json.dumps(res), flush=True)
