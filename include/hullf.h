@@ -65,7 +65,7 @@ typedef enum {
     HULLF_EINVAL = 1,      /* bad argument: null pointer, n >= 2^32, misaligned */
     HULLF_ENONFINITE = 2,  /* an input coordinate is NaN or infinite */
     HULLF_ECAPACITY = 3,   /* output capacity too small; the count is still written */
-    HULLF_ENOMEM = 4,      /* device or host allocation failed */
+    HULLF_ENOMEM = 4,      /* allocation failed, or the context's workspace cap is reached */
     HULLF_EDEVICE = 5,     /* a HIP runtime call failed */
     HULLF_EAGAIN = 6       /* a served request is not finished yet */
 } hullf_status;
@@ -84,6 +84,11 @@ typedef enum {
 /* Create a context on HIP device `device`; it owns the scratch memory
  * (partial extreme records, octagon record, region-skip boxes, keep bits,
  * survivor staging, hull-finishing buffers) and the tuned launch shapes.
+ * workspace_bytes caps the device memory the context may hold at once
+ * (0 = no cap: buffers grow on demand).  Creation itself needs about 320 KB;
+ * a call whose scratch would exceed the cap returns HULLF_ENOMEM without
+ * enqueuing work, and the context stays usable for smaller calls.  Caller
+ * buffers (points, survivors, counts) never count against it.
  * *out is set only on HULLF_OK.  Launch settings read from the environment
  * at creation (all optional; results do not depend on them):
  *   HULLF_FILTER_SHAPE=block,ppt  inside-test shape (256|512, 8|16)
@@ -92,10 +97,14 @@ typedef enum {
  *   HULLF_COMPACT_BLOCK=b         compaction block size (256|512|1024)
  *   HULLF_REDUCE_GRID=g           reduction blocks, 1..4096 (default 8 per CU)
  *   HULLF_FINISH=host             hull finishing always on the host */
-hullf_status hullf_create(int device, hullf_ctx_t *out);
+hullf_status hullf_create(int device, size_t workspace_bytes, hullf_ctx_t *out);
 
 /* Release the context and its device memory.  NULL is ignored. */
 void hullf_destroy(hullf_ctx_t ctx);
+
+/* Device workspace the context holds now (*used_bytes) and its cap
+ * (*cap_bytes, 0 = none). */
+hullf_status hullf_workspace(hullf_ctx_t ctx, uint64_t *used_bytes, uint64_t *cap_bytes);
 
 /* Static string for a status code. */
 const char *hullf_status_str(hullf_status s);

@@ -85,6 +85,20 @@ hipError_t launch_gather(const float2* pts, const uint32_t* surv, const uint64_t
 uint32_t reduce_chunk_points();
 bool shape_supported(Shape shape);
 
+// Launch plan of the single-set filter (reduction, set-up, inside test,
+// compaction) for n >= 1 points on a device with `cus` compute units.
+// reduce_grid_max / per_cu: 0 = defaults.  Scratch sizes in elements.
+struct FilterPlan {
+    int reduce_grid;      // reduction blocks (partial records to merge)
+    Shape shape;          // inside-test shape
+    uint32_t spans;       // compaction spans per block
+    int grid;             // inside-test and compaction blocks
+    uint64_t bits_words;  // keep-bit words (uint64)
+    uint64_t boxes;       // region-skip boxes (float4)
+};
+FilterPlan plan_filter(uint64_t n, int cus, Shape shape, int per_cu, int reduce_grid_max);
+constexpr uint32_t kFilterMaxBlocks = 4096;   // blocks of the two compaction passes
+
 // Two-pass compaction of one set: classify (inside test -> keep bits in
 // point order, one survivor count per block), then compact (ascending
 // indices).  Block b of both launches owns points [b*R, (b+1)*R) with

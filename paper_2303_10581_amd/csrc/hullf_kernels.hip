@@ -1676,6 +1676,23 @@ hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsig
 
 uint32_t compact_span_points() { return kSpan; }
 
+FilterPlan plan_filter(uint64_t n, int cus, Shape shape, int per_cu, int reduce_grid_max) {
+    FilterPlan p;
+    const uint64_t nch = (n + kRChunk - 1) / kRChunk;
+    const uint64_t want = reduce_grid_max > 0 ? (uint64_t)reduce_grid_max : (uint64_t)cus * 8;
+    const uint64_t g = std::min<uint64_t>(want, (uint64_t)kReduceMaxGrid);
+    p.reduce_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(nch, g));
+    p.shape = classify_shape_supported(shape) ? shape : Shape{512, 16};
+    const uint64_t nspans = (n + kSpan - 1) / kSpan;
+    const int pc = per_cu > 0 ? per_cu : (p.shape.block >= 512 ? 3 : 6);
+    const uint64_t target = std::min<uint64_t>((uint64_t)cus * pc, kFilterMaxBlocks);
+    p.spans = (uint32_t)((nspans + target - 1) / target);
+    p.grid = (int)((nspans + p.spans - 1) / p.spans);
+    p.bits_words = 2 * ((n + 127) / 128);
+    p.boxes = 4 * nch;
+    return p;
+}
+
 bool classify_shape_supported(Shape s) {
     return shape_supported(s) && kSpan % (uint32_t)(s.block * s.ppt) == 0u;
 }

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <unordered_map>
 #include <vector>
 
 #include "hull_host.h"
@@ -19,7 +20,7 @@ using namespace hullf;
 namespace {
 
 constexpr int kKinds = 5;   // 0 reduce, 1 inside test, 2 batched, 3 octagon set-up, 4 compaction
-constexpr uint32_t kMaxBlocks = 4096;   // blocks of the two compaction passes
+constexpr uint32_t kMaxBlocks = kFilterMaxBlocks;   // blocks of the two compaction passes
 
 struct GraphEntry {
     const void* pts;
@@ -43,6 +44,11 @@ struct Timed {
 struct hullf_ctx {
     int device = 0;
     int cus = 256;
+    // device workspace: every scratch buffer is counted against ws_cap
+    // (0 = no cap); a request beyond it fails with HULLF_ENOMEM
+    uint64_t ws_cap = 0;
+    uint64_t ws_used = 0;
+    std::unordered_map<void*, uint64_t> ws_sizes;
     // one point set
     Octagon* oct = nullptr;
     unsigned long long* part = nullptr;   // 9 * kReduceMaxGrid
@@ -136,22 +142,55 @@ hullf_status map_err(hipError_t e) {
         if (e_ != hipSuccess) return map_err(e_); \
     } while (0)
 
+// Device scratch of a context, counted against its workspace cap.  Over the
+// cap the allocation is refused with hipErrorOutOfMemory (HULLF_ENOMEM).
+hipError_t ws_alloc(hullf_ctx* c, void** p, uint64_t bytes) {
+    *p = nullptr;
+    if (c->ws_cap != 0 && c->ws_used + bytes > c->ws_cap) return hipErrorOutOfMemory;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    c->ws_sizes[*p] = bytes;
+    c->ws_used += bytes;
+    return hipSuccess;
+}
+
 template <class T>
-hipError_t grow_device(T** p, uint64_t* cap, uint64_t need, hipStream_t stream) {
+hipError_t ws_alloc(hullf_ctx* c, T** p, uint64_t count) {
+    return ws_alloc(c, reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+void ws_free(hullf_ctx* c, void* p) {
+    if (!p) return;
+    auto it = c->ws_sizes.find(p);
+    if (it != c->ws_sizes.end()) {
+        c->ws_used -= it->second;
+        c->ws_sizes.erase(it);
+    }
+    (void)hipFree(p);
+}
+
+// Grow a device buffer to at least `need` elements (with a quarter of slack
+// when the workspace cap leaves room for it).
+template <class T>
+hipError_t grow_device(hullf_ctx* c, T** p, uint64_t* cap, uint64_t need, hipStream_t stream) {
     if (need <= *cap && *p) return hipSuccess;
     uint64_t want = std::max<uint64_t>(need + need / 4, 64);
     if (*p) {
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return e;
-        (void)hipFree(*p);
+        ws_free(c, *p);
         *p = nullptr;
         *cap = 0;
     }
-    hipError_t e = hipMalloc((void**)p, want * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return e;
+    if (c->ws_cap != 0) {
+        const uint64_t room = c->ws_cap > c->ws_used ? (c->ws_cap - c->ws_used) / sizeof(T) : 0;
+        want = std::max<uint64_t>(need, std::min<uint64_t>(want, room));
     }
+    hipError_t e = ws_alloc(c, p, want);
+    if (e != hipSuccess) return e;
     *cap = want;
     return hipSuccess;
 }
@@ -202,11 +241,7 @@ hipError_t timed(hullf_ctx* c, int kind, hipStream_t s, F launch) {
 }
 
 int reduce_grid(const hullf_ctx* c, uint64_t n) {
-    const uint64_t ch = reduce_chunk_points();
-    const uint64_t nch = (n + ch - 1) / ch;
-    const uint64_t want = c->reduce_grid_max > 0 ? (uint64_t)c->reduce_grid_max : (uint64_t)c->cus * 8;
-    const uint64_t g = std::min<uint64_t>(want, (uint64_t)kReduceMaxGrid);
-    return (int)std::max<uint64_t>(1, std::min<uint64_t>(nch, g));
+    return plan_filter(n, c->cus, c->filter_shape, c->classify_per_cu, c->reduce_grid_max).reduce_grid;
 }
 
 bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0u; }
@@ -223,34 +258,26 @@ void drop_graphs(hullf_ctx* c) {
 hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uint32_t* d_surv,
                             uint64_t cap, uint64_t* d_count, hipStream_t s) {
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
-    const int rg = reduce_grid(c, n);
-    Shape sh = c->filter_shape;
-    if (!classify_shape_supported(sh)) sh = Shape{512, 16};
-    const uint64_t span = compact_span_points();
-    const uint64_t nspans = (n + span - 1) / span;
-    const int per_cu = c->classify_per_cu > 0 ? c->classify_per_cu : (sh.block >= 512 ? 3 : 6);
-    const uint64_t target = std::min<uint64_t>((uint64_t)c->cus * per_cu, kMaxBlocks);
-    const uint64_t spans = (nspans + target - 1) / target;
-    const int grid = (int)((nspans + spans - 1) / spans);
-    CHECK_HIP(grow_device(&c->bits, &c->bits_cap, 2 * ((n + 127) / 128), s));
+    const FilterPlan p = plan_filter(n, c->cus, c->filter_shape, c->classify_per_cu, c->reduce_grid_max);
+    CHECK_HIP(grow_device(c, &c->bits, &c->bits_cap, p.bits_words, s));
     float4* box = nullptr;
     uint64_t nbox = 0;
     if (c->region_skip) {
-        const uint64_t ch = reduce_chunk_points();
-        nbox = 4 * ((n + ch - 1) / ch);
-        CHECK_HIP(grow_device(&c->boxes, &c->boxes_cap, nbox, s));
+        nbox = p.boxes;
+        CHECK_HIP(grow_device(c, &c->boxes, &c->boxes_cap, nbox, s));
         box = c->boxes;
     }
+    const int rg = p.reduce_grid;
     CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, box, rg, s); }));
     CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
     CHECK_HIP(timed(c, 1, s, [&] {
-        return launch_classify(pts, n, c->oct, (uint32_t)spans, c->bits, c->blkcnt, box, nbox, c->groups_read, sh,
-                               grid, s);
+        return launch_classify(pts, n, c->oct, p.spans, c->bits, c->blkcnt, box, nbox, c->groups_read, p.shape,
+                               p.grid, s);
     }));
     c->groups_total += (n + 127) / 128;
     CHECK_HIP(timed(c, 4, s, [&] {
-        return launch_compact(c->bits, c->blkcnt, n, (uint32_t)spans, c->oct, d_surv, cap, d_count,
-                              c->compact_block, grid, s);
+        return launch_compact(c->bits, c->blkcnt, n, p.spans, c->oct, d_surv, cap, d_count, c->compact_block,
+                              p.grid, s);
     }));
     return HULLF_OK;
 }
@@ -264,30 +291,30 @@ hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
         for (int k = 0; k < 3; ++k) {
-            (void)hipFree(c->fk[k]);
-            (void)hipFree(c->fv[k]);
+            ws_free(c, c->fk[k]);
+            ws_free(c, c->fv[k]);
             c->fk[k] = nullptr;
             c->fv[k] = nullptr;
         }
-        (void)hipFree(c->fchain);
-        (void)hipFree(c->fcnt);
+        ws_free(c, c->fchain);
+        ws_free(c, c->fcnt);
         c->fchain = nullptr;
         c->fcnt = nullptr;
         c->f_cap = 0;
         const uint64_t cap = m + m / 8 + 1024;
         for (int k = 0; k < 3; ++k) {
-            if ((e = hipMalloc((void**)&c->fk[k], cap * sizeof(uint64_t))) != hipSuccess) return e;
-            if ((e = hipMalloc((void**)&c->fv[k], cap * sizeof(uint32_t))) != hipSuccess) return e;
+            if ((e = ws_alloc(c, &c->fk[k], cap)) != hipSuccess) return e;
+            if ((e = ws_alloc(c, &c->fv[k], cap)) != hipSuccess) return e;
         }
-        if ((e = hipMalloc((void**)&c->fchain, cap * sizeof(uint32_t))) != hipSuccess) return e;
-        if ((e = hipMalloc((void**)&c->fcnt, (cap / kChainChunk + 1) * sizeof(uint32_t))) != hipSuccess) return e;
+        if ((e = ws_alloc(c, &c->fchain, cap)) != hipSuccess) return e;
+        if ((e = ws_alloc(c, &c->fcnt, cap / kChainChunk + 1)) != hipSuccess) return e;
         c->f_cap = cap;
     }
     const uint64_t hw = 256ull * finish_sort_tiles((uint32_t)m);
-    hipError_t e = grow_device(&c->fhist, &c->fhist_cap, hw, s);
+    hipError_t e = grow_device(c, &c->fhist, &c->fhist_cap, hw, s);
     if (e != hipSuccess) return e;
     // frow: 256 row sums, [256] a total, [258..259] the bad-index flag (uint64)
-    if (!c->frow && (e = hipMalloc((void**)&c->frow, 260 * sizeof(uint32_t))) != hipSuccess) return e;
+    if (!c->frow && (e = ws_alloc(c, &c->frow, 260)) != hipSuccess) return e;
     if (!c->h_total && (e = hipHostMalloc((void**)&c->h_total, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess)
         return e;
     return hipSuccess;
@@ -358,7 +385,7 @@ hullf_status hull_of(hullf_ctx* c, const float2* pts, uint64_t n, const uint32_t
     out.clear();
     if (m == 0) return HULLF_OK;
     if (m >= kDeviceFinishMin && !c->host_finish) return finish_on_device(c, pts, n, d_surv, m, out, s);
-    CHECK_HIP(grow_device(&c->gather, &c->gather_cap, m, s));
+    CHECK_HIP(grow_device(c, &c->gather, &c->gather_cap, m, s));
     CHECK_HIP(grow_host(&c->h_surv, &c->h_cap, m));
     CHECK_HIP(grow_host(&c->h_xy, &c->h_xy_cap, m));
     const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((m + 255) / 256, (uint64_t)c->cus * 8));
@@ -380,14 +407,14 @@ hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, hipStream_
     bool realloc = false;
     if (S > c->b_sets_cap) {
         CHECK_HIP(hipStreamSynchronize(s));
-        (void)hipFree(c->b_sets);
-        (void)hipFree(c->b_octs);
+        ws_free(c, c->b_sets);
+        ws_free(c, c->b_octs);
         c->b_sets = nullptr;
         c->b_octs = nullptr;
         c->b_sets_cap = 0;
         const uint32_t cap = std::max<uint32_t>(S, 64);
-        CHECK_HIP(hipMalloc((void**)&c->b_sets, cap * sizeof(SetInfo)));
-        CHECK_HIP(hipMalloc((void**)&c->b_octs, cap * sizeof(Octagon)));
+        CHECK_HIP(ws_alloc(c, &c->b_sets, cap));
+        CHECK_HIP(ws_alloc(c, &c->b_octs, cap));
         c->b_sets_cap = cap;
         realloc = true;
     }
@@ -396,25 +423,25 @@ hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, hipStream_
     if (items > 0xFFFFFFFFull || rtiles > 0xFFFFFFFFull) return HULLF_EINVAL;
     if (items > c->b_items_cap || !c->b_bits || !c->b_blkcnt) {
         CHECK_HIP(hipStreamSynchronize(s));
-        (void)hipFree(c->b_bits);
-        (void)hipFree(c->b_blkcnt);
+        ws_free(c, c->b_bits);
+        ws_free(c, c->b_blkcnt);
         c->b_bits = nullptr;
         c->b_blkcnt = nullptr;
         c->b_items_cap = 0;
         const uint64_t cap = items + items / 4 + 64;
-        CHECK_HIP(hipMalloc((void**)&c->b_bits, cap * batch_item_words() * sizeof(uint64_t)));
-        CHECK_HIP(hipMalloc((void**)&c->b_blkcnt, cap * sizeof(uint32_t)));
+        CHECK_HIP(ws_alloc(c, &c->b_bits, cap * batch_item_words()));
+        CHECK_HIP(ws_alloc(c, &c->b_blkcnt, cap));
         c->b_items_cap = cap;
         realloc = true;
     }
     if (rtiles > c->b_part_cap || !c->b_part) {
         uint64_t words = c->b_part_cap * 9;
-        CHECK_HIP(grow_device(&c->b_part, &words, rtiles * 9, s));
+        CHECK_HIP(grow_device(c, &c->b_part, &words, rtiles * 9, s));
         c->b_part_cap = words / 9;
         realloc = true;
     }
     if (c->region_skip && (c->b_boxes_cap < c->b_part_cap * batch_tile_boxes() || !c->b_boxes)) {
-        CHECK_HIP(grow_device(&c->b_boxes, &c->b_boxes_cap, c->b_part_cap * batch_tile_boxes(), s));
+        CHECK_HIP(grow_device(c, &c->b_boxes, &c->b_boxes_cap, c->b_part_cap * batch_tile_boxes(), s));
         realloc = true;
     }
     if (realloc) drop_graphs(c);
@@ -460,7 +487,7 @@ const char* hullf_status_str(hullf_status s) {
     return "unknown status";
 }
 
-hullf_status hullf_create(int device, hullf_ctx_t* out) {
+hullf_status hullf_create(int device, size_t workspace_bytes, hullf_ctx_t* out) {
     if (!out) return HULLF_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HULLF_EINVAL;
@@ -468,6 +495,7 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
     hullf_ctx* c = new (std::nothrow) hullf_ctx();
     if (!c) return HULLF_ENOMEM;
     c->device = device;
+    c->ws_cap = workspace_bytes;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cus = cus;
@@ -484,13 +512,13 @@ hullf_status hullf_create(int device, hullf_ctx_t* out) {
         if (b == 256 || b == 512 || b == 1024) c->compact_block = b;
     }
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = hipMalloc((void**)&c->oct, sizeof(Octagon));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->part, 9ull * kReduceMaxGrid * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->count, sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->blkcnt, kMaxBlocks * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->groups_read, sizeof(unsigned long long));
+    if (e == hipSuccess) e = ws_alloc(c, &c->oct, 1);
+    if (e == hipSuccess) e = ws_alloc(c, &c->part, 9ull * kReduceMaxGrid);
+    if (e == hipSuccess) e = ws_alloc(c, &c->count, 1);
+    if (e == hipSuccess) e = ws_alloc(c, &c->blkcnt, kMaxBlocks);
+    if (e == hipSuccess) e = ws_alloc(c, &c->groups_read, 1);
     if (e == hipSuccess) e = hipMemset(c->groups_read, 0, sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->b_tot, sizeof(BatchTotals));
+    if (e == hipSuccess) e = ws_alloc(c, &c->b_tot, 1);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_count, sizeof(uint64_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_oct, sizeof(Octagon), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
@@ -582,7 +610,7 @@ hullf_status convex_hull(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint3
     if (n == 0) return HULLF_OK;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    CHECK_HIP(grow_device(&c->surv, &c->surv_cap, n, s));
+    CHECK_HIP(grow_device(c, &c->surv, &c->surv_cap, n, s));
     hullf_status st = enqueue_filter(c, d_pts, n, c->surv, n, c->count, s);
     if (st != HULLF_OK) return st;
     CHECK_HIP(hipMemcpyAsync(c->h_count, c->count, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -750,6 +778,13 @@ hullf_status hullf_skip_stats(hullf_ctx_t c, uint64_t* groups_read, uint64_t* gr
     *groups_read = v;
     *groups_total = c->groups_total;
     c->groups_total = 0;
+    return HULLF_OK;
+}
+
+hullf_status hullf_workspace(hullf_ctx_t c, uint64_t* used_bytes, uint64_t* cap_bytes) {
+    if (!c || !used_bytes || !cap_bytes) return HULLF_EINVAL;
+    *used_bytes = c->ws_used;
+    *cap_bytes = c->ws_cap;
     return HULLF_OK;
 }
 

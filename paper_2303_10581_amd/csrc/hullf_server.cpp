@@ -397,7 +397,7 @@ hullf_status hullf_server_create(int device, const hullf_server_config* cfg, hul
     if (!s) return HULLF_ENOMEM;
     s->device = device;
     s->cfg = c;
-    hullf_status r = hullf_create(device, &s->ctx);
+    hullf_status r = hullf_create(device, 0, &s->ctx);
     if (r != HULLF_OK) {
         s->ctx = nullptr;
         delete s;
@@ -431,7 +431,7 @@ hullf_status hullf_server_create(int device, const hullf_server_config* cfg, hul
     if (r == HULLF_OK) r = map_err(hipStreamSynchronize(s->compute));
     for (uint32_t k = 0; k < c.finish_threads && r == HULLF_OK; ++k) {
         hullf_ctx_t f = nullptr;
-        r = hullf_create(device, &f);
+        r = hullf_create(device, 0, &f);
         if (r == HULLF_OK) s->fctx.push_back(f);
     }
     if (r != HULLF_OK) {

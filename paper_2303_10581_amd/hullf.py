@@ -38,7 +38,8 @@ def _load():
     P, U64, U32, I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
     st = ctypes.c_int
     sig = {
-        "hullf_create": ([I, ctypes.POINTER(P)], st),
+        "hullf_create": ([I, ctypes.c_size_t, ctypes.POINTER(P)], st),
+        "hullf_workspace": ([P, ctypes.POINTER(U64), ctypes.POINTER(U64)], st),
         "hullf_destroy": ([P], None),
         "hullf_status_str": ([st], ctypes.c_char_p),
         "hullf_octagon": ([P, P, U64, P, P], st),
@@ -96,12 +97,18 @@ def _points(pts):
 class Context:
     """Owns a hullf context (scratch memory, tuned shapes, graph cache)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, workspace_bytes: int = 0):
         lib = _load()
         h = ctypes.c_void_p()
-        _check(lib.hullf_create(int(device), ctypes.byref(h)), "hullf_create")
+        _check(lib.hullf_create(int(device), int(workspace_bytes), ctypes.byref(h)), "hullf_create")
         self.handle = h
         self.device = int(device)
+
+    def workspace(self):
+        """(device bytes held now, cap in bytes or 0)."""
+        u, c = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(_load().hullf_workspace(self.handle, ctypes.byref(u), ctypes.byref(c)), "hullf_workspace")
+        return u.value, c.value
 
     def close(self):
         if self.handle:
@@ -384,7 +391,7 @@ class Server:
 
 def exported_symbols():
     """Names of the C-ABI functions the binding expects."""
-    return ["hullf_create", "hullf_destroy", "hullf_status_str", "hullf_octagon", "hull_filter",
+    return ["hullf_create", "hullf_destroy", "hullf_workspace", "hullf_status_str", "hullf_octagon", "hull_filter",
             "convex_hull", "hullf_flags", "hull_from_survivors", "hull_filter_batched", "hull_filter_segments",
             "hull_filter_batched_shape", "hullf_autotune_batched", "hullf_timing_enable",
             "hullf_timing_read", "hullf_skip_stats", "hullf_server_create", "hullf_server_destroy", "hullf_server_submit",

@@ -59,7 +59,7 @@ def test_create_without_gpu_fails_cleanly(lib):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
-    assert lib.hullf_create(0, ctypes.byref(h)) != 0
+    assert lib.hullf_create(0, 0, ctypes.byref(h)) != 0
     assert not h.value
 
 

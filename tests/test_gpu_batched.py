@@ -200,14 +200,6 @@ def test_autotune_then_parity(ctx, torch_dev):
     _check(pts, off, surv.cpu().numpy().astype(np.uint32), counts.cpu().numpy(), "after autotune")
 
 
-def test_full_batched_config(ctx, torch_dev):
-    # 4096 sets, sizes log-uniform in [100, 1e6], kinds mixed, centre/scale
-    pts, off, kinds = workloads.batch(S=4096, seed=6)
-    say(f"[gpu] batched full config S=4096 n={pts.shape[0]}")
-    sv, cn = _run(ctx, torch_dev, pts, off)
-    _check(pts, off, sv, cn, "full batched config")
-
-
 @pytest.mark.parametrize("block,ppt", SHAPES)
 def test_batched_structured_keep_patterns(ctx, torch_dev, block, ppt):
     """Sets whose survivors form structured patterns, at odd set offsets."""

@@ -249,29 +249,3 @@ def test_launch_settings(torch_dev, monkeypatch, shape, compact, skip, per_cu):
 def test_config_small_normal_1e6(ctx, torch_dev):
     xy = workloads.normal(1_000_000, 1)
     _check_all(ctx, torch_dev, xy, "normal 1e6 seed 1")
-
-
-@pytest.mark.parametrize("kind,seed", [("normal", 2), ("circle", 3), ("displaced", 4)])
-def test_full_size_1e8(ctx, torch_dev, kind, seed):
-    n = 100_000_000
-    say(f"[gpu] full size {kind} n={n} seed={seed}")
-    xy = workloads.by_kind(kind, n, seed)
-    t = upload(xy, torch_dev)
-    assert ctx.octagon(t).tolist() == oracle.extremes(xy).tolist()
-    want = oracle.survivors(xy)
-    got = survivors_np(ctx, t)
-    assert got.size == want.size and np.array_equal(got, want)
-    if kind == "normal":
-        assert np.array_equal(ctx.convex_hull(t), oracle.hull(xy, want))
-    del t
-
-
-def test_full_size_5e8_circle_jitter(ctx, torch_dev):
-    n = 500_000_000
-    say(f"[gpu] full size circle_jitter n={n} seed=5")
-    xy = workloads.circle_jitter(n, 5, 0.01)
-    t = upload(xy, torch_dev)
-    want = oracle.survivors(xy)
-    got = survivors_np(ctx, t)
-    assert got.size == want.size and np.array_equal(got, want)
-    del t
