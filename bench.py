@@ -79,22 +79,53 @@ def algorithmic_bytes(n: int, survivors: int, read_frac: float = 1.0, boxes: boo
             "compact": n // 8 + 4 * survivors}
 
 
-def cpu_baseline(sets, budget_s: float = 15.0):
-    """The oracle (single-threaded C) on a bounded prefix of each set."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _pctl(v):
+    a = np.asarray(v, dtype=np.float64)
+    return {"median": float(np.median(a)), "p10": float(np.percentile(a, 10)),
+            "p90": float(np.percentile(a, 90))}
+
+
+def cpu_baseline(sets, steps: int = 5, step_s: float = 2.0):
+    """The oracle's filter on this host: one thread (the oracle as it stands,
+    like the paper's sequential CPU filters) and all cores (its OpenMP build,
+    same arithmetic), each over `steps` timed steps of a bounded prefix of
+    every set; rates as median with p10/p90 over the steps.  The two builds'
+    survivors are compared on the one-thread sample."""
     import oracle
     oracle.build()
-    probe = sets[0][2][:1_000_000]
-    t0 = time.perf_counter()
-    oracle.survivors(probe)
-    rate = probe.shape[0] / max(time.perf_counter() - t0, 1e-6)
-    m = int(min(N_SET, max(1_000_000, budget_s * rate / len(sets))))
-    pts = 0
-    t0 = time.perf_counter()
-    for _, _, xy in sets:
-        oracle.survivors(xy[:m])
-        pts += m
-    dt = time.perf_counter() - t0
-    # the 1e6-point N(0,1) set (seed 1): filter and exact hull, single thread
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+    def rows(fn, budget_s):
+        probe = sets[0][2][:1_000_000]
+        t0 = time.perf_counter()
+        fn(probe)
+        rate = probe.shape[0] / max(time.perf_counter() - t0, 1e-6)
+        m = int(min(N_SET, max(1_000_000, budget_s * rate / len(sets))))
+        rates = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            for _, _, xy in sets:
+                fn(xy[:m])
+            rates.append(m * len(sets) / (time.perf_counter() - t0) / 1e9)
+        return m, rates
+
+    m1, r1 = rows(oracle.survivors, step_s)
+    mp, rp = rows(lambda a: oracle.survivors_omp(a, threads), step_s)
+    same = all(np.array_equal(oracle.survivors(xy[:m1]), oracle.survivors_omp(xy[:m1], threads))
+               for _, _, xy in sets)
+    one, allc = _pctl(r1), _pctl(rp)
+    # the 1e6-point N(0,1) set (seed 1): filter and exact hull, one thread
     from paper_2303_10581_amd import workloads
     small = workloads.normal(1_000_000, 1)
     t0 = time.perf_counter()
@@ -102,8 +133,15 @@ def cpu_baseline(sets, budget_s: float = 15.0):
     t1 = time.perf_counter()
     oracle.hull(small, sv)
     t2 = time.perf_counter()
-    return {"value": pts / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m} points of each of the 3 sets ({pts} points, {dt:.1f} s, single thread)",
+    return {"value": round(one["median"], 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m1} points of each of the 3 sets per step, {steps} steps, one thread",
+            "p10": round(one["p10"], 5), "p90": round(one["p90"], 5),
+            "all_cores": {"value": round(allc["median"], 4), "p10": round(allc["p10"], 4),
+                          "p90": round(allc["p90"], 4), "unit": "Gpoints/s", "cores": threads,
+                          "kind": "oracle (OpenMP build of the same filter)",
+                          "sample": f"first {mp} points of each of the 3 sets per step, {steps} steps",
+                          "survivors_equal_one_thread": bool(same)},
+            "nproc": os.cpu_count(), "threads_available": threads, "cpu_model": _cpu_model(),
             "small_set_1e6": {"filter_us": round((t1 - t0) * 1e6, 1), "hull_us": round((t2 - t1) * 1e6, 1)}}
 
 

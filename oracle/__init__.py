@@ -9,6 +9,9 @@ Functions follow Algorithm 1 of the paper:
   extremes(xy)   -- Sec. 3.1, the eight octagon vertices (indices)
   keep(xy, idx)  -- Sec. 3.2, the inside test (1 = survives)
   survivors(xy)  -- Sec. 4.1.1, ascending indices of the survivors
+  survivors_omp  -- the same on every host core (CPU baseline timing)
+  extremes16, keep_poly, survivors16
+                 -- Sec. 2, the 16-direction filter of the related work
   hull(xy, sub)  -- Sec. 3.3, counter-clockwise hull vertex indices
 """
 from __future__ import annotations
@@ -31,7 +34,7 @@ def build(force: bool = False) -> str:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call([
             "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-            "-fexcess-precision=standard", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm",
+            "-fexcess-precision=standard", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm",
         ])
         os.replace(tmp, _LIB)
     return _LIB
@@ -52,6 +55,16 @@ def _load():
         lib.oracle_keep.restype = None
         lib.oracle_survivors.argtypes = [P, U64, P, P]
         lib.oracle_survivors.restype = ctypes.c_int64
+        lib.oracle_survivors_omp.argtypes = [P, U64, P, P, ctypes.c_int]
+        lib.oracle_survivors_omp.restype = ctypes.c_int64
+        lib.oracle_extremes16.argtypes = [P, U64, P]
+        lib.oracle_extremes16.restype = None
+        lib.oracle_keep_poly.argtypes = [P, U64, P, ctypes.c_int, P]
+        lib.oracle_keep_poly.restype = None
+        lib.oracle_survivors16.argtypes = [P, U64, P, P]
+        lib.oracle_survivors16.restype = ctypes.c_int64
+        lib.oracle_key16_values.argtypes = [P, U64, ctypes.c_int, P]
+        lib.oracle_key16_values.restype = None
         lib.oracle_hull.argtypes = [P, U64, P, U64, P]
         lib.oracle_hull.restype = U64
         F = ctypes.c_float
@@ -111,6 +124,68 @@ def survivors(xy) -> np.ndarray:
     n = a.shape[0]
     out = np.zeros(max(n, 1), dtype=np.uint32)
     c = _load().oracle_survivors(a.ctypes.data, n, out.ctypes.data, None)
+    if c == -2:
+        raise NonFiniteInput("non-finite coordinate")
+    if c < 0:
+        raise MemoryError("oracle allocation failed")
+    return out[:c].copy()
+
+
+def survivors_omp(xy, threads: int = 0) -> np.ndarray:
+    """survivors(xy) computed on `threads` OpenMP threads (0: all), for the
+    all-core CPU baseline; same arithmetic and result as survivors()."""
+    a = _pts(xy)
+    n = a.shape[0]
+    out = np.zeros(max(n, 1), dtype=np.uint32)
+    c = _load().oracle_survivors_omp(a.ctypes.data, n, out.ctypes.data, None, int(threads))
+    if c == -2:
+        raise NonFiniteInput("non-finite coordinate")
+    if c < 0:
+        raise MemoryError("oracle allocation failed")
+    return out[:c].copy()
+
+
+def extremes16(xy) -> np.ndarray:
+    """Indices V0..V15 of the 16-direction filter (Sec. 2; directions at
+    22.5-degree steps counter-clockwise from +x, first index on ties);
+    V[2j] is octagon vertex E_j."""
+    a = _pts(xy)
+    if a.shape[0] == 0:
+        raise ValueError("empty point set has no extremes")
+    if not validate(a):
+        raise NonFiniteInput("non-finite coordinate")
+    out = np.zeros(16, dtype=np.uint32)
+    _load().oracle_extremes16(a.ctypes.data, a.shape[0], out.ctypes.data)
+    return out
+
+
+def key16_values(xy, k: int) -> np.ndarray:
+    """float32 key of direction k (k * 22.5 degrees) of every point."""
+    a = _pts(xy)
+    out = np.zeros(a.shape[0], dtype=np.float32)
+    if a.shape[0]:
+        _load().oracle_key16_values(a.ctypes.data, a.shape[0], int(k), out.ctypes.data)
+    return out
+
+
+def keep_poly(xy, idx) -> np.ndarray:
+    """uint8 flags, 1 = survives the polygon with vertex indices idx (in
+    order, any length >= 1) under the binary64 rule of keep()."""
+    a = _pts(xy)
+    n = a.shape[0]
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    out = np.zeros(n, dtype=np.uint8)
+    if n:
+        _load().oracle_keep_poly(a.ctypes.data, n, idx.ctypes.data, int(idx.size), out.ctypes.data)
+    return out
+
+
+def survivors16(xy) -> np.ndarray:
+    """Ascending indices of the points that survive the 16-direction filter."""
+    a = _pts(xy)
+    n = a.shape[0]
+    out = np.zeros(max(n, 1), dtype=np.uint32)
+    c = _load().oracle_survivors16(a.ctypes.data, n, out.ctypes.data, None)
     if c == -2:
         raise NonFiniteInput("non-finite coordinate")
     if c < 0:

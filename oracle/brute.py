@@ -155,3 +155,77 @@ def rounding_margin(a, b, p) -> Fraction:
     ex, ey = b[0] - a[0], b[1] - a[1]
     qx, qy = p[0] - a[0], p[1] - a[1]
     return Fraction(8 * (abs(ex * qy) + abs(ey * qx)), 1 << 53)
+
+
+# --- Sec. 2: the 16-direction filter ---------------------------------------
+
+# binary32 nearest to tan(22.5 deg) = sqrt(2) - 1
+TAN_22_5 = Fraction(float.fromhex("0x1.a8279ap-2"))
+
+
+def rnd32(q: Fraction) -> np.float32:
+    """q rounded to binary32, to nearest with ties to even (overflow gives
+    +-inf)."""
+    if q == 0:
+        return np.float32(0.0)
+    c = np.float32(float(q))
+    if np.isinf(c):
+        return c
+    best = None
+    for v in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        if np.isinf(v):
+            continue
+        d = abs(Fraction(float(v)) - q)
+        even = (int(np.array(v, dtype=np.float32).view(np.uint32)) & 1) == 0
+        key = (d, not even)
+        if best is None or key < best[0]:
+            best = (key, v)
+    return best[1]
+
+
+def key16_exact(k: int, x, y) -> np.float32:
+    """The key of direction k (k * 22.5 degrees) of the FP32 point (x, y):
+    one rounding of the exact x + T y (or its rotations) to binary32, the
+    axis keys exact, the diagonal keys fl32(x +- y), negated for the
+    directions taken as minima."""
+    X, Y, T = Fraction(float(x)), Fraction(float(y)), TAN_22_5
+    base = {
+        0: lambda: np.float32(x),
+        1: lambda: rnd32(X + T * Y),
+        2: lambda: rnd32(X + Y),
+        3: lambda: rnd32(T * X + Y),
+        4: lambda: np.float32(y),
+        5: lambda: rnd32(-T * X + Y),
+        6: lambda: -rnd32(X - Y),
+        7: lambda: rnd32(T * Y - X),
+    }
+    # directions 8..15 are the opposite of 0..7: the negated key of k - 8
+    return base[k]() if k < 8 else -base[k - 8]()
+
+
+def extremes16_exact(xy) -> list:
+    """V0..V15: for each direction the first index of the maximal key."""
+    out = []
+    for k in range(16):
+        best_i, best = 0, None
+        for i in range(len(xy)):
+            v = key16_exact(k, xy[i][0], xy[i][1])
+            if best is None or v > best:
+                best, best_i = v, i
+        out.append(best_i)
+    return out
+
+
+def poly_edges(xy, idx):
+    """Exact (a, b) of the non-degenerate edges (idx[j], idx[j+1]) of a
+    polygon of input points, in order."""
+    V = [_pt(xy, int(i)) for i in idx]
+    k = len(V)
+    return [(V[j], V[(j + 1) % k]) for j in range(k) if V[j] != V[(j + 1) % k]]
+
+
+def strictly_inside_poly_exact(xy, idx, i) -> bool:
+    """Exact rule: point i strictly left of every non-degenerate edge."""
+    E = poly_edges(xy, idx)
+    p = _pt(xy, i)
+    return len(E) >= 1 and all(det_exact(a, b, p) > 0 for a, b in E)

@@ -402,3 +402,249 @@ uint64_t oracle_hull(const float *xy, uint64_t n, const uint32_t *subset,
     free(p);
     return t;
 }
+
+/* ------------------------------------------------------------------------ */
+/* All-core build of the filter (CPU baseline timing only)                  */
+/* ------------------------------------------------------------------------ */
+
+/* oracle_survivors over `threads` OpenMP threads (<= 0: the runtime's
+ * default), for timing the filter on every host core.  Same arithmetic:
+ * each thread takes a contiguous slice of the points, finds the slice's
+ * extremes with the comparisons of oracle_extremes, and the slices are
+ * merged in ascending order keeping the earlier slice on equal keys, so the
+ * first index attaining each key wins as in the one-thread scan.  The inside
+ * test is strictly_inside per point and edge; the survivors of each slice
+ * are written at the slice's offset (an exclusive sum of the slice counts).
+ * Returns what oracle_survivors returns. */
+#include <omp.h>
+
+#define OMP_MAX_SLICES 1024
+
+int64_t oracle_survivors_omp(const float *xy, uint64_t n, uint32_t *surv,
+                             uint32_t idx_out[8], int threads)
+{
+    int T = threads > 0 ? threads : omp_get_max_threads();
+    if (T > OMP_MAX_SLICES) T = OMP_MAX_SLICES;
+    if ((uint64_t)T > n) T = n > 0 ? (int)n : 1;
+    int bad = 0;
+#pragma omp parallel for num_threads(T) reduction(| : bad) schedule(static)
+    for (int64_t i = 0; i < (int64_t)(2 * n); ++i)
+        bad |= !isfinite(xy[i]);
+    if (bad)
+        return -2;
+    if (n == 0)
+        return 0;
+
+    /* per slice: the first index attaining each key, and its key value;
+     * key order: x, y (max), x, y (min), x+y, y-x (max), x+y (min), x-y (max) */
+    uint64_t (*sidx)[8] = malloc(sizeof(uint64_t[8]) * (size_t)T);
+    float (*sval)[8] = malloc(sizeof(float[8]) * (size_t)T);
+    uint64_t *cnt = malloc(sizeof(uint64_t) * ((size_t)T + 1));
+    uint8_t *keep = (uint8_t *)malloc(n);
+    if (!sidx || !sval || !cnt || !keep) {
+        free(sidx); free(sval); free(cnt); free(keep);
+        return -4;
+    }
+#pragma omp parallel num_threads(T)
+    {
+        int t = omp_get_thread_num();
+        uint64_t lo = n * (uint64_t)t / (uint64_t)T, hi = n * (uint64_t)(t + 1) / (uint64_t)T;
+        uint64_t right = lo, top = lo, left = lo, low = lo, tr = lo, tl = lo, bl = lo, br = lo;
+        float best_tr = 0, best_tl = 0, best_bl = 0, best_br = 0;
+        for (uint64_t i = lo; i < hi; ++i) {
+            float x = xy[2 * i], y = xy[2 * i + 1];
+            if (x > xy[2 * right]) right = i;
+            if (y > xy[2 * top + 1]) top = i;
+            if (x < xy[2 * left]) left = i;
+            if (y < xy[2 * low + 1]) low = i;
+            float s = x + y;
+            float d = x - y;
+            if (i == lo || s > best_tr) { best_tr = s; tr = i; }
+            if (i == lo || -d > best_tl) { best_tl = -d; tl = i; }
+            if (i == lo || s < best_bl) { best_bl = s; bl = i; }
+            if (i == lo || d > best_br) { best_br = d; br = i; }
+        }
+        if (lo < hi) {
+            sidx[t][0] = right; sval[t][0] = xy[2 * right];
+            sidx[t][1] = top;   sval[t][1] = xy[2 * top + 1];
+            sidx[t][2] = left;  sval[t][2] = xy[2 * left];
+            sidx[t][3] = low;   sval[t][3] = xy[2 * low + 1];
+            sidx[t][4] = tr;    sval[t][4] = best_tr;
+            sidx[t][5] = tl;    sval[t][5] = best_tl;
+            sidx[t][6] = bl;    sval[t][6] = best_bl;
+            sidx[t][7] = br;    sval[t][7] = best_br;
+        }
+    }
+    /* merge: keys 0, 1, 4, 5, 7 are maxima, 2, 3, 6 minima; a later slice
+     * replaces the current choice only if strictly better */
+    uint64_t m_idx[8];
+    float m_val[8];
+    for (int k = 0; k < 8; ++k) { m_idx[k] = sidx[0][k]; m_val[k] = sval[0][k]; }
+    for (int t = 1; t < T; ++t) {
+        for (int k = 0; k < 8; ++k) {
+            int is_min = (k == 2 || k == 3 || k == 6);
+            int better = is_min ? (sval[t][k] < m_val[k]) : (sval[t][k] > m_val[k]);
+            if (better) { m_idx[k] = sidx[t][k]; m_val[k] = sval[t][k]; }
+        }
+    }
+    uint32_t idx[8] = {(uint32_t)m_idx[0], (uint32_t)m_idx[4], (uint32_t)m_idx[1], (uint32_t)m_idx[5],
+                       (uint32_t)m_idx[2], (uint32_t)m_idx[6], (uint32_t)m_idx[3], (uint32_t)m_idx[7]};
+    if (idx_out)
+        memcpy(idx_out, idx, sizeof idx);
+
+    /* edges exactly as in oracle_keep */
+    double ax[8], ay[8], bx[8], by[8];
+    int m = 0;
+    for (int j = 0; j < 8; ++j) {
+        float x0 = xy[2 * (uint64_t)idx[j]], y0 = xy[2 * (uint64_t)idx[j] + 1];
+        int k = (j + 1) % 8;
+        float x1 = xy[2 * (uint64_t)idx[k]], y1 = xy[2 * (uint64_t)idx[k] + 1];
+        if (x0 == x1 && y0 == y1)
+            continue;
+        ax[m] = x0; ay[m] = y0; bx[m] = x1; by[m] = y1;
+        ++m;
+    }
+#pragma omp parallel num_threads(T)
+    {
+        int t = omp_get_thread_num();
+        uint64_t lo = n * (uint64_t)t / (uint64_t)T, hi = n * (uint64_t)(t + 1) / (uint64_t)T;
+        uint64_t c = 0;
+        for (uint64_t i = lo; i < hi; ++i) {
+            double px = xy[2 * i], py = xy[2 * i + 1];
+            int inside_all = (m >= 1);
+            for (int e = 0; e < m; ++e)
+                if (!strictly_inside(ax[e], ay[e], bx[e], by[e], px, py))
+                    inside_all = 0;
+            keep[i] = inside_all ? 0 : 1;
+            c += keep[i];
+        }
+        cnt[t + 1] = c;
+#pragma omp barrier
+#pragma omp single
+        {
+            cnt[0] = 0;
+            for (int u = 1; u <= T; ++u) cnt[u] += cnt[u - 1];
+        }
+        uint64_t o = cnt[t];
+        for (uint64_t i = lo; i < hi; ++i)
+            if (keep[i])
+                surv[o++] = (uint32_t)i;
+    }
+    int64_t total = (int64_t)cnt[T];
+    free(sidx); free(sval); free(cnt); free(keep);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Related-work variant (Sec. 2): the 16-direction filter                   */
+/* ------------------------------------------------------------------------ */
+
+/* Sec. 2 describes a filter that finds 16 hull points by rotating the
+ * point set at three angles and discards the points inside their polygon.
+ * Reading taken here: the 16 directions are k * 22.5 degrees, k = 0..15
+ * (rotations by 22.5, 45 and 67.5 degrees, plus the unrotated axes; each
+ * rotation contributes min and max of both coordinates).  A rotation by
+ * angle a scaled by 1 / cos a keeps every argmax, so the key of direction
+ * (1, t) is x + t*y; with t = T = fl32(tan 22.5 deg) it is evaluated in FP32
+ * as one fused multiply-add (one rounding, like fl32(x+y)).  The even
+ * directions are the octagon's eight keys, so vertex 2j is octagon vertex
+ * E_j.  Vertex k maximises key_k below, first index on ties. */
+#define TAN_22_5_F32 0x1.a8279ap-2f
+
+static float key16(int k, float x, float y)
+{
+    const float T = TAN_22_5_F32;
+    switch (k) {
+    case 0: return x;                      /* 0 deg: max x            */
+    case 1: return fmaf(T, y, x);          /* 22.5: (1, T)            */
+    case 2: return x + y;                  /* 45                      */
+    case 3: return fmaf(T, x, y);          /* 67.5: (T, 1)            */
+    case 4: return y;                      /* 90                      */
+    case 5: return fmaf(-T, x, y);         /* 112.5: (-T, 1)          */
+    case 6: return -(x - y);               /* 135: fl32(y-x)          */
+    case 7: return fmaf(T, y, -x);         /* 157.5: (-1, T)          */
+    case 8: return -x;                     /* 180: min x              */
+    case 9: return -fmaf(T, y, x);         /* 202.5: min of key 1     */
+    case 10: return -(x + y);              /* 225: min fl32(x+y)      */
+    case 11: return -fmaf(T, x, y);        /* 247.5: min of key 3     */
+    case 12: return -y;                    /* 270: min y              */
+    case 13: return -fmaf(-T, x, y);       /* 292.5: min of key 5     */
+    case 14: return x - y;                 /* 315                     */
+    default: return -fmaf(T, y, -x);       /* 337.5: min of key 7     */
+    }
+}
+
+/* idx[0..15]: vertex k is the first point maximising key16(k, .). */
+void oracle_extremes16(const float *xy, uint64_t n, uint32_t idx[16])
+{
+    for (int k = 0; k < 16; ++k) {
+        uint64_t best_i = 0;
+        float best = key16(k, xy[0], xy[1]);
+        for (uint64_t i = 1; i < n; ++i) {
+            float v = key16(k, xy[2 * i], xy[2 * i + 1]);
+            if (v > best) { best = v; best_i = i; }
+        }
+        idx[k] = (uint32_t)best_i;
+    }
+}
+
+/* keep[i] = 1 if point i survives the polygon whose vertices are the points
+ * idx[0..k) in order: the rule of oracle_keep over the edges
+ * (idx[j], idx[(j+1) mod k]) whose end points differ. */
+void oracle_keep_poly(const float *xy, uint64_t n, const uint32_t *idx, int k,
+                      uint8_t *keep)
+{
+    double *ax = malloc(4 * sizeof(double) * (size_t)k);
+    double *ay = ax + k, *bx = ax + 2 * k, *by = ax + 3 * k;
+    int m = 0;
+    for (int j = 0; j < k; ++j) {
+        float x0 = xy[2 * (uint64_t)idx[j]], y0 = xy[2 * (uint64_t)idx[j] + 1];
+        int j1 = (j + 1) % k;
+        float x1 = xy[2 * (uint64_t)idx[j1]], y1 = xy[2 * (uint64_t)idx[j1] + 1];
+        if (x0 == x1 && y0 == y1)
+            continue;
+        ax[m] = x0; ay[m] = y0; bx[m] = x1; by[m] = y1;
+        ++m;
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        double px = xy[2 * i], py = xy[2 * i + 1];
+        int inside_all = (m >= 1);
+        for (int e = 0; e < m; ++e)
+            if (!strictly_inside(ax[e], ay[e], bx[e], by[e], px, py))
+                inside_all = 0;
+        keep[i] = inside_all ? 0 : 1;
+    }
+    free(ax);
+}
+
+/* Survivors of the 16-direction filter (ascending); returns the count, -2
+ * for a non-finite coordinate. */
+int64_t oracle_survivors16(const float *xy, uint64_t n, uint32_t *surv,
+                           uint32_t idx_out[16])
+{
+    if (oracle_validate(xy, n) != 0)
+        return -2;
+    if (n == 0)
+        return 0;
+    uint32_t idx[16];
+    oracle_extremes16(xy, n, idx);
+    if (idx_out)
+        memcpy(idx_out, idx, sizeof idx);
+    uint8_t *keep = (uint8_t *)malloc(n);
+    if (!keep)
+        return -4;
+    oracle_keep_poly(xy, n, idx, 16, keep);
+    int64_t c = 0;
+    for (uint64_t i = 0; i < n; ++i)
+        if (keep[i])
+            surv[c++] = (uint32_t)i;
+    free(keep);
+    return c;
+}
+
+/* out[i] = key of direction k of point i (exported for the key-level pins). */
+void oracle_key16_values(const float *xy, uint64_t n, int k, float *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = key16(k, xy[2 * i], xy[2 * i + 1]);
+}

@@ -41,9 +41,10 @@ def near_edges(base: np.ndarray, vertices: np.ndarray, per_edge: int, seed: int,
     float32), nudged by up to max_ulps units in x and/or y."""
     rng = np.random.default_rng(seed)
     V = base[vertices].astype(np.float64)
+    k = len(vertices)
     pts = []
-    for j in range(8):
-        a, b = V[j], V[(j + 1) % 8]
+    for j in range(k):
+        a, b = V[j], V[(j + 1) % k]
         t = rng.uniform(0.05, 0.95, per_edge)
         p = (a[None, :] * (1 - t)[:, None] + b[None, :] * t[:, None]).astype(np.float32)
         kx = rng.integers(-max_ulps, max_ulps + 1, per_edge)
@@ -73,6 +74,35 @@ def with_near_edge_points(base: np.ndarray, extremes_fn, per_edge: int = 200,
     ok = (_keys(extra) < top[None, :]).all(axis=1)
     xy = np.concatenate([base, extra[ok]], axis=0)
     assert np.array_equal(extremes_fn(xy), v)
+    return xy
+
+
+# binary32 nearest to tan(22.5 deg), as a float64 (the 16-direction keys)
+_T16 = float.fromhex("0x1.a8279ap-2")
+
+
+def _keys16_f64(xy: np.ndarray) -> np.ndarray:
+    """The 16 direction keys in float64 (construction only: used to keep
+    added points clear of every direction's maximum)."""
+    x = xy[:, 0].astype(np.float64)
+    y = xy[:, 1].astype(np.float64)
+    T = _T16
+    half = [x, x + T * y, x + y, T * x + y, y, -T * x + y, y - x, T * y - x]
+    return np.stack(half + [-h for h in half], axis=1)
+
+
+def with_near_edge_points16(base: np.ndarray, extremes16_fn, per_edge: int = 100,
+                            seed: int = 0, max_ulps: int = 3) -> np.ndarray:
+    """base plus points a few ulps either side of the 16 edges of the
+    16-direction polygon, leaving its vertices unchanged: a candidate is kept
+    only if its key is clearly below each direction's maximum."""
+    v = extremes16_fn(base)
+    extra = near_edges(base, v, per_edge, seed, max_ulps)
+    top = _keys16_f64(base)[v, np.arange(16)]
+    margin = 8.0 * np.spacing(np.abs(top).astype(np.float32)).astype(np.float64)
+    ok = (_keys16_f64(extra) < (top - margin)[None, :]).all(axis=1)
+    xy = np.concatenate([base, extra[ok]], axis=0)
+    assert np.array_equal(extremes16_fn(xy), v)
     return xy
 
 

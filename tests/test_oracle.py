@@ -275,3 +275,33 @@ def test_orient_exact_near_collinear(oracle_mod):
         b = (o + d * rng.uniform(0.1, 2)).astype(np.float32)
         b = cases.ulp_nudge(b, rng.integers(-1, 2, 2))
         assert oracle_mod.orient_exact(o, a, b) == brute.orient(o, a, b)
+
+
+def _tie_heavy(n: int, seed: int) -> np.ndarray:
+    """Every key attained many times across the array (so across slices)."""
+    rng = np.random.default_rng(seed)
+    xy = rng.integers(-5, 6, (n, 2)).astype(np.float32)
+    xy[rng.choice(n, n // 10, replace=False)] = (0.0, -0.0)
+    return xy
+
+
+@pytest.mark.parametrize("threads", [1, 2, 3, 8, 13])
+def test_all_core_filter_equals_one_thread(oracle_mod, threads):
+    """The OpenMP build of the filter (all-core CPU baseline) returns the
+    one-thread oracle's survivors and octagon, also when every extreme is
+    tied across slices (the slice merge keeps the first index)."""
+    sets = cases.named_sets(30_011, 29)
+    sets["ties"] = _tie_heavy(20_003, 3)
+    sets["tiny"] = workloads.normal(5, 2)
+    for name, xy in sets.items():
+        want = oracle_mod.survivors(xy)
+        got = oracle_mod.survivors_omp(xy, threads)
+        assert np.array_equal(got, want), (name, threads)
+
+
+def test_all_core_filter_nonfinite_and_empty(oracle_mod):
+    xy = workloads.normal(1000, 4)
+    xy[17, 0] = np.inf
+    with pytest.raises(oracle_mod.NonFiniteInput):
+        oracle_mod.survivors_omp(xy, 4)
+    assert oracle_mod.survivors_omp(np.zeros((0, 2), np.float32), 4).size == 0

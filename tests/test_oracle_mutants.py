@@ -39,6 +39,22 @@ MUTANTS = {
 }
 
 
+# the 16-direction filter (Sec. 2)
+MUTANTS16 = {
+    "tan_off_by_one_ulp": ("#define TAN_22_5_F32 0x1.a8279ap-2f", "#define TAN_22_5_F32 0x1.a8279cp-2f"),
+    "fma_split_in_two_roundings": ("case 1: return fmaf(T, y, x);", "case 1: return x + T * y;"),
+    "odd_vertices_swapped": ("case 3: return fmaf(T, x, y);          /* 67.5: (T, 1)            */\n"
+                             "    case 4: return y;",
+                             "case 3: return y;\n    case 4: return fmaf(T, x, y);"),
+    "min_taken_as_max": ("case 11: return -fmaf(T, x, y);", "case 11: return fmaf(T, x, y);"),
+    "rotation_sign": ("case 5: return fmaf(-T, x, y);", "case 5: return fmaf(T, x, -y);"),
+    "poly_edge_skips_a_vertex": ("int j1 = (j + 1) % k;", "int j1 = (j + 2) % k;"),
+    "poly_last_edge_dropped": ("    for (int j = 0; j < k; ++j) {\n        float x0",
+                               "    for (int j = 0; j < k - 1; ++j) {\n        float x0"),
+    "tie_last_occurrence16": ("if (v > best) { best = v; best_i = i; }", "if (v >= best) { best = v; best_i = i; }"),
+}
+
+
 def _build_mutant(tmp_path, name, old, new):
     src = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
     assert old in src, f"mutation anchor for {name} not found"
@@ -46,7 +62,7 @@ def _build_mutant(tmp_path, name, old, new):
     c = tmp_path / f"{name}.c"
     so = tmp_path / f"{name}.so"
     c.write_text(mut)
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-shared", "-fPIC",
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
                            "-o", str(so), str(c), "-lm"])
     return str(so)
 
@@ -100,9 +116,49 @@ def _pins_pass() -> bool:
         return False
 
 
+def _pins16_pass() -> bool:
+    """Fast subset of the 16-direction pins (tests/test_oracle16.py)."""
+    try:
+        rng = np.random.default_rng(1)
+        xy = np.concatenate([workloads.normal(120, 3),
+                             rng.integers(-2**20, 2**20, (60, 2)).astype(np.float32)]).astype(np.float32)
+        for k in range(16):
+            want = np.array([brute.key16_exact(k, a, b) for a, b in xy], dtype=np.float32)
+            if not np.array_equal(oracle.key16_values(xy, k), want):
+                return False
+        for seed in range(8):
+            xy = cases.named_sets(150, seed)["normal"] if seed % 2 else cases.small_integer_grid(80, 3, seed)
+            idx = oracle.extremes16(xy)
+            if idx.tolist() != brute.extremes16_exact(xy):
+                return False
+        for seed in range(12):
+            xy = cases.small_integer_grid(60, [2, 10, 1000][seed % 3], seed)
+            idx = oracle.extremes16(xy)
+            exact = [0 if brute.strictly_inside_poly_exact(xy, idx, i) else 1 for i in range(len(xy))]
+            if oracle.keep_poly(xy, idx).tolist() != exact:
+                return False
+        base = workloads.displaced(300, 3)
+        xy = cases.with_near_edge_points16(base, oracle.extremes16, per_edge=15, seed=1)
+        idx = oracle.extremes16(xy)
+        k = oracle.keep_poly(xy, idx)
+        E = brute.poly_edges(xy, idx)
+        for i in np.flatnonzero(k == 0):
+            p = (brute.exact_int(xy[i, 0]), brute.exact_int(xy[i, 1]))
+            if not all(brute.det_exact(a, b, p) > 0 for a, b in E):
+                return False
+        n = 200_000
+        h = set(oracle.hull(workloads.displaced(n, 4)).tolist())
+        if not h <= set(oracle.survivors16(workloads.displaced(n, 4)).tolist()):
+            return False
+        return True
+    except (AssertionError, RuntimeError, KeyError, IndexError):
+        return False
+
+
 def test_unmutated_oracle_passes_the_pins():
     oracle.build()
     assert _pins_pass()
+    assert _pins16_pass()
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -112,9 +168,29 @@ def test_pins_catch_mutant(tmp_path, monkeypatch, name):
     oracle.build()
     real = oracle._load()
     lib = ctypes.CDLL(so)
-    for fn in ("oracle_validate", "oracle_extremes", "oracle_keep", "oracle_survivors",
-               "oracle_hull", "oracle_orient_exact"):
-        getattr(lib, fn).argtypes = getattr(real, fn).argtypes
-        getattr(lib, fn).restype = getattr(real, fn).restype
+    _wire(lib, real)
     monkeypatch.setattr(oracle, "_lib", lib)
     assert not _pins_pass(), f"mutant {name} survived the pins"
+
+
+_FUNCS = ("oracle_validate", "oracle_extremes", "oracle_keep", "oracle_survivors", "oracle_hull",
+          "oracle_orient_exact", "oracle_extremes16", "oracle_keep_poly", "oracle_survivors16",
+          "oracle_key16_values")
+
+
+def _wire(lib, real):
+    for fn in _FUNCS:
+        getattr(lib, fn).argtypes = getattr(real, fn).argtypes
+        getattr(lib, fn).restype = getattr(real, fn).restype
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS16))
+def test_pins16_catch_mutant(tmp_path, monkeypatch, name):
+    old, new = MUTANTS16[name]
+    so = _build_mutant(tmp_path, name, old, new)
+    oracle.build()
+    real = oracle._load()
+    lib = ctypes.CDLL(so)
+    _wire(lib, real)
+    monkeypatch.setattr(oracle, "_lib", lib)
+    assert not _pins16_pass(), f"mutant {name} survived the pins"
