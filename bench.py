@@ -292,6 +292,9 @@ def run_bench(args):
             e2e[kind] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "hull_vertices": int(h.size)}
         result["e2e_hull"] = e2e
 
+    if not args.no_e2e:
+        result["filter16"] = bench_filter16(ctx, dpts, surv, cnt, [k for k, _, _ in sets], survivors, per_set)
+
     if not args.no_batched:
         result["batched"] = bench_batched(ctx, dev)
 
@@ -304,6 +307,9 @@ def run_bench(args):
     del dpts, surv
     torch.cuda.empty_cache()
 
+    if not args.no_e2e:
+        result["p_sweep_1e7"] = bench_p_sweep_1e7(dev)
+
     if not args.no_serving:
         result["serving"] = bench_serving(args)
 
@@ -311,6 +317,108 @@ def run_bench(args):
         log("[bench] timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(sets)
     return result
+
+
+def bench_filter16(ctx, dpts, surv, cnt, kinds, survivors8, per_set, reps: int = 5):
+    """The 16-direction filter of the related work (Sec. 2) on the three
+    1e8-point sets: hull_filter16 per set (median of `reps` calls, HIP
+    events), its survivors against the octagon filter's, and its
+    per-kernel times."""
+    import torch
+    stream = torch.cuda.current_stream()
+    res = {}
+    for i, kind in enumerate(kinds):
+        ms = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.hull_filter16(dpts[i], surv=surv[i], count=cnt[i], stream=stream)
+            b.record(stream)
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        c = int(cnt[i].item())
+        ctx.timing(True)
+        ctx.timing_read()
+        ctx.hull_filter16(dpts[i], surv=surv[i], count=cnt[i], stream=stream)
+        r = ctx.timing_read()
+        ctx.timing(False)
+        med = float(np.median(ms[1:]))
+        res[kind] = {"survivors": c, "octagon_survivors": survivors8[i],
+                     "discarded_pct": round(100.0 * (N_SET - c) / N_SET, 3),
+                     "octagon_discarded_pct": round(100.0 * (N_SET - survivors8[i]) / N_SET, 3),
+                     "hull_filter16_us": round(med * 1e3, 1), "Gpoints_s": round(N_SET / med / 1e6, 1),
+                     "octagon_device_us": round(N_SET / per_set[kind]["Gpoints_s"] / 1e3, 1),
+                     "kernels_us": {k: round(r[k][1] * 1e3, 1) for k in ("reduce", "setup", "filter", "compact")}}
+    # leave the octagon survivors in place for the legs that follow
+    for i in range(len(kinds)):
+        ctx.hull_filter(dpts[i], surv=surv[i], count=cnt[i], stream=stream)
+    torch.cuda.synchronize()
+    return res
+
+
+PSWEEP_P = (0.0, 0.02, 0.04, 0.06, 0.08, 0.10)
+
+
+def bench_p_sweep_1e7(dev, n: int = 10_000_000):
+    """The displacement sweep of Table 1 at 1e7 points (radius 1 + U[-p, p],
+    seed 8): discarded fraction, hull_filter time (median of 5, HIP events)
+    and convex_hull end to end on the GPU; the survivors and the hull are
+    compared with the oracle.  The oracle's hull of all points on one host
+    thread stands in for the paper's CPU hull (CGAL is not available), and
+    its hull of the GPU survivors gives the paper's column: CPU hull of all
+    points / (GPU filter + CPU hull of the survivors)."""
+    import torch
+    import oracle
+    from paper_2303_10581_amd import hullf, workloads
+    ctx = hullf.Context(0)
+    stream = torch.cuda.current_stream()
+    rows = []
+    try:
+        for p in PSWEEP_P:
+            xy = workloads.displaced(n, 8, p)
+            t = torch.from_numpy(xy).to(dev)
+            sv = torch.empty(n, dtype=torch.int32, device=dev)
+            c = torch.empty(1, dtype=torch.int64, device=dev)
+            ms = []
+            for _ in range(6):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                ctx.hull_filter(t, surv=sv, count=c, stream=stream)
+                b.record(stream)
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+            m = int(c.item())
+            got = sv[:m].cpu().numpy().astype(np.uint32)
+            want = oracle.survivors_omp(xy)
+            t1 = time.perf_counter()
+            h = ctx.convex_hull(t)
+            gpu_hull_ms = (time.perf_counter() - t1) * 1e3
+            t1 = time.perf_counter()
+            h_all = oracle.hull(xy)
+            cpu_all_s = time.perf_counter() - t1
+            t1 = time.perf_counter()
+            h_surv = oracle.hull(xy, got)
+            cpu_surv_s = time.perf_counter() - t1
+            f_ms = float(np.median(ms[1:]))
+            row = {"p": p, "discarded_pct": round(100.0 * (n - m) / n, 2),
+                   "hull_filter_ms": round(f_ms, 3), "Gpoints_s": round(n / f_ms / 1e6, 1),
+                   "convex_hull_ms": round(gpu_hull_ms, 2), "hull_vertices": int(h.size),
+                   "survivors_match_oracle": bool(np.array_equal(got, want)),
+                   "hull_match_oracle": bool(np.array_equal(h, h_all) and np.array_equal(h_surv, h_all)),
+                   "cpu_hull_all_s": round(cpu_all_s, 3), "cpu_hull_survivors_s": round(cpu_surv_s, 3),
+                   "speedup_filter_plus_cpu_hull": round(cpu_all_s / (f_ms / 1e3 + cpu_surv_s), 2),
+                   "speedup_gpu_convex_hull": round(cpu_all_s / (gpu_hull_ms / 1e3), 1)}
+            if p in PAPER_TABLE1_DISCARD_PCT:
+                row["paper_discarded_pct"] = PAPER_TABLE1_DISCARD_PCT[p]
+            rows.append(row)
+            log(f"[bench] p-sweep 1e7 p={p}: {row}")
+            del t, sv
+            torch.cuda.empty_cache()
+    finally:
+        ctx.close()
+    return {"workload": f"displaced circumference, n={n}, radius 1 + U[-p, p], seed 8",
+            "cpu_hull": "oracle monotone chain with exact orientation, one host thread (stand-in for the "
+                        "paper's CGAL hull)", "rows": rows}
 
 
 def bench_small(ctx, dev, reps: int = 50):
@@ -419,8 +527,11 @@ def bench_library_compaction(ctx, dpts, surv, cnt, kinds, reps: int = 5):
 
 
 def bench_batched(ctx, dev):
-    """4096 sets, log-uniform sizes in [100, 1e6], kinds mixed: one persistent
-    launch (HIP graph) against 4096 plain hull_filter launches."""
+    """4096 sets, log-uniform sizes in [100, 1e6], kinds mixed: one graph of
+    persistent launches against 4096 plain hull_filter launches.  The
+    autotuner picks the inside-test shape on this batch first (and stores
+    it in the context's tune cache); the graph then runs that shape.  Both
+    paths write every set's survivors, compared in full, set by set."""
     import torch
     from paper_2303_10581_amd import workloads
     t0 = time.time()
@@ -432,6 +543,7 @@ def bench_batched(ctx, dev):
     surv = torch.empty(pts.shape[0], dtype=torch.int32, device=dev)
     counts = torch.empty(S, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
+    tb, tpp, tms = ctx.autotune_batched(tp, to, surv, counts, reps=3, stream=stream)
     ctx.hull_filter_batched(tp, to, surv=surv, counts=counts, stream=stream)
     torch.cuda.synchronize()
     reps = 5
@@ -440,32 +552,40 @@ def bench_batched(ctx, dev):
         ctx.hull_filter_batched(tp, to, surv=surv, counts=counts, stream=stream)
     torch.cuda.synchronize()
     b_ms = (time.perf_counter() - t0) * 1e3 / reps
-    # plain per-set launches on the same GPU
+    # plain per-set launches on the same GPU, into a second survivor array
     offs = off.tolist()
+    surv2 = torch.empty_like(surv)
     views = [tp[offs[s]:offs[s + 1]] for s in range(S)]
     c1 = torch.empty(S, dtype=torch.int64, device=dev)
     for s in range(S):
-        ctx.hull_filter(views[s], surv=surv[offs[s]:], count=c1[s:s + 1], cap=offs[s + 1] - offs[s],
+        ctx.hull_filter(views[s], surv=surv2[offs[s]:], count=c1[s:s + 1], cap=offs[s + 1] - offs[s],
                         stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(S):
-        ctx.hull_filter(views[s], surv=surv[offs[s]:], count=c1[s:s + 1], cap=offs[s + 1] - offs[s],
+        ctx.hull_filter(views[s], surv=surv2[offs[s]:], count=c1[s:s + 1], cap=offs[s + 1] - offs[s],
                         stream=stream)
     torch.cuda.synchronize()
     p_ms = (time.perf_counter() - t0) * 1e3
-    same = bool(torch.equal(counts, c1))
+    cb, cp = counts.cpu().numpy(), c1.cpu().numpy()
+    a, b = surv.cpu().numpy(), surv2.cpu().numpy()
+    same = bool(np.array_equal(cb, cp)) and all(
+        np.array_equal(a[offs[s]:offs[s] + int(cb[s])], b[offs[s]:offs[s] + int(cb[s])]) for s in range(S))
+    del surv2
     n = int(pts.shape[0])
     return {
         "workload": "4096 sets, sizes log-uniform [1e2, 1e6], kinds uniform, seed 6",
         "points": n,
+        "autotuned_shape": {"block": tb, "ppt": tpp, "ms": round(tms, 3)},
         "batched_ms": round(b_ms, 3),
-        "batched_hulls_per_s": round(S / (b_ms / 1e3), 1),
+        "sets_filtered_per_s": round(S / (b_ms / 1e3), 1),
         "batched_Gpoints_s": round(n / b_ms / 1e6, 1),
         "per_set_launch_ms": round(p_ms, 3),
-        "per_set_hulls_per_s": round(S / (p_ms / 1e3), 1),
+        "per_set_sets_filtered_per_s": round(S / (p_ms / 1e3), 1),
         "speedup": round(p_ms / b_ms, 2),
-        "counts_match": same,
+        "survivors_match_per_set": same,
+        "note": "filter and compaction only (Algorithm 1 without the hull step); hulls of these sets are "
+                "compared with the oracle in the GPU tests",
     }
 
 
@@ -519,6 +639,26 @@ def _serve(srv, pool, times, order):
     return lat, res, wall
 
 
+def _stages(res):
+    """p50/p99 (ms) of each stage of the served requests' timelines:
+    admit (submit -> slot and arena region), copy (-> resident), wait
+    (-> its batch launched), filter (-> batch finished), finish (-> hull);
+    and, for the slowest 1 % of requests, the mean share of each stage."""
+    keys = ("admitted_us", "resident_us", "launched_us", "filtered_us", "done_us")
+    names = ("admit", "copy", "wait", "filter", "finish")
+    t = np.array([[r[1][k] for k in keys] for r in res], dtype=np.float64)
+    d = np.diff(np.concatenate([np.zeros((t.shape[0], 1)), t], axis=1), axis=1) / 1e3
+    out = {nm: {"p50": round(float(np.percentile(d[:, i], 50)), 3), "p99": round(float(np.percentile(d[:, i], 99)), 3)}
+           for i, nm in enumerate(names)}
+    slow = d[t[:, 4] >= np.percentile(t[:, 4], 99)]
+    tot = slow.sum(axis=1, keepdims=True)
+    share = (slow / np.maximum(tot, 1e-9)).mean(axis=0)
+    out["slowest_1pct_share"] = {nm: round(float(share[i]), 3) for i, nm in enumerate(names)}
+    sizes = np.array([r[1]["n"] for r in res])
+    out["slowest_1pct_mean_points"] = int(sizes[t[:, 4] >= np.percentile(t[:, 4], 99)].mean())
+    return out
+
+
 def bench_serving(args):
     """Serving: hull requests (sizes log-uniform in [1e3, 1e7], kinds mixed)
     through the request loop.  A burst of every pool request at once gives
@@ -557,6 +697,7 @@ def bench_serving(args):
         cap = len(pool) / wall
         same = all(np.array_equal(res[k][0], base_hulls[k]) for k in range(len(pool)))
         out["capacity_hulls_per_s"] = round(cap, 1)
+        out["burst_stages_ms"] = _stages(res)
         out["burst"] = {"requests": len(pool), "wall_s": round(wall, 3),
                         "p50_ms": round(float(np.percentile(lat, 50)), 2),
                         "p99_ms": round(float(np.percentile(lat, 99)), 2)}
@@ -570,6 +711,7 @@ def bench_serving(args):
             st0 = srv.stats()
             lat, res, wall = _serve(srv, pool, times, order)
             st1 = srv.stats()
+            stages = _stages(res)
             same = same and all(np.array_equal(res[k][0], base_hulls[order[k]]) for k in range(m))
             nb = st1["batches"] - st0["batches"]
             runs.append({
@@ -579,6 +721,7 @@ def bench_serving(args):
                 "hulls_per_s": round(m / wall, 1),
                 "mean_batch_requests": round((st1["batched_requests"] - st0["batched_requests"]) / max(nb, 1), 2),
                 "gpu_busy_frac": round((st1["batch_ms"] - st0["batch_ms"]) / 1e3 / wall, 4),
+                "stages_ms": stages,
             })
             log(f"[bench] serving at {qps:.1f} qps: p50 {runs[-1]['p50_ms']} ms p99 {runs[-1]['p99_ms']} ms")
         out["runs"] = runs
@@ -649,8 +792,10 @@ def traffic_summary(fetch_dir, write_dir, out_path=TRAFFIC_JSON):
     so that bench.py reports it only while the kernels are unchanged."""
     def kind(name):
         for k in ("k_reduce", "k_setup", "k_classify", "k_compact"):
-            if "::" + k in name or name.startswith(k):
-                return k
+            for head in ("::" + k, k):
+                at = name.find(head)
+                if at >= 0 and (head != k or at == 0) and name[at + len(head):at + len(head) + 1] in ("<", "("):
+                    return k
         return None
 
     out = {"kernel_sha": kernel_hash(), "bytes_per_dispatch": {}, "by_kernel": {}}

@@ -96,7 +96,10 @@ typedef enum {
  *   HULLF_CLASSIFY_PER_CU=k       inside-test blocks per compute unit
  *   HULLF_COMPACT_BLOCK=b         compaction block size (256|512|1024)
  *   HULLF_REDUCE_GRID=g           reduction blocks, 1..4096 (default 8 per CU)
- *   HULLF_FINISH=host             hull finishing always on the host */
+ *   HULLF_FINISH=host             hull finishing always on the host
+ *   HULLF_TUNE_CACHE=path         tune cache file of the batched launch
+ *                                 (default $XDG_CACHE_HOME/hullf/tune.txt or
+ *                                 ~/.cache/hullf/tune.txt; empty: none) */
 hullf_status hullf_create(int device, size_t workspace_bytes, hullf_ctx_t *out);
 
 /* Release the context and its device memory.  NULL is ignored. */
@@ -141,11 +144,31 @@ hullf_status convex_hull(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
  * (otherwise HULLF_EINVAL).  h_hull / cap / h_count as for convex_hull: the
  * hull of the listed points, by indices into d_pts; of repeated
  * coordinates the first listed index is kept.  From 2^18 survivors on the
- * points are sorted and reduced by chunked monotone chains on the device,
- * and only the remaining candidates are chained on the host. */
+ * points are sorted, reduced by chunked monotone chains and the chunk
+ * chains merged on the device; only the lower and upper hull chains are
+ * copied back. */
 hullf_status hull_from_survivors(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
                                  const uint32_t *d_surv, uint64_t m, uint32_t *h_hull,
                                  uint64_t cap, uint64_t *h_count, void *stream);
+
+/* The 16-direction filter of the related work (Sec. 2): 16 extreme points
+ * of the point set rotated at three angles, then the points strictly inside
+ * their polygon discarded.  Directions k * 22.5 degrees, k = 0..15,
+ * counter-clockwise from +x; vertex k maximises key k, the first index on
+ * ties:  key k = line k and key k+8 = -(line k) for k < 8, with
+ *   line 0 = x, 1 = fma(T, y, x), 2 = fl32(x+y), 3 = fma(T, x, y), 4 = y,
+ *   5 = fma(-T, x, y), 6 = fl32(y-x), 7 = fma(T, y, -x),
+ * T = fl32(tan 22.5 deg) = 0x1.a8279ap-2, each fma rounded once.  The even
+ * vertices are the octagon's E0..E7.  The inside test is the rule above
+ * over the 16 edges (V_k, V_k+1) whose end points differ.
+ * hullf_polygon16: vertices V0..V15 (host array), synchronous; errors as
+ * hullf_octagon.  hull_filter16: survivors and count as hull_filter,
+ * asynchronous. */
+hullf_status hullf_polygon16(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
+                             uint32_t idx_out[16], void *stream);
+hullf_status hull_filter16(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
+                           uint32_t *d_surv, uint64_t cap, uint64_t *d_count,
+                           void *stream);
 
 /* Debug export of the bit vector of Sec. 3.2 (one byte per point, 1 =
  * survives), asynchronous.  d_flags: n device bytes.  If a coordinate is not
@@ -195,6 +218,12 @@ hullf_status hull_filter_batched_shape(hullf_ctx_t ctx, const hullf_pt *d_pts,
 /* Autotuner: time every supported (block, ppt) shape of the batched kernel
  * on the given batch (`reps` launches each, after one warm-up), keep the
  * fastest in the context for later batched calls, and report it.
+ * The choice is also stored in the tune cache under the batch's class
+ * (architecture, CU count, floor(log2 S), floor(log2 of the mean set size))
+ * and persisted to the cache file, which contexts read at creation: a later
+ * batched call of the same class uses that shape (in this and later
+ * processes).  The kind of point distribution is not part of the key: the
+ * library cannot know it before the batch is filtered.
  * best_block / best_ppt / best_ms may be NULL.  Synchronous. */
 hullf_status hullf_autotune_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
                                     const uint64_t *d_off, uint32_t S,

@@ -10,6 +10,10 @@
 //                  chunk (positions into the sorted sequence)
 //   k_scan_counts  exclusive scan of the chunk chain lengths (one block)
 //   k_chain_gather the chain vertices of all chunks, in order
+//   k_bridge       merge tree over the chunk chains: the bridge of each pair
+//                  of adjacent chains (one wave per pair)
+//   k_merge_gather the merged chains (prefix of the left chain up to the
+//                  bridge, suffix of the right one from it), in order
 //
 // Why chunks are enough: a point that is not a vertex of its chunk's lower
 // chain lies on or above a segment between two points of the chunk, so it
@@ -312,6 +316,7 @@ __device__ __forceinline__ int orient_dev(float ox, float oy, float ax, float ay
 // equals its predecessor's (the first level only; later levels have no
 // repeats).
 constexpr uint32_t kChainMaxC = 256;   // a stack entry is a one-byte offset into the chunk
+constexpr uint32_t kChainPrefetch = 16;   // keys loaded together
 
 __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys, uint32_t m, uint32_t C, int sign,
                                               int dedup, uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
@@ -328,28 +333,39 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
     float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f;   // top (2) and below-top (1) of the stack
     uint64_t prev = (b > 0) ? keys[b - 1] : 0ull;
     bool have_prev = b > 0;
-    for (uint32_t i = b; i < e; ++i) {
-        const uint64_t k = keys[i];
-        if (dedup && have_prev && k == prev) continue;
-        prev = k;
-        have_prev = true;
-        const float x = key_x(k), y = key_y(k);
-        while (len >= 2 && orient_dev(x1, y1, x2, y2, x, y) * sign <= 0) {
-            --len;
-            x2 = x1;
-            y2 = y1;
-            if (len >= 2) {
-                const uint64_t kb = keys[b + st[64u * (len - 2)]];
-                x1 = key_x(kb);
-                y1 = key_y(kb);
+    // The chunk's keys are read kChainPrefetch at a time, all loads issued
+    // before the first is used: one memory round trip per batch instead of
+    // one per point (the stack pops below mostly hit the cache).
+    for (uint32_t i0 = b; i0 < e; i0 += kChainPrefetch) {
+        uint64_t kb[kChainPrefetch];
+#pragma unroll
+        for (uint32_t u = 0; u < kChainPrefetch; ++u) kb[u] = (i0 + u < e) ? keys[i0 + u] : 0ull;
+#pragma unroll
+        for (uint32_t u = 0; u < kChainPrefetch; ++u) {
+            const uint32_t i = i0 + u;
+            if (i >= e) break;
+            const uint64_t k = kb[u];
+            if (dedup && have_prev && k == prev) continue;
+            prev = k;
+            have_prev = true;
+            const float x = key_x(k), y = key_y(k);
+            while (len >= 2 && orient_dev(x1, y1, x2, y2, x, y) * sign <= 0) {
+                --len;
+                x2 = x1;
+                y2 = y1;
+                if (len >= 2) {
+                    const uint64_t kp = keys[b + st[64u * (len - 2)]];
+                    x1 = key_x(kp);
+                    y1 = key_y(kp);
+                }
             }
+            st[64u * len] = (uint8_t)(i - b);
+            ++len;
+            x1 = x2;
+            y1 = y2;
+            x2 = x;
+            y2 = y;
         }
-        st[64u * len] = (uint8_t)(i - b);
-        ++len;
-        x1 = x2;
-        y1 = y2;
-        x2 = x;
-        y2 = y;
     }
     uint32_t* o = out + (uint64_t)b;
     for (uint32_t j = 0; j < len; ++j) o[j] = b + st[64u * j];
@@ -425,6 +441,117 @@ __global__ __launch_bounds__(256) void k_chain_gather(const uint64_t* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// merge tree of chains
+// ---------------------------------------------------------------------------
+// Chains c = 0..nc-1 occupy [off[c], off[c+1]) of the key array, each a
+// strict lower (sign 1) or upper (sign -1) chain of consecutive points of
+// the sorted sequence, so every point of chain 2p precedes every point of
+// chain 2p+1.  The hull of their union is a prefix A[0..i*] of the left
+// chain A followed by a suffix B[j*..] of the right chain B (the bridge).
+// With s(a, b, c) = sign * orient(a, b, c):
+//   tangent from a point q before B: t(q) = the first j with
+//     s(q, B[j], B[j+1]) > 0 (else the last index) -- the slopes from q to
+//     the vertices of the convex chain B fall and then rise, and t(q) is the
+//     last vertex of least slope, so B points collinear with q and B[t(q)]
+//     lie between them and are not strict vertices;
+//   i* = the first i with s(A[i], B[t(A[i])], A[i+1]) >= 0 (else the last
+//     index): left of i* the next vertex of A lies strictly below the
+//     tangent line (A[i+1] is a hull vertex), from i* on it does not, and
+//     the first such i is the left end of the bridge when several A points
+//     lie on it;
+//   j* = t(A[i*]).
+// Both searches are over monotone predicates.  The tangent search is
+// wave-parallel (64 samples per step); the search over A is a binary search
+// whose steps each run one tangent search.
+__device__ __forceinline__ int orient_keys(uint64_t a, uint64_t b, uint64_t c) {
+    return orient_dev(key_x(a), key_y(a), key_x(b), key_y(b), key_x(c), key_y(c));
+}
+
+// First j in [0, lb) with j == lb - 1 or s(q, B[j], B[j+1]) > 0 (lb >= 1);
+// every lane returns it.
+__device__ __forceinline__ uint32_t tangent_from(const uint64_t* __restrict__ B, uint32_t lb, uint64_t q, int sign) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t lo = 0, hi = lb - 1;   // the answer is in [lo, hi]; the predicate holds at hi
+    while (hi > lo) {
+        const uint32_t n = hi - lo;
+        const uint32_t step = (n + 63u) / 64u;
+        const uint32_t at = lo + (lane + 1u) * step - 1u;   // lane samples: the last one reaches hi - 1
+        bool v = true;
+        if (at < hi) v = orient_keys(q, B[at], B[at + 1u]) * sign > 0;
+        const unsigned long long m = __ballot(v);
+        if (m == 0ull) {   // every sample (up to hi - 1) fails: the answer is hi
+            lo = hi;
+            break;
+        }
+        const uint32_t f = (uint32_t)(__ffsll((long long)m) - 1);
+        const uint32_t af = lo + (f + 1u) * step - 1u;
+        const uint32_t nlo = (f == 0u) ? lo : lo + f * step;   // one past the previous sample
+        hi = min(af, hi);
+        lo = nlo;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_bridge(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ off,
+                                                uint32_t nc, int sign, uint2* __restrict__ br,
+                                                uint32_t* __restrict__ len) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t np = (nc + 1u) / 2u;
+    for (uint32_t p = blockIdx.x * 4u + (threadIdx.x >> 6); p < np; p += gridDim.x * 4u) {
+        const uint32_t a0 = off[2u * p], a1 = off[2u * p + 1u];
+        const uint32_t b1 = (2u * p + 1u < nc) ? off[2u * p + 2u] : a1;
+        const uint32_t la = a1 - a0, lb = b1 - a1;
+        uint32_t keep = la, j = 0;   // A[0..keep) ++ B[j..lb)
+        if (la > 0u && lb > 0u) {
+            const uint64_t* A = keys + a0;
+            const uint64_t* B = keys + a1;
+            uint32_t lo = 0, hi = la - 1u;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) / 2u;
+                const uint64_t am = A[mid];
+                const uint32_t t = tangent_from(B, lb, am, sign);
+                if (orient_keys(am, B[t], A[mid + 1u]) * sign >= 0) hi = mid;
+                else lo = mid + 1u;
+            }
+            keep = lo + 1u;
+            j = tangent_from(B, lb, A[lo], sign);
+        }
+        if (lane == 0u) {
+            br[p] = make_uint2(keep, j);
+            len[p] = keep + (lb - j);
+        }
+    }
+}
+
+// The merged chains in order: pair p's chain goes to noff[p].
+__global__ __launch_bounds__(256) void k_merge_gather(const uint64_t* __restrict__ keys,
+                                                      const uint32_t* __restrict__ vals,
+                                                      const uint32_t* __restrict__ off, uint32_t nc,
+                                                      const uint2* __restrict__ br,
+                                                      const uint32_t* __restrict__ noff, uint64_t* __restrict__ kout,
+                                                      uint32_t* __restrict__ vout) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t np = (nc + 1u) / 2u;
+    for (uint32_t p = blockIdx.x * 4u + (threadIdx.x >> 6); p < np; p += gridDim.x * 4u) {
+        const uint32_t a0 = off[2u * p], a1 = off[2u * p + 1u];
+        const uint32_t b1 = (2u * p + 1u < nc) ? off[2u * p + 2u] : a1;
+        const uint2 r = br[p];
+        const uint32_t o = noff[p];
+        for (uint32_t k = lane; k < r.x; k += 64u) {
+            kout[o + k] = keys[a0 + k];
+            vout[o + k] = vals[a0 + k];
+        }
+        const uint32_t nb = (b1 - a1) - r.y;
+        for (uint32_t k = lane; k < nb; k += 64u) {
+            kout[o + r.x + k] = keys[a1 + r.y + k];
+            vout[o + r.x + k] = vals[a1 + r.y + k];
+        }
+    }
+}
+
+__global__ void k_copy_u32(uint32_t* dst, const uint32_t* src) { *dst = *src; }
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -478,6 +605,24 @@ hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint3
                                uint32_t* vout, int grid, hipStream_t stream) {
     hipLaunchKernelGGL(k_chain_gather, dim3(grid), dim3(256), 0, stream, keys, vals, m, C, chain, off, total, kout,
                        vout);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, hipStream_t stream) {
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, stream, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_bridge(const uint64_t* keys, const uint32_t* off, uint32_t nc, int sign, uint2* br, uint32_t* len,
+                         int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(k_bridge, dim3(grid), dim3(256), 0, stream, keys, off, nc, sign, br, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_gather(const uint64_t* keys, const uint32_t* vals, const uint32_t* off, uint32_t nc,
+                               const uint2* br, const uint32_t* noff, uint64_t* kout, uint32_t* vout, int grid,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(k_merge_gather, dim3(grid), dim3(256), 0, stream, keys, vals, off, nc, br, noff, kout, vout);
     return hipGetLastError();
 }
 

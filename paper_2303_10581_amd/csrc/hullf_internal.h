@@ -7,35 +7,40 @@
 
 namespace hullf {
 
-// Octagon record computed on the device from the eight extremes (Sec. 3.1)
-// and read by every inside-test kernel (Sec. 3.2).
+// Polygon record computed on the device from the NV extremes and read by
+// every inside-test kernel (Sec. 3.2).  NV = 8: the octagon of Sec. 3.1;
+// NV = 16: the 16-direction polygon of the related-work filter (Sec. 2).
 //
-// Edges: the non-degenerate directed edges (E_j, E_j+1) in binary64
+// Edges: the non-degenerate directed edges (V_j, V_j+1) in binary64
 // (vertex a, difference b-a); unused slots repeat edge 0 so that loops can
-// always run over 8 entries.
+// always run over NV entries.
 // Prefilter (fast == 1): for each edge, FP32 coefficients of the edge line
 // scaled by a power of two s_e so that the FP32 evaluation
 //   d_e = fma(A, y - cy, fma(NB, x - cx, C0))
 // is within 0.5 of s_e times the exact edge value (see setup_octagon).
 // Quick-accept box (bxl < x < bxh, byl < y < byh): every point inside it is
 // discarded by the binary64 rule; empty when bxl > bxh.
-struct alignas(16) Octagon {
-    uint32_t idx[8];
+// The four status words come first, at the same offsets for every NV.
+template <int NV>
+struct alignas(16) Poly {
     int32_t status;   // 0 ok, 1 non-finite input, 3 internal error (no candidate)
     int32_t mode;     // 0 keep every point (fewer than 3 distinct vertices), 1 test
     int32_t fast;     // FP32 prefilter usable
     int32_t m;        // number of non-degenerate edges
+    uint32_t idx[NV];
     float bxl, bxh, byl, byh;
     float cx, cy, pad0, pad1;
-    float A[8], NB[8], C0[8];
-    double ax[8], ay[8], ex[8], ey[8];
+    float A[NV], NB[NV], C0[NV];
+    double ax[NV], ay[NV], ex[NV], ey[NV];
     // Region skip (skip == 1): a box whose four corners all have binary64
     // edge values above sm[e] on every edge lies strictly inside the rule's
     // discard region, with the margin of the quick-accept box proof.
-    double sm[8];
+    double sm[NV];
     int32_t skip;
     int32_t pad2[3];
 };
+using Octagon = Poly<8>;
+using Poly16 = Poly<16>;
 
 // Per-set bookkeeping of the batched launch (written by the plan kernel).
 struct alignas(16) SetInfo {
@@ -118,6 +123,24 @@ hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t
                           const Octagon* oct, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,
                           hipStream_t stream);
 
+// The 16-direction filter (Sec. 2, related work): reduction of the 16
+// directional keys (17 partial words per block, direction-major:
+// part[j * kReduceMaxGrid + b], plus boxes as launch_reduce), the polygon
+// set-up, and the inside test / compaction over its edges (same spans,
+// keep bits and block counts as the octagon's launches).
+constexpr int kPart16Words = 17;
+hipError_t launch_reduce16(const float2* pts, uint64_t n, unsigned long long* part, float4* box, int grid,
+                           hipStream_t stream);
+int reduce16_grid(uint64_t n, int cus);
+hipError_t launch_setup16(const float2* pts, uint64_t n, Poly16* poly, const unsigned long long* part,
+                          uint32_t nblocks, hipStream_t stream);
+hipError_t launch_classify(const float2* pts, uint64_t n, const Poly16* poly, uint32_t spans, uint64_t* bits,
+                           uint32_t* blkcnt, const float4* box, uint64_t nbox, unsigned long long* loaded,
+                           Shape shape, int grid, hipStream_t stream);
+hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
+                          const Poly16* poly, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,
+                          hipStream_t stream);
+
 // Batched: plan, reduction, octagon set-up, classify and compact (five
 // launches).  part: 9 * max_rtiles uint64 scratch.  off: S+1 CSR offsets,
 // or (seg) S (begin, count) pairs, ascending and disjoint.  bits holds
@@ -149,6 +172,18 @@ hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, u
 hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, int dedup, uint32_t* chain,
                         uint32_t* cnt, hipStream_t stream);
 hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, hipStream_t stream);
+// Merge tree over chains c < nc at [off[c], off[c+1]) (off holds nc + 1
+// words): pair p = chains 2p, 2p+1 (the last one alone when nc is odd).
+// launch_bridge writes br[p] = (points kept of the left chain, first point
+// kept of the right one) and len[p] = the merged length; after an exclusive
+// scan of len into noff (np + 1 words, the total last), launch_merge_gather
+// writes the merged chains.
+hipError_t launch_bridge(const uint64_t* keys, const uint32_t* off, uint32_t nc, int sign, uint2* br, uint32_t* len,
+                         int grid, hipStream_t stream);
+hipError_t launch_merge_gather(const uint64_t* keys, const uint32_t* vals, const uint32_t* off, uint32_t nc,
+                               const uint2* br, const uint32_t* noff, uint64_t* kout, uint32_t* vout, int grid,
+                               hipStream_t stream);
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, hipStream_t stream);
 hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint32_t m, uint32_t C,
                                const uint32_t* chain, const uint32_t* off, uint32_t total, uint64_t* kout,
                                uint32_t* vout, int grid, hipStream_t stream);

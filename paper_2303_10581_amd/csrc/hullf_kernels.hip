@@ -18,6 +18,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "hullf_internal.h"
 
@@ -178,6 +179,32 @@ __device__ __forceinline__ float key_select(int j, float x, float y) {
     const float a = (m == 2) ? 0.0f : x;
     const float b = (m == 0) ? 0.0f : ((m == 3) ? -y : y);
     return a + b;
+}
+
+// The 16-direction filter of the related work (Sec. 2) rotates the points
+// at three angles; its 16 directions are k * 22.5 degrees counter-clockwise
+// from +x.  A rotation scaled by 1 / cos keeps every argmax, so the key of
+// direction (1, t) is x + t*y, and with t = T = fl32(tan 22.5 deg) it is one
+// fused multiply-add (one rounding, like fl32(x+y)).  Eight lines carry the
+// 16 keys: key k (k < 8) is line k and key k + 8 its negation, which is
+// exact, so the maximiser of key k + 8 is the minimiser of line k.  The even
+// keys are the octagon's: x, fl32(x+y), y, fl32(y-x) and their negations.
+constexpr float kTan22_5 = 0x1.a8279ap-2f;
+__device__ __forceinline__ float line16(int k, float x, float y) {
+    switch (k & 7) {
+        case 0: return x;
+        case 1: return fmaf(kTan22_5, y, x);
+        case 2: return x + y;
+        case 3: return fmaf(kTan22_5, x, y);
+        case 4: return y;
+        case 5: return fmaf(-kTan22_5, x, y);
+        case 6: return y - x;
+        default: return fmaf(kTan22_5, y, -x);
+    }
+}
+__device__ __forceinline__ float key16(int k, float x, float y) {
+    const float v = line16(k, x, y);
+    return k < 8 ? v : -v;
 }
 
 // IEEE-754 2019 maximum/minimum (NaN-propagating) lower to gfx950's
@@ -485,21 +512,29 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
 // 2^-48 M = 32 e M on every edge.  Edge values are affine, so every point of
 // the box then has D > 27 e M > 7.01 e M and the rule discards it.
 
-// Executed by all 64 lanes of one wave; lane l works on vertex/edge l & 7,
-// and lanes 0..31 check one (edge, box corner) pair each.
-// `p` is the merged packed key of direction lane & 7 (0 if none), `nf` the
-// merged NaN flag; `known`, if not null, holds the 8 vertices' coordinates
-// (else they are read from pts).
+// Executed by all 64 lanes of one wave; lane l works on vertex/edge
+// l mod NV, and lanes below 4*NV check one (edge, box corner) pair each.
+// The NV vertices are counter-clockwise from the maximum of x, at equal
+// angular steps of their directions, so vertex 0 is max x, NV/4 max y, NV/2
+// min x, 3NV/4 min y, and the odd multiples of NV/8 are the four diagonal
+// (octagon corner) directions.
+// `p` is the merged packed key of direction lane mod NV (0 if none), `nf`
+// the merged NaN flag; `known`, if not null, holds the NV vertices'
+// coordinates (else they are read from pts).
 // Returns the status it wrote (0 ok, 1 non-finite, 3 internal), uniform.
+template <int NV>
 __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uint64_t lo, uint64_t n,
-                                             unsigned long long p, uint32_t nf, Octagon* o,
+                                             unsigned long long p, uint32_t nf, Poly<NV>* o,
                                              const float2* known = nullptr) {
 #pragma clang fp contract(off)
+    static_assert(NV == 8 || NV == 16, "octagon or 16-gon");
+    constexpr uint32_t VM = NV - 1;
+    constexpr unsigned long long VMASK = (1ull << NV) - 1ull;
     const uint32_t lane = lane_id();
-    const int j = (int)(lane & 7u);
+    const int j = (int)(lane & VM);
     const uint32_t id = unpack_idx(p);
     const bool miss = (p == 0ull) || ((uint64_t)id >= n);
-    if (lane < 8) o->idx[j] = id;
+    if (lane < NV) o->idx[j] = id;
     if (lane == 0) {
         o->mode = 0;
         o->fast = 0;
@@ -517,23 +552,23 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
     }
     const float2 q = known ? known[j] : pts[lo + id];
     const float vx = q.x, vy = q.y;
-    // bounding box: E0 max x, E4 min x, E2 max y, E6 min y
-    const float xmax = __shfl(vx, 0, 64), xmin = __shfl(vx, 4, 64);
-    const float ymax = __shfl(vy, 2, 64), ymin = __shfl(vy, 6, 64);
+    // bounding box: vertex 0 max x, NV/2 min x, NV/4 max y, 3NV/4 min y
+    const float xmax = __shfl(vx, 0, 64), xmin = __shfl(vx, NV / 2, 64);
+    const float ymax = __shfl(vy, NV / 4, 64), ymin = __shfl(vy, 3 * NV / 4, 64);
     const bool bad = nf || !isfinite(xmax) || !isfinite(xmin) || !isfinite(ymax) || !isfinite(ymin);
     if (lane == 0) o->status = bad ? 1 : 0;
     if (bad) return 1;
 
-    const float nx = __shfl(vx, (j + 1) & 7, 64), ny = __shfl(vy, (j + 1) & 7, 64);
+    const float nx = __shfl(vx, (j + 1) & VM, 64), ny = __shfl(vy, (j + 1) & VM, 64);
     const bool deg = (vx == nx) && (vy == ny);
     bool first = true;   // first vertex with these coordinates
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NV; ++k) {
         const float kx = __shfl(vx, k, 64), ky = __shfl(vy, k, 64);
         if (k < j && kx == vx && ky == vy) first = false;
     }
-    const int distinct = __popcll(__ballot(lane < 8 && first));
-    const unsigned long long ndm = __ballot(lane < 8 && !deg) & 0xFFull;
+    const int distinct = __popcll(__ballot(lane < NV && first));
+    const unsigned long long ndm = __ballot(lane < NV && !deg) & VMASK;
     const int m = __popcll(ndm);
     if (lane == 0) o->m = m;
     // Fewer than three distinct vertices: no point can be strictly inside
@@ -545,7 +580,7 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
     {
         int cnt = 0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < NV; ++k)
             if ((ndm >> k) & 1ull) {
                 if (cnt == j) src = k;
                 ++cnt;
@@ -555,7 +590,7 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
     const float sbx = __shfl(nx, src, 64), sby = __shfl(ny, src, 64);
     const double ax = sax, ay = say;
     const double ex = (double)sbx - ax, ey = (double)sby - ay;
-    if (lane < 8) {
+    if (lane < NV) {
         o->ax[j] = ax;
         o->ay[j] = ay;
         o->ex[j] = ex;
@@ -569,8 +604,8 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
     const float cy = (float)(0.5 * (double)ymin + 0.5 * (double)ymax);
     const double M = (fabs(ex) * H + fabs(ey) * W) * up;
     const bool mok = isfinite(W) && isfinite(H) && (M > 0.0) && isfinite(M);
-    if (lane < 8) o->sm[j] = 0x1p-48 * M;
-    const bool skipok = __ballot(lane < 8 && !mok) == 0ull;
+    if (lane < NV) o->sm[j] = 0x1p-48 * M;
+    const bool skipok = __ballot(lane < NV && !mok) == 0ull;
     bool ok = mok;
     int E = 0;
     (void)frexp(ok ? M * 0x1p-20 : 1.0, &E);   // 16 u M = f 2^E, f in [0.5, 1)
@@ -580,24 +615,25 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
     const double kk = ex * ((double)cy - ay) - ey * ((double)cx - ax);
     const double c0 = sc * kk;
     ok = ok && fabs(a) <= 0x1p100 && fabs(nb) <= 0x1p100 && fabs(c0) <= 0x1p100;
-    if (lane < 8) {
+    if (lane < NV) {
         o->A[j] = (float)a;
         o->NB[j] = (float)nb;
         o->C0[j] = (float)c0;
     }
-    const bool fast = __ballot(lane < 8 && !ok) == 0ull;
+    const bool fast = __ballot(lane < NV && !ok) == 0ull;
 
     // quick-accept box: candidate from the corner vertices, shrunk towards
     // the centre until all four corners pass every edge
-    float XL = fmaxf(__shfl(vx, 3, 64), __shfl(vx, 5, 64)), XH = fminf(__shfl(vx, 1, 64), __shfl(vx, 7, 64));
-    float YL = fmaxf(__shfl(vy, 5, 64), __shfl(vy, 7, 64)), YH = fminf(__shfl(vy, 1, 64), __shfl(vy, 3, 64));
+    constexpr int D1 = NV / 8, D3 = 3 * NV / 8, D5 = 5 * NV / 8, D7 = 7 * NV / 8;
+    float XL = fmaxf(__shfl(vx, D3, 64), __shfl(vx, D5, 64)), XH = fminf(__shfl(vx, D1, 64), __shfl(vx, D7, 64));
+    float YL = fmaxf(__shfl(vy, D5, 64), __shfl(vy, D7, 64)), YH = fminf(__shfl(vy, D1, 64), __shfl(vy, D3, 64));
     bool boxok = fast && XL < XH && YL < YH;
-    const int corner = (int)((lane >> 3) & 3u);
+    const int corner = (int)((lane / NV) & 3u);
     for (int it = 0; boxok && it < 8; ++it) {
         const double qx = (corner & 1) ? (double)XH : (double)XL;
         const double qy = (corner & 2) ? (double)YH : (double)YL;
         const double D = ex * (qy - ay) - ey * (qx - ax);
-        const bool pass = (lane >= 32) || (D > 0x1p-48 * M);
+        const bool pass = (lane >= 4 * NV) || (D > 0x1p-48 * M);
         if (__ballot(!pass) == 0ull) break;
         if (it == 7) {
             boxok = false;
@@ -630,13 +666,14 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
 // ---------------------------------------------------------------------------
 
 // The binary64 rule: strictly inside every edge (mode == 1 implies m >= 3).
-__device__ __forceinline__ bool contract_inside(const Octagon* __restrict__ o, float px, float py) {
+template <int NV>
+__device__ __forceinline__ bool contract_inside(const Poly<NV>* __restrict__ o, float px, float py) {
 #pragma clang fp contract(off)
     const double x = px, y = py;
     bool in = true;
     // one edge at a time: this is the rare path, keep its registers few
 #pragma unroll 1
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < NV; ++e) {
         const double qx = x - o->ax[e];
         const double qy = y - o->ay[e];
         const double l = o->ex[e] * qy;
@@ -653,31 +690,36 @@ __device__ __forceinline__ bool contract_inside(const Octagon* __restrict__ o, f
 // kernels that test points: read through the constant address space, its
 // uniform fields become scalar loads (scalar cache, their own wait counter)
 // instead of vector loads whose waits would also drain the point stream.
-typedef const __attribute__((address_space(4))) Octagon OctagonK;
-__device__ __forceinline__ OctagonK* as_const(const Octagon* o) { return (OctagonK*)o; }
+template <int NV>
+using PolyK = const __attribute__((address_space(4))) Poly<NV>;
+typedef PolyK<8> OctagonK;
+template <int NV>
+__device__ __forceinline__ PolyK<NV>* as_const(const Poly<NV>* o) { return (PolyK<NV>*)o; }
 
-__device__ __forceinline__ float edge_min(OctagonK* __restrict__ o, float x, float y) {
-    const float qx = x - o->cx, qy = y - o->cy;
-    float d[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = fmaf(o->A[e], qy, fmaf(o->NB[e], qx, o->C0[e]));
-    return min8(d);
+// Minimum of NV values (NV = 8 or 16).
+template <int NV>
+__device__ __forceinline__ float min_n(const float* d) {
+    if constexpr (NV == 8) return min8(d);
+    else return __builtin_elementwise_minimum(min8(d), min8(d + 8));
 }
 
 // The octagon fields of the FP32 fast paths, read once per kernel (or per
 // set) into registers: read inside the sub-tile loop they were reloaded by
 // every pair slot's branch, each reload a scalar-memory wait, and C0 copied
 // into vector registers again each time (an FMA reads one scalar operand).
-struct EdgeRegs {
-    float A[8], NB[8], C0[8];
+template <int NV>
+struct EdgeRegsN {
+    float A[NV], NB[NV], C0[NV];
     float cx, cy, bxl, bxh, byl, byh;
     int mode, fast;
 };
-__device__ __forceinline__ EdgeRegs load_edges(const Octagon* __restrict__ o) {
-    OctagonK* ok = as_const(o);
-    EdgeRegs r;
+typedef EdgeRegsN<8> EdgeRegs;
+template <int NV>
+__device__ __forceinline__ EdgeRegsN<NV> load_edges(const Poly<NV>* __restrict__ o) {
+    PolyK<NV>* ok = as_const(o);
+    EdgeRegsN<NV> r;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < NV; ++e) {
         r.A[e] = ok->A[e];
         r.NB[e] = ok->NB[e];
         // held in a vector register: the inner FMA's other scalar operand
@@ -696,16 +738,19 @@ __device__ __forceinline__ EdgeRegs load_edges(const Octagon* __restrict__ o) {
     r.fast = ok->fast;
     return r;
 }
-__device__ __forceinline__ float edge_min(const EdgeRegs& k, float x, float y) {
+template <int NV>
+__device__ __forceinline__ float edge_min(const EdgeRegsN<NV>& k, float x, float y) {
     const float qx = x - k.cx, qy = y - k.cy;
-    float d[8];
+    float d[NV];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = fmaf(k.A[e], qy, fmaf(k.NB[e], qx, k.C0[e]));
-    return min8(d);
+    for (int e = 0; e < NV; ++e) d[e] = fmaf(k.A[e], qy, fmaf(k.NB[e], qx, k.C0[e]));
+    return min_n<NV>(d);
 }
 
 // 1 = the point survives.  Decision-equivalent to the binary64 rule.
-__device__ __forceinline__ bool keep_point(const Octagon* __restrict__ o, const EdgeRegs& ek, float x, float y) {
+template <int NV>
+__device__ __forceinline__ bool keep_point(const Poly<NV>* __restrict__ o, const EdgeRegsN<NV>& ek, float x,
+                                           float y) {
     if (ek.mode == 0) return true;
     const bool inbox = (ek.bxl < x) & (x < ek.bxh) & (ek.byl < y) & (y < ek.byh);
     if (inbox) return false;
@@ -766,8 +811,8 @@ __device__ __forceinline__ uint32_t load_sub(const float2* __restrict__ pts, uin
 // Inside test of one loaded sub-tile; returns the keep mask (bit 2j+h).
 // Points in the uncertain band are re-read by index and take the binary64
 // rule itself.
-template <int BLOCK, int PPT>
-__device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, const EdgeRegs& ek,
+template <int BLOCK, int PPT, int NV>
+__device__ __forceinline__ uint32_t classify_sub(const Poly<NV>* __restrict__ o, const EdgeRegsN<NV>& ek,
                                                  const float2* __restrict__ pts, uint64_t sb,
                                                  const float4 (&q)[PPT / 2], uint32_t validm) {
     constexpr int NP = PPT / 2;
@@ -811,7 +856,7 @@ __device__ __forceinline__ uint32_t classify_sub(const Octagon* __restrict__ o, 
                 8u * (uint32_t)(b & 1));
             // an opaque copy of the pointer keeps the compiler from hoisting
             // the binary64 edge data into registers on the hot path
-            const Octagon* oo = o;
+            const Poly<NV>* oo = o;
             asm volatile("" : "+s"(oo));
             if (!contract_inside(oo, pt.x, pt.y)) keepm |= 1u << b;
         }
@@ -874,6 +919,9 @@ __device__ __forceinline__ float from_ordered(uint32_t o) {
 // the chunk's first point in range and may run one point past the chunk:
 // the lowest index attaining `best` lies in the chunk, so the first match in
 // the window is still that index.
+// NV = 8: key j is the octagon reduction's tracked value (key_select);
+// NV = 16: key j is key16(j).
+template <int NV = 8>
 __device__ __forceinline__ uint32_t scan_chunk(const float2* __restrict__ pts, uint64_t lo, uint64_t hi,
                                                uint32_t p, int j, float best, float2* pt) {
     constexpr uint32_t K = kRChunk / 64;
@@ -895,7 +943,7 @@ __device__ __forceinline__ uint32_t scan_chunk(const float2* __restrict__ pts, u
     float2 qc = make_float2(0.0f, 0.0f);
 #pragma unroll
     for (int i = (int)K - 1; i >= 0; --i)
-        if (key_select(j, q[i].x, q[i].y) == best) {
+        if ((NV == 8 ? key_select(j, q[i].x, q[i].y) : key16(j, q[i].x, q[i].y)) == best) {
             cand = (uint32_t)(st + lane + 64u * (uint32_t)i - lo);
             qc = q[i];
         }
@@ -981,6 +1029,204 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const float2* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Sec. 2 (related work): the 16 extremes of the rotated point set
+// ---------------------------------------------------------------------------
+// Same chunk geometry as k_reduce (256 threads, 8 points per thread per
+// 2048-point chunk, the same four region-skip boxes per chunk), 16 keys.
+// Every key is tracked as a maximum (keys k + 8 as the negated minimum of
+// line k), with the chunk in which it last strictly improved; the block
+// records (key, first point of the lowest such chunk over its holders + 1),
+// and k_setup16 scans that chunk for the lowest index.  Up to 128 registers
+// per lane (32 running values and chunks, 16 coordinates).
+constexpr int kR16PerCU = 4;   // blocks per CU at the occupancy the registers allow
+
+template <bool VEC4>
+__global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_reduce16(
+    const float2* __restrict__ pts, uint64_t n, unsigned long long* __restrict__ part, float4* __restrict__ box) {
+    constexpr uint32_t CH = kRChunk;
+    constexpr int NW = kRBlock / 64;
+    __shared__ float sh_v[16][NW];
+    __shared__ uint32_t sh_cm[16];
+    const uint32_t t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+    const uint32_t nch = (uint32_t)((n + CH - 1) / CH);
+    const uint32_t c0 = blockIdx.x, cstep = gridDim.x;
+    float v[16];
+    uint32_t grp[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        v[j] = -kInfF;
+        grp[j] = c0;
+    }
+    bool bad = false;
+    float4 bacc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint32_t nb = 0, cfirst = c0;
+    auto put_box = [&](uint32_t c, float4 b) {
+        if (lane == nb) bacc = b;
+        if (++nb == 64u) {
+            box[(uint64_t)(cfirst + lane * cstep) * NW + wv] = bacc;
+            nb = 0;
+            cfirst = c + cstep;
+        }
+    };
+    for (uint32_t c = c0; c < nch; c += cstep) {
+        const uint64_t cb = (uint64_t)c * CH;
+        if (cb + CH <= n) {
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + cb, CH * 8u);
+            float4 q[kRG];
+#pragma unroll
+            for (int k = 0; k < kRG; ++k) q[k] = load_pair_buf<VEC4>(rs, 16u * t, 16u * k * kRBlock);
+            float xs[8], ys[8];
+#pragma unroll
+            for (int k = 0; k < kRG; ++k) {
+                xs[2 * k] = q[k].x;
+                ys[2 * k] = q[k].y;
+                xs[2 * k + 1] = q[k].z;
+                ys[2 * k + 1] = q[k].w;
+            }
+            float bx0 = 0.0f, bx1 = 0.0f, by0 = 0.0f, by1 = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                float L[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) L[k] = line16(i, xs[k], ys[k]);
+                const float mx = max8(L), mn = min8(L);
+                if (i == 2) bad |= __builtin_isnan(mx);   // maximum() propagates NaN: x+y covers every coordinate
+                if (i == 0) { bx0 = mn; bx1 = mx; }
+                if (i == 4) { by0 = mn; by1 = mx; }
+                if (mx > v[i]) { v[i] = mx; grp[i] = c; }
+                if (-mn > v[i + 8]) { v[i + 8] = -mn; grp[i + 8] = c; }
+            }
+            if (box) {
+                const float b0 = wave_minmax_dpp<false>(bx0), b1 = wave_minmax_dpp<true>(bx1);
+                const float b2 = wave_minmax_dpp<false>(by0), b3 = wave_minmax_dpp<true>(by1);
+                put_box(c, make_float4(b0, b1, b2, b3));
+            }
+        } else {
+            if (box) {
+                const float qn = __builtin_nanf("");
+                put_box(c, make_float4(qn, qn, qn, qn));
+            }
+            const RangeView rv = range_view(pts, cb, CH, 0, n);
+            const uint32_t tt = opaque_tid();
+#pragma unroll 1
+            for (uint32_t k = 0; k < 2 * kRG; ++k) {
+                bool ok;
+                const uint32_t p = 2u * ((k >> 1) * kRBlock + tt) + (k & 1u);
+                const float2 pq = load_point_checked(rv.r, p, rv.lo_rel, rv.hi_rel, ok);
+                if (!ok) continue;
+                bad |= __builtin_isnan(pq.x + pq.y);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const float L = line16(i, pq.x, pq.y);
+                    if (L > v[i]) { v[i] = L; grp[i] = c; }
+                    if (-L > v[i + 8]) { v[i + 8] = -L; grp[i + 8] = c; }
+                }
+            }
+        }
+    }
+    if (box && nb != 0u && lane < nb) box[(uint64_t)(cfirst + lane * cstep) * NW + wv] = bacc;
+
+    // block best per key; the holders' lowest first-improvement chunk
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const float w = wave_max(v[j]);
+        if (lane == 0) sh_v[j][wv] = w;
+    }
+    if (t < 16) sh_cm[t] = 0xFFFFFFFFu;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        float best = sh_v[j][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) best = fmaxf(best, sh_v[j][w]);
+        const bool hold = (v[j] == best) && (grp[j] < nch);
+        const uint32_t cw = wave_min_u32(hold ? grp[j] : 0xFFFFFFFFu);
+        if (lane == 0 && cw != 0xFFFFFFFFu) atomicMin(&sh_cm[j], cw);
+    }
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
+    if (t < 16) {
+        const int j = (int)t;
+        float best = sh_v[j][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) best = fmaxf(best, sh_v[j][w]);
+        const uint32_t c = sh_cm[j];
+        part[(uint64_t)j * kReduceMaxGrid + blockIdx.x] =
+            (c != 0xFFFFFFFFu) ? pack_key(best, (uint32_t)((uint64_t)c * CH + 1u)) : 0ull;
+    } else if (t == 16) {
+        part[16ull * kReduceMaxGrid + blockIdx.x] = any_bad ? 1ull : 0ull;
+    }
+}
+
+// Pass 2 of the 16-direction filter (one block of 16 waves): merge the
+// partial records (17 words per block, direction-major), then wave j finds
+// the lowest index attaining key j in the chunk that won it, and wave 0
+// builds the polygon record.
+constexpr int kSetup16Block = 1024;
+__global__ __launch_bounds__(kSetup16Block) void k_setup16(const float2* __restrict__ pts, uint64_t n,
+                                                           Poly16* poly, const unsigned long long* __restrict__ part,
+                                                           uint32_t nblocks) {
+    constexpr int NW = kSetup16Block / 64;
+    static_assert(NW == 16, "one wave per direction");
+    static_assert(kReduceMaxGrid == 4 * kSetup16Block, "one round of records");
+    __shared__ unsigned long long sh_m[17][NW];
+    __shared__ unsigned long long sh_k[16];
+    __shared__ float2 sh_pt[16];
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+    const uint32_t b0 = 4u * t;
+    // two halves of the directions, each one memory round trip: thread t
+    // reads blocks 4t..4t+3 of every direction of the half as two 16-byte
+    // loads; words past nblocks are replaced by 0 (identity of max and OR)
+    auto merge = [&](auto jfirst_c, auto jcount_c) {
+        constexpr int J0 = decltype(jfirst_c)::value, JN = decltype(jcount_c)::value;
+        ulonglong2 w[JN][2];
+#pragma unroll
+        for (int i = 0; i < JN; ++i) {
+            const ulonglong2* src = reinterpret_cast<const ulonglong2*>(part + (uint64_t)(J0 + i) * kReduceMaxGrid + b0);
+            w[i][0] = src[0];
+            w[i][1] = src[1];
+        }
+#pragma unroll
+        for (int i = 0; i < JN; ++i) {
+            const int j = J0 + i;
+            const unsigned long long e0 = (b0 + 0u < nblocks) ? w[i][0].x : 0ull;
+            const unsigned long long e1 = (b0 + 1u < nblocks) ? w[i][0].y : 0ull;
+            const unsigned long long e2 = (b0 + 2u < nblocks) ? w[i][1].x : 0ull;
+            const unsigned long long e3 = (b0 + 3u < nblocks) ? w[i][1].y : 0ull;
+            unsigned long long v = (j == 16) ? (e0 | e1 | e2 | e3) : max(max(e0, e1), max(e2, e3));
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, 64);
+                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, 64);
+                const unsigned long long u = ((unsigned long long)hi << 32) | lo;
+                v = (j == 16) ? (v | u) : max(v, u);
+            }
+            if (lane == 0) sh_m[j][wave] = v;
+        }
+    };
+    merge(std::integral_constant<int, 0>{}, std::integral_constant<int, 9>{});
+    merge(std::integral_constant<int, 9>{}, std::integral_constant<int, 8>{});
+    __syncthreads();
+    {
+        const int j = (int)wave;
+        unsigned long long key = 0ull;
+        for (int w = 0; w < NW; ++w) key = max(key, sh_m[j][w]);
+        unsigned long long res = 0ull;
+        if (key != 0ull) {
+            const float kv = from_ordered((uint32_t)(key >> 32));
+            const uint32_t idx = scan_chunk<16>(pts, 0, n, unpack_idx(key), j, kv, &sh_pt[j]);
+            if (idx != 0xFFFFFFFFu) res = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - idx);
+        }
+        if (lane == 0) sh_k[j] = res;
+    }
+    __syncthreads();
+    if (t < 64) {
+        unsigned long long nf = 0ull;
+        for (int w = 0; w < NW; ++w) nf |= sh_m[16][w];
+        (void)setup_octagon<16>(pts, 0, n, sh_k[lane & 15u], (uint32_t)nf, poly, sh_pt);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Two-pass compaction: classify (inside test, keep bits) then compact
 // ---------------------------------------------------------------------------
 // Pass 1 streams the points once and stores the keep bits in point order:
@@ -1014,10 +1260,11 @@ static_assert(kRBlock * kRG * 2 == 16 * 128 && kRBlock / 64 == 4, "box of group 
 
 // True iff all four corners of box b have a binary64 edge value above sm[e]
 // on every edge e (false for a NaN box).
-__device__ __forceinline__ bool box_inside(float4 b, OctagonK* __restrict__ ok) {
+template <int NV>
+__device__ __forceinline__ bool box_inside(float4 b, PolyK<NV>* __restrict__ ok) {
     bool pass = true;
 #pragma unroll 1
-    for (int e = 0; e < 8; ++e) {   // one edge's data live at a time
+    for (int e = 0; e < NV; ++e) {   // one edge's data live at a time
         const double ax = ok->ax[e], ay = ok->ay[e], ex = ok->ex[e], ey = ok->ey[e], sm = ok->sm[e];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -1034,10 +1281,107 @@ __device__ __forceinline__ bool box_inside(float4 b, OctagonK* __restrict__ ok) 
 // block's range (64 boxes, 32768 points, per word).  A range longer than
 // kSkipWords words is not skipped past them.
 constexpr uint32_t kSkipWords = 1024;
+// Sparse inside test: a block whose unread groups (inside passing boxes) are
+// at least 3/4 of its groups, and whose other groups fit in kSparseList
+// entries, lists the groups to read and tests only those, NP per wave at a
+// time with all their loads issued together; the skipped groups get zero
+// keep words.  Walking the range sub-tile by sub-tile instead costs one
+// memory round trip per sub-tile even when almost nothing is read.
+constexpr uint32_t kSparseList = 2048;
 
-template <int BLOCK, int PPT, bool VEC4>
+// Skip bit of group g (0 if its box is not covered by the block's words).
+__device__ __forceinline__ bool group_skipped(const unsigned long long* sh_skip, uint64_t g, uint64_t w0,
+                                              uint32_t nw) {
+    const uint64_t rel = (g >> 8) - w0;
+    if (rel >= nw) return false;
+    const uint32_t bit = (uint32_t)(4u * ((g >> 4) & 15u) + (g & 3u));
+    return (sh_skip[rel] >> bit) & 1ull;
+}
+
+// Load the points of NP listed groups (slot k: group list[k], valid for
+// k < cnt): lane l holds points 128 g + 2l and 128 g + 2l + 1 of slot k, the
+// layout of a pair slot; returns the validity mask (bit 2k+h).
+template <int NP, bool VEC4>
+__device__ __forceinline__ uint32_t load_groups(const float2* __restrict__ pts, uint64_t n,
+                                                const uint32_t* list, uint32_t cnt, float4 (&q)[NP]) {
+    const uint32_t lane = lane_id();
+    uint32_t validm = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        q[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if ((uint32_t)k < cnt) {   // wave-uniform
+            const uint64_t g = uniform_u32(list[k]);
+            const uint64_t i0 = 128ull * g + 2u * lane;
+            const float2* gp = pts + 128ull * g;   // uniform base
+            if (128ull * g + 128ull <= n) {
+                if constexpr (VEC4) {
+                    q[k] = reinterpret_cast<const float4*>(gp)[lane];
+                } else {
+                    const float2 a = gp[2u * lane], b = gp[2u * lane + 1u];
+                    q[k] = make_float4(a.x, a.y, b.x, b.y);
+                }
+                validm |= 3u << (2 * k);
+            } else {
+                const bool v0 = i0 < n, v1 = i0 + 1u < n;
+                const float2 a = v0 ? gp[2u * lane] : make_float2(0.0f, 0.0f);
+                const float2 b = v1 ? gp[2u * lane + 1u] : make_float2(0.0f, 0.0f);
+                q[k] = make_float4(a.x, a.y, b.x, b.y);
+                validm |= ((v0 ? 1u : 0u) | (v1 ? 2u : 0u)) << (2 * k);
+            }
+        }
+    }
+    return validm;
+}
+
+// classify_sub for listed groups: the same decisions, with the uncertain
+// band re-read from the listed group's own base.
+template <int NP, int NV>
+__device__ __forceinline__ uint32_t classify_groups(const Poly<NV>* __restrict__ o, const EdgeRegsN<NV>& ek,
+                                                    const float2* __restrict__ pts, const uint32_t* list,
+                                                    const float4 (&q)[NP], uint32_t validm) {
+    if (ek.mode == 0) return validm;
+    uint32_t keepm = 0, pendm = 0;
+    const float bxl = ek.bxl, bxh = ek.bxh, byl = ek.byl, byh = ek.byh;
+    const bool fast = ek.fast != 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const bool ok0 = (validm >> (2 * j)) & 1u, ok1 = (validm >> (2 * j + 1)) & 1u;
+        const bool in0 = (bxl < q[j].x) & (q[j].x < bxh) & (byl < q[j].y) & (q[j].y < byh);
+        const bool in1 = (bxl < q[j].z) & (q[j].z < bxh) & (byl < q[j].w) & (q[j].w < byh);
+        const bool need0 = ok0 & !in0, need1 = ok1 & !in1;
+        if (__ballot(need0 | need1) != 0ull) {
+            uint32_t k2 = 0, p2 = 0;
+            if (fast) {
+                const float mn0 = edge_min(ek, q[j].x, q[j].y);
+                const float mn1 = edge_min(ek, q[j].z, q[j].w);
+                k2 = ((need0 & (mn0 < -1.0f)) ? 1u : 0u) | ((need1 & (mn1 < -1.0f)) ? 2u : 0u);
+                p2 = ((need0 & !(mn0 < -1.0f) & !(mn0 > 2.0f)) ? 1u : 0u) |
+                     ((need1 & !(mn1 < -1.0f) & !(mn1 > 2.0f)) ? 2u : 0u);
+            } else {
+                p2 = (need0 ? 1u : 0u) | (need1 ? 2u : 0u);
+            }
+            keepm |= k2 << (2 * j);
+            pendm |= p2 << (2 * j);
+        }
+    }
+    while (__ballot(pendm != 0u) != 0ull) {
+        if (pendm) {
+            const int b = __ffs(pendm) - 1;
+            pendm &= pendm - 1u;
+            const uint64_t g = list[b >> 1];
+            const uint32_t ln = opaque_tid() & 63u;
+            const float2 pt = pts[128ull * g + 2u * ln + (uint32_t)(b & 1)];
+            const Poly<NV>* oo = o;
+            asm volatile("" : "+s"(oo));
+            if (!contract_inside(oo, pt.x, pt.y)) keepm |= 1u << b;
+        }
+    }
+    return keepm;
+}
+
+template <int BLOCK, int PPT, bool VEC4, int NV>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_classify(
-    const float2* __restrict__ pts, uint64_t n, const Octagon* __restrict__ oct, uint32_t spans,
+    const float2* __restrict__ pts, uint64_t n, const Poly<NV>* __restrict__ oct, uint32_t spans,
     uint64_t* __restrict__ bits, uint32_t* __restrict__ blkcnt, const float4* __restrict__ box, uint64_t nbox,
     unsigned long long* loaded) {
     constexpr int NP = PPT / 2;
@@ -1047,6 +1391,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     static_assert(NP <= 64, "one lane per pair slot stores the bits");
     __shared__ uint32_t sh_w[NW], sh_g[NW];
     __shared__ unsigned long long sh_skip[kSkipWords];
+    __shared__ uint32_t sh_list[kSparseList];
+    __shared__ uint32_t sh_nlist;
     if (oct->status != 0) return;
     const uint32_t lane = lane_id();
     const uint32_t wave = uniform_u32(threadIdx.x >> 6);   // keeps wave-derived addresses scalar
@@ -1057,22 +1403,66 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     // against the octagon and keeps one bit per box in LDS (word i - w0 covers
     // points [i*32768, (i+1)*32768)).  Each wave's 64 consecutive boxes make
     // one ballot, so every lane of a wave takes the same loop trips.
-    OctagonK* ok = as_const(oct);
+    PolyK<NV>* ok = as_const(oct);
     const bool skipon = box != nullptr && ok->mode == 1 && ok->skip != 0;
     const uint64_t w0 = r0 >> 15;
     const uint32_t nw = (uint32_t)min<uint64_t>(((r1 + 32767u) >> 15) - w0, kSkipWords);
     if (skipon) {
         for (uint32_t i = threadIdx.x; i < nw * 64u; i += BLOCK) {
             const uint64_t bi = (w0 << 6) + i;
-            const bool pass = bi < nbox && box_inside(box[bi], ok);
+            const bool pass = bi < nbox && box_inside<NV>(box[bi], ok);
             const unsigned long long m = __ballot(pass);
             if (lane == 0) sh_skip[i >> 6] = m;
         }
         __syncthreads();
     }
-    const EdgeRegs ek = load_edges(oct);
+    const EdgeRegsN<NV> ek = load_edges(oct);
     uint32_t total = 0, groups = 0;
-    for (uint64_t sb = r0; sb < r1; sb += ST) {
+    // Sparse inside test: list the groups to read (lane per group) and
+    // decide whether the block takes the listed path.
+    bool sparse = false;
+    const uint64_t g0 = r0 >> 7, g1 = (r1 + 127) >> 7;
+    if (skipon) {
+        if (threadIdx.x == 0) sh_nlist = 0u;
+        __syncthreads();
+        for (uint64_t gb = g0 + (uint64_t)wave * 64u; gb < g1; gb += (uint64_t)NW * 64u) {
+            const uint64_t g = gb + lane;
+            const bool need = g < g1 && !group_skipped(sh_skip, g, w0, nw);
+            const unsigned long long m = __ballot(need);
+            uint32_t base = 0;
+            if (lane == 0 && m != 0ull) base = atomicAdd(&sh_nlist, (uint32_t)__popcll(m));
+            base = uniform_u32((uint32_t)__shfl((int)base, 0, 64));
+            const uint32_t pos = base + rank_below(m);
+            if (need && pos < kSparseList) sh_list[pos] = (uint32_t)g;
+        }
+        __syncthreads();
+        const uint32_t nl = sh_nlist;
+        sparse = nl <= kSparseList && 4ull * nl <= g1 - g0;
+    }
+    if (sparse) {
+        const uint32_t nl = sh_nlist;
+        // zero keep words for the groups that are not read
+        for (uint64_t gb = g0 + (uint64_t)wave * 64u; gb < g1; gb += (uint64_t)NW * 64u) {
+            const uint64_t g = gb + lane;
+            if (g < g1 && group_skipped(sh_skip, g, w0, nw))
+                *reinterpret_cast<ulonglong2*>(bits + 2 * g) = make_ulonglong2(0ull, 0ull);
+        }
+        // the listed groups, NP per wave at a time
+        for (uint32_t b = wave * (uint32_t)NP; b < nl; b += (uint32_t)(NW * NP)) {
+            const uint32_t cnt = min((uint32_t)NP, nl - b);
+            float4 q[NP];
+            const uint32_t validm = load_groups<NP, VEC4>(pts, n, sh_list + b, cnt, q);
+            const uint32_t k = classify_groups<NP, NV>(oct, ek, pts, sh_list + b, q, validm);
+            unsigned long long m0 = 0ull, m1 = 0ull;
+            if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);
+            if (lane < cnt) {
+                const uint64_t g = sh_list[b + lane];
+                *reinterpret_cast<ulonglong2*>(bits + 2 * g) = make_ulonglong2(m0, m1);
+            }
+            groups += cnt;
+        }
+    }
+    for (uint64_t sb = r0; !sparse && sb < r1; sb += ST) {
         uint32_t skipm = 0;
         const uint64_t rel = (sb >> 15) - w0;
         if (skipon && sb + ST <= n && rel < nw) {
@@ -1088,7 +1478,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
         groups += (uint32_t)(NP - __popc(skipm));
         float4 q[NP];
         const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q, skipm);
-        const uint32_t k = classify_sub<BLOCK, PPT>(oct, ek, pts, sb, q, validm);
+        const uint32_t k = classify_sub<BLOCK, PPT, NV>(oct, ek, pts, sb, q, validm);
         // lane j keeps the two ballots of pair slot j, then all NP groups
         // of this wave are stored by one instruction
         unsigned long long m0 = 0ull, m1 = 0ull;
@@ -1212,10 +1602,10 @@ __device__ __forceinline__ void compact_span(unsigned long long w0, unsigned lon
 // Pass 2 of one set.  Each round the block's waves take consecutive spans
 // (one each); the next round's keep bits are loaded before this round's
 // survivors are stored, so the loads do not wait behind the stores.
-template <int BLOCK>
+template <int BLOCK, int NV>
 __global__ __launch_bounds__(BLOCK) void k_compact(const uint64_t* __restrict__ bits,
                                                    const uint32_t* __restrict__ blkcnt, uint64_t n,
-                                                   uint32_t spans, const Octagon* __restrict__ oct,
+                                                   uint32_t spans, const Poly<NV>* __restrict__ oct,
                                                    uint32_t* __restrict__ out, uint64_t cap, uint64_t* count) {
     constexpr int NW = BLOCK / 64;
     __shared__ __attribute__((aligned(16))) uint32_t sh_stage[NW][kStageWords];
@@ -1555,7 +1945,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
                 }
                 float4 q[NP];
                 const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, b, hi, sb, q, skipm);
-                const uint32_t k = classify_sub<BLOCK, PPT>(o, ek, pts, sb, q, validm);
+                const uint32_t k = classify_sub<BLOCK, PPT, 8>(o, ek, pts, sb, q, validm);
                 unsigned long long m0 = 0ull, m1 = 0ull;
                 if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);   // else the wave kept nothing
                 const uint32_t g = (uint32_t)((sb - r0) >> 7) + lane * NW + wave;
@@ -1674,6 +2064,29 @@ hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsig
     return hipGetLastError();
 }
 
+int reduce16_grid(uint64_t n, int cus) {
+    const uint64_t nch = (n + kRChunk - 1) / kRChunk;
+    const uint64_t g = std::min<uint64_t>((uint64_t)cus * kR16PerCU, (uint64_t)kReduceMaxGrid);
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(nch, g));
+}
+
+hipError_t launch_reduce16(const float2* pts, uint64_t n, unsigned long long* part, float4* box, int grid,
+                           hipStream_t stream) {
+    if (grid < 1 || grid > kReduceMaxGrid) return hipErrorInvalidValue;
+    if (is_vec4(pts))
+        hipLaunchKernelGGL(k_reduce16<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part, box);
+    else
+        hipLaunchKernelGGL(k_reduce16<false>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part, box);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup16(const float2* pts, uint64_t n, Poly16* poly, const unsigned long long* part,
+                          uint32_t nblocks, hipStream_t stream) {
+    if (nblocks < 1 || nblocks > (uint32_t)kReduceMaxGrid) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_setup16, dim3(1), dim3(kSetup16Block), 0, stream, pts, n, poly, part, nblocks);
+    return hipGetLastError();
+}
+
 uint32_t compact_span_points() { return kSpan; }
 
 FilterPlan plan_filter(uint64_t n, int cus, Shape shape, int per_cu, int reduce_grid_max) {
@@ -1699,18 +2112,19 @@ bool classify_shape_supported(Shape s) {
 
 #define HULLF_CLASSIFY_SHAPES(X) X(256, 8) X(256, 16) X(512, 8) X(512, 16)
 
-hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
+template <int NV>
+hipError_t classify_launch(const float2* pts, uint64_t n, const Poly<NV>* oct, uint32_t spans, uint64_t* bits,
                            uint32_t* blkcnt, const float4* box, uint64_t nbox, unsigned long long* loaded,
                            Shape shape, int grid, hipStream_t stream) {
     const bool v = is_vec4(pts);
 #define X(B, P)                                                                                           \
     if (shape.block == B && shape.ppt == P) {                                                             \
         if (v)                                                                                            \
-            hipLaunchKernelGGL((k_classify<B, P, true>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
+            hipLaunchKernelGGL((k_classify<B, P, true, NV>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
                                bits, blkcnt, box, nbox, loaded);                                          \
         else                                                                                              \
-            hipLaunchKernelGGL((k_classify<B, P, false>), dim3(grid), dim3(B), 0, stream, pts, n, oct, spans, \
-                               bits, blkcnt, box, nbox, loaded);                                          \
+            hipLaunchKernelGGL((k_classify<B, P, false, NV>), dim3(grid), dim3(B), 0, stream, pts, n, oct,   \
+                               spans, bits, blkcnt, box, nbox, loaded);                                   \
         return hipGetLastError();                                                                         \
     }
     HULLF_CLASSIFY_SHAPES(X)
@@ -1718,19 +2132,44 @@ hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, ui
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_classify(const float2* pts, uint64_t n, const Octagon* oct, uint32_t spans, uint64_t* bits,
+                           uint32_t* blkcnt, const float4* box, uint64_t nbox, unsigned long long* loaded,
+                           Shape shape, int grid, hipStream_t stream) {
+    return classify_launch<8>(pts, n, oct, spans, bits, blkcnt, box, nbox, loaded, shape, grid, stream);
+}
+
+hipError_t launch_classify(const float2* pts, uint64_t n, const Poly16* poly, uint32_t spans, uint64_t* bits,
+                           uint32_t* blkcnt, const float4* box, uint64_t nbox, unsigned long long* loaded,
+                           Shape shape, int grid, hipStream_t stream) {
+    return classify_launch<16>(pts, n, poly, spans, bits, blkcnt, box, nbox, loaded, shape, grid, stream);
+}
+
+template <int NV>
+hipError_t compact_launch(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
+                          const Poly<NV>* oct, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,
+                          hipStream_t stream) {
+    if (block == 1024)
+        hipLaunchKernelGGL((k_compact<1024, NV>), dim3(grid), dim3(1024), 0, stream, bits, blkcnt, n, spans, oct,
+                           out, cap, count);
+    else if (block == 512)
+        hipLaunchKernelGGL((k_compact<512, NV>), dim3(grid), dim3(512), 0, stream, bits, blkcnt, n, spans, oct, out,
+                           cap, count);
+    else
+        hipLaunchKernelGGL((k_compact<256, NV>), dim3(grid), dim3(256), 0, stream, bits, blkcnt, n, spans, oct, out,
+                           cap, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
                           const Octagon* oct, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,
                           hipStream_t stream) {
-    if (block == 1024)
-        hipLaunchKernelGGL(k_compact<1024>, dim3(grid), dim3(1024), 0, stream, bits, blkcnt, n, spans, oct, out,
-                           cap, count);
-    else if (block == 512)
-        hipLaunchKernelGGL(k_compact<512>, dim3(grid), dim3(512), 0, stream, bits, blkcnt, n, spans, oct, out, cap,
-                           count);
-    else
-        hipLaunchKernelGGL(k_compact<256>, dim3(grid), dim3(256), 0, stream, bits, blkcnt, n, spans, oct, out, cap,
-                           count);
-    return hipGetLastError();
+    return compact_launch<8>(bits, blkcnt, n, spans, oct, out, cap, count, block, grid, stream);
+}
+
+hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
+                          const Poly16* poly, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,
+                          hipStream_t stream) {
+    return compact_launch<16>(bits, blkcnt, n, spans, poly, out, cap, count, block, grid, stream);
 }
 
 hipError_t launch_flags(const float2* pts, uint64_t n, const Octagon* oct, uint8_t* flags, int grid,

@@ -8,6 +8,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <string>
+#include <sys/stat.h>
+#include <unistd.h>
 #include <unordered_map>
 #include <vector>
 
@@ -63,6 +67,10 @@ struct hullf_ctx {
     uint64_t h_xy_cap = 0;
     uint64_t* h_count = nullptr;
     Octagon* h_oct = nullptr;
+    // the 16-direction filter (allocated on first use)
+    Poly16* poly16 = nullptr;
+    unsigned long long* part16 = nullptr;   // kPart16Words * kReduceMaxGrid
+    Poly16* h_poly16 = nullptr;
     // hull finishing on the device (large survivor sets)
     uint64_t* fk[3] = {nullptr, nullptr, nullptr};   // keys: sorted, then level outputs
     uint32_t* fv[3] = {nullptr, nullptr, nullptr};   // point indices
@@ -103,6 +111,12 @@ struct hullf_ctx {
     uint32_t* b_blkcnt = nullptr;          // two-pass: survivors per work item
     uint64_t b_items_cap = 0;
     Shape batch_shape{256, 16};
+    // Tune cache of the batched launch: the autotuner's choice per
+    // (architecture, CU count, set-count class, mean-set-size class), kept
+    // in a text file across processes (empty path: not persisted).
+    std::string arch;
+    std::string tune_path;
+    std::map<std::string, Shape> tune;
     hipStream_t capture = nullptr;
     std::vector<GraphEntry> graphs;
     // timing
@@ -282,9 +296,49 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
     return HULLF_OK;
 }
 
+hipError_t ensure_poly16(hullf_ctx* c) {
+    hipError_t e = hipSuccess;
+    if (!c->poly16 && (e = ws_alloc(c, &c->poly16, 1)) != hipSuccess) return e;
+    if (!c->part16 && (e = ws_alloc(c, &c->part16, (uint64_t)kPart16Words * kReduceMaxGrid)) != hipSuccess) return e;
+    if (!c->h_poly16 && (e = hipHostMalloc((void**)&c->h_poly16, sizeof(Poly16), hipHostMallocDefault)) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+// Enqueue the 16-direction filter for one set (n >= 1): reduction of the 16
+// keys, the polygon set-up, then the octagon filter's inside-test and
+// compaction launches over the polygon's edges.
+hullf_status enqueue_filter16(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uint32_t* d_surv, uint64_t cap,
+                              uint64_t* d_count, hipStream_t s) {
+    const float2* pts = reinterpret_cast<const float2*>(d_pts);
+    CHECK_HIP(ensure_poly16(c));
+    const FilterPlan p = plan_filter(n, c->cus, c->filter_shape, c->classify_per_cu, c->reduce_grid_max);
+    CHECK_HIP(grow_device(c, &c->bits, &c->bits_cap, p.bits_words, s));
+    float4* box = nullptr;
+    uint64_t nbox = 0;
+    if (c->region_skip) {
+        nbox = p.boxes;
+        CHECK_HIP(grow_device(c, &c->boxes, &c->boxes_cap, nbox, s));
+        box = c->boxes;
+    }
+    const int rg = reduce16_grid(n, c->cus);
+    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce16(pts, n, c->part16, box, rg, s); }));
+    CHECK_HIP(timed(c, 3, s, [&] { return launch_setup16(pts, n, c->poly16, c->part16, (uint32_t)rg, s); }));
+    CHECK_HIP(timed(c, 1, s, [&] {
+        return launch_classify(pts, n, c->poly16, p.spans, c->bits, c->blkcnt, box, nbox, c->groups_read, p.shape,
+                               p.grid, s);
+    }));
+    c->groups_total += (n + 127) / 128;
+    CHECK_HIP(timed(c, 4, s, [&] {
+        return launch_compact(c->bits, c->blkcnt, n, p.spans, c->poly16, d_surv, cap, d_count, c->compact_block,
+                              p.grid, s);
+    }));
+    return HULLF_OK;
+}
+
 constexpr uint32_t kChainChunk = 256;          // sorted points per chain thread
 constexpr uint64_t kDeviceFinishMin = 1u << 18;   // survivors from which the device sorts and chains
-constexpr uint32_t kHostChainMax = 1u << 16;      // chain levels stop at this many candidates
+constexpr uint32_t kLevelStop = 1u << 16;         // chunk levels stop at this many candidates
 
 hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
     if (m > c->f_cap) {
@@ -307,7 +361,7 @@ hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
             if ((e = ws_alloc(c, &c->fv[k], cap)) != hipSuccess) return e;
         }
         if ((e = ws_alloc(c, &c->fchain, cap)) != hipSuccess) return e;
-        if ((e = ws_alloc(c, &c->fcnt, cap / kChainChunk + 1)) != hipSuccess) return e;
+        if ((e = ws_alloc(c, &c->fcnt, cap / kChainChunk + 2)) != hipSuccess) return e;
         c->f_cap = cap;
     }
     const uint64_t hw = 256ull * finish_sort_tiles((uint32_t)m);
@@ -327,8 +381,10 @@ inline float unord_host(uint32_t k) {
     return f;
 }
 
-// Sort the m survivors on the device, reduce them to chain candidates by
-// chunked monotone chains, and finish on the host.
+// Sort the m survivors on the device, reduce them by chunked monotone
+// chains, merge the chunk chains on the device (merge tree) into the lower
+// and the upper hull chain, and copy back only those two chains; the host
+// joins them.
 hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const uint32_t* d_surv, uint64_t m,
                               std::vector<uint32_t>& out, hipStream_t s) {
     CHECK_HIP(ensure_finish(c, m, s));
@@ -342,12 +398,15 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
     if (*c->h_count != 0) return HULLF_EINVAL;
     CHECK_HIP(launch_finish_sort(c->fk[0], c->fv[0], c->fk[1], c->fv[1], mm, c->fhist, c->frow, s));
     std::vector<HostPt> lists[2];
+    uint32_t* const off_b = c->fchain + c->f_cap / 2;   // second offset array of the merge rounds
+    uint2* const br = reinterpret_cast<uint2*>(c->fchain);
     for (int side = 0; side < 2; ++side) {
         const int sign = side == 0 ? 1 : -1;
+        // chunk levels while they shrink the set well
         int cur = 0, dedup = 1;
-        uint32_t cm = mm;
-        while (cm > kHostChainMax) {
-            const int nxt = (cur == 1) ? 2 : 1;
+        uint32_t cm = mm, nc = 0;
+        for (;;) {
+            const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
             const uint32_t nch = (cm + kChainChunk - 1) / kChainChunk;
             CHECK_HIP(launch_chain(c->fk[cur], cm, kChainChunk, sign, dedup, c->fchain, c->fcnt, s));
             CHECK_HIP(launch_scan_counts(c->fcnt, nch, c->frow + 256, s));
@@ -362,8 +421,31 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
             cur = nxt;
             dedup = 0;
             cm = tot;
-            if (slow) break;
+            nc = nch;
+            if (slow || cm <= kLevelStop) break;
         }
+        // merge tree: the chunk chains of the last level, pairwise, until
+        // one chain (the side's hull) is left; no host round trip between
+        // rounds
+        CHECK_HIP(launch_copy_u32(c->fcnt + nc, c->frow + 256, s));   // off[nc] = total
+        uint32_t* off_in = c->fcnt;
+        uint32_t* off_out = off_b;
+        while (nc > 1) {
+            const uint32_t np = (nc + 1) / 2;
+            const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
+            const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((np + 3) / 4, (uint32_t)c->cus * 8));
+            CHECK_HIP(launch_bridge(c->fk[cur], off_in, nc, sign, br, off_out, gg, s));
+            CHECK_HIP(launch_scan_counts(off_out, np, off_out + np, s));
+            CHECK_HIP(launch_merge_gather(c->fk[cur], c->fv[cur], off_in, nc, br, off_out, c->fk[nxt], c->fv[nxt],
+                                          gg, s));
+            std::swap(off_in, off_out);
+            cur = nxt;
+            nc = np;
+        }
+        CHECK_HIP(hipMemcpyAsync(c->h_total, off_in + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        cm = *c->h_total;
+        if (cm > mm) return HULLF_EDEVICE;
         CHECK_HIP(grow_host(&c->h_fk, &c->h_f_cap, cm));
         CHECK_HIP(grow_host(&c->h_fv, &c->h_fv_cap, cm));
         CHECK_HIP(hipMemcpyAsync(c->h_fk, c->fk[cur], (uint64_t)cm * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -401,6 +483,69 @@ hullf_status hull_of(hullf_ctx* c, const float2* pts, uint64_t n, const uint32_t
     }
     monotone_chain(p, out);
     return HULLF_OK;
+}
+
+// Tune-cache key of a batch: floor(log2 S) and floor(log2(mean set size)).
+std::string tune_key(const hullf_ctx* c, uint32_t S, uint64_t n_total) {
+    const uint64_t mean = std::max<uint64_t>(1, n_total / std::max<uint32_t>(S, 1));
+    int sc = 0, mc = 0;
+    while ((2ull << sc) <= S) ++sc;
+    while ((2ull << mc) <= mean) ++mc;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s:%d:s%d:m%d", c->arch.c_str(), c->cus, sc, mc);
+    return buf;
+}
+
+// The shape the batched launch uses: the tune cache's entry for the batch's
+// class, else the context's (default or last tuned) shape.
+Shape batch_shape_for(const hullf_ctx* c, uint32_t S, uint64_t n_total) {
+    auto it = c->tune.find(tune_key(c, S, n_total));
+    return it != c->tune.end() ? it->second : c->batch_shape;
+}
+
+// Cache file: one "key block ppt" line per entry; unknown or malformed
+// lines and unsupported shapes are ignored.
+void tune_load(hullf_ctx* c) {
+    if (c->tune_path.empty()) return;
+    FILE* f = std::fopen(c->tune_path.c_str(), "r");
+    if (!f) return;
+    char key[160];
+    int b = 0, p = 0;
+    while (std::fscanf(f, "%159s %d %d", key, &b, &p) == 3) {
+        const Shape sh{b, p};
+        if (shape_supported(sh)) c->tune[key] = sh;
+    }
+    std::fclose(f);
+}
+
+// Rewrite the cache file with the context's entries merged into the ones
+// already stored (written to a temporary file, then renamed).
+void tune_save(hullf_ctx* c) {
+    if (c->tune_path.empty()) return;
+    std::map<std::string, Shape> merged;
+    {
+        hullf_ctx tmp;
+        tmp.tune_path = c->tune_path;
+        tune_load(&tmp);
+        merged = tmp.tune;
+    }
+    for (auto& kv : c->tune) merged[kv.first] = kv.second;
+    const std::string dir = c->tune_path.substr(0, c->tune_path.find_last_of('/'));
+    if (!dir.empty() && dir != c->tune_path) {
+        std::string part;
+        for (size_t i = 0; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') {
+                part = dir.substr(0, i);
+                if (!part.empty()) (void)mkdir(part.c_str(), 0755);
+            }
+    }
+    const std::string tmpf = c->tune_path + ".tmp" + std::to_string((unsigned long)getpid());
+    FILE* f = std::fopen(tmpf.c_str(), "w");
+    if (!f) return;
+    for (auto& kv : merged) std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.block, kv.second.ppt);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) (void)std::rename(tmpf.c_str(), c->tune_path.c_str());
+    else (void)std::remove(tmpf.c_str());
 }
 
 hullf_status ensure_batch(hullf_ctx* c, uint32_t S, uint64_t n_total, hipStream_t s) {
@@ -511,6 +656,22 @@ hullf_status hullf_create(int device, size_t workspace_bytes, hullf_ctx_t* out) 
         const int b = std::atoi(e);
         if (b == 256 || b == 512 || b == 1024) c->compact_block = b;
     }
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+            std::string a = prop.gcnArchName;
+            c->arch = a.substr(0, a.find(':'));
+        }
+        if (c->arch.empty()) c->arch = "unknown";
+        if (const char* e = std::getenv("HULLF_TUNE_CACHE")) {
+            c->tune_path = e;
+        } else if (const char* x = std::getenv("XDG_CACHE_HOME")) {
+            c->tune_path = std::string(x) + "/hullf/tune.txt";
+        } else if (const char* h = std::getenv("HOME")) {
+            c->tune_path = std::string(h) + "/.cache/hullf/tune.txt";
+        }
+        tune_load(c);
+    }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = ws_alloc(c, &c->oct, 1);
     if (e == hipSuccess) e = ws_alloc(c, &c->part, 9ull * kReduceMaxGrid);
@@ -542,7 +703,7 @@ void hullf_destroy(hullf_ctx_t c) {
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt, c->boxes,
-                   c->groups_read,
+                   c->groups_read, c->poly16, c->part16,
                    c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_boxes, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -550,7 +711,7 @@ void hullf_destroy(hullf_ctx_t c) {
                    c->frow};
     for (void* p : fin)
         if (p) (void)hipFree(p);
-    void* host[] = {c->h_surv, c->h_xy, c->h_count, c->h_oct, c->h_fk, c->h_fv, c->h_total};
+    void* host[] = {c->h_surv, c->h_xy, c->h_count, c->h_oct, c->h_fk, c->h_fv, c->h_total, c->h_poly16};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     if (c->capture) (void)hipStreamDestroy(c->capture);
@@ -585,6 +746,37 @@ hullf_status hull_filter(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint3
         return HULLF_OK;
     }
     return enqueue_filter(c, d_pts, n, d_surv, cap, d_count, s);
+}
+
+hullf_status hullf_polygon16(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint32_t idx_out[16],
+                             void* stream) {
+    if (!c || !d_pts || !idx_out || n == 0 || n >= (1ull << 32) || !aligned8(d_pts)) return HULLF_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_HIP(ensure_poly16(c));
+    const float2* pts = reinterpret_cast<const float2*>(d_pts);
+    const int rg = reduce16_grid(n, c->cus);
+    CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce16(pts, n, c->part16, nullptr, rg, s); }));
+    CHECK_HIP(timed(c, 3, s, [&] { return launch_setup16(pts, n, c->poly16, c->part16, (uint32_t)rg, s); }));
+    CHECK_HIP(hipMemcpyAsync(c->h_poly16, c->poly16, sizeof(Poly16), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    if (c->h_poly16->status == 1) return HULLF_ENONFINITE;
+    if (c->h_poly16->status != 0) return HULLF_EDEVICE;
+    std::memcpy(idx_out, c->h_poly16->idx, 16 * sizeof(uint32_t));
+    return HULLF_OK;
+}
+
+hullf_status hull_filter16(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint32_t* d_surv, uint64_t cap,
+                           uint64_t* d_count, void* stream) {
+    if (!c || !d_count || n >= (1ull << 32)) return HULLF_EINVAL;
+    if (n > 0 && (!d_pts || !aligned8(d_pts) || (cap > 0 && !d_surv))) return HULLF_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        CHECK_HIP(launch_write_count(d_count, 0, s));
+        return HULLF_OK;
+    }
+    return enqueue_filter16(c, d_pts, n, d_surv, cap, d_count, s);
 }
 
 hullf_status hullf_flags(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint8_t* d_flags, void* stream) {
@@ -649,7 +841,7 @@ hullf_status hull_filter_batched_shape(hullf_ctx_t c, const hullf_pt* d_pts, con
                                        uint64_t* d_counts, int block, int ppt, void* stream) {
     hullf_status st = check_batch_args(c, d_pts, d_off, S, n_total, d_surv, d_counts);
     if (st != HULLF_OK || S == 0) return st;
-    Shape shape = c->batch_shape;
+    Shape shape = batch_shape_for(c, S, n_total);
     if (block) shape.block = block;
     if (ppt) shape.ppt = ppt;
     if (!shape_supported(shape)) return HULLF_EINVAL;
@@ -671,7 +863,7 @@ hullf_status hull_filter_segments(hullf_ctx_t c, const hullf_pt* d_pts, const ui
     if (st != HULLF_OK || S == 0) return st;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    const Shape shape = c->batch_shape;
+    const Shape shape = batch_shape_for(c, S, n_total);
     st = ensure_batch(c, S, n_total, s);
     if (st != HULLF_OK) return st;
     hullf_status r = HULLF_OK;
@@ -688,7 +880,7 @@ hullf_status hull_filter_batched(hullf_ctx_t c, const hullf_pt* d_pts, const uin
     if (st != HULLF_OK || S == 0) return st;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    const Shape shape = c->batch_shape;
+    const Shape shape = batch_shape_for(c, S, n_total);
     st = ensure_batch(c, S, n_total, s);
     if (st != HULLF_OK) return st;
     GraphEntry* hit = nullptr;
@@ -761,6 +953,8 @@ hullf_status hullf_autotune_batched(hullf_ctx_t c, const hullf_pt* d_pts, const 
     (void)hipEventDestroy(b);
     if (r != HULLF_OK) return r;
     c->batch_shape = best;
+    c->tune[tune_key(c, S, n_total)] = best;
+    tune_save(c);
     drop_graphs(c);
     if (best_block) *best_block = best.block;
     if (best_ppt) *best_ppt = best.ppt;

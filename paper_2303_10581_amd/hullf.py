@@ -44,6 +44,8 @@ def _load():
         "hullf_status_str": ([st], ctypes.c_char_p),
         "hullf_octagon": ([P, P, U64, P, P], st),
         "hull_filter": ([P, P, U64, P, U64, P, P], st),
+        "hullf_polygon16": ([P, P, U64, P, P], st),
+        "hull_filter16": ([P, P, U64, P, U64, P, P], st),
         "convex_hull": ([P, P, U64, P, U64, P, P], st),
         "hullf_flags": ([P, P, U64, P, P], st),
         "hull_from_survivors": ([P, P, U64, P, U64, P, U64, P, P], st),
@@ -144,6 +146,37 @@ class Context:
         _check(_load().hull_filter(self.handle, pts.data_ptr(), n, surv.data_ptr(), int(cap),
                                    count.data_ptr(), _stream(stream)), "hull_filter")
         return surv, count
+
+    def polygon16(self, pts, stream=None) -> np.ndarray:
+        """Indices V0..V15 of the 16-direction filter's polygon (synchronous)."""
+        pts = _points(pts)
+        out = np.zeros(16, dtype=np.uint32)
+        _check(_load().hullf_polygon16(self.handle, pts.data_ptr(), pts.shape[0], out.ctypes.data,
+                                       _stream(stream)), "hullf_polygon16")
+        return out
+
+    def hull_filter16(self, pts, surv=None, count=None, cap=None, stream=None):
+        """Enqueue the 16-direction filter; returns (surv, count) like hull_filter."""
+        torch = _torch()
+        pts = _points(pts)
+        n = pts.shape[0]
+        if surv is None:
+            surv = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+        if count is None:
+            count = torch.empty(1, dtype=torch.int64, device=pts.device)
+        if cap is None:
+            cap = surv.numel()
+        _check(_load().hull_filter16(self.handle, pts.data_ptr(), n, surv.data_ptr(), int(cap),
+                                     count.data_ptr(), _stream(stream)), "hull_filter16")
+        return surv, count
+
+    def survivors16(self, pts, stream=None):
+        """Ascending survivors of the 16-direction filter (synchronises)."""
+        surv, count = self.hull_filter16(pts, stream=stream)
+        c = int(count.item()) & ((1 << 64) - 1)
+        if c == COUNT_NONFINITE:
+            raise HullfError(ENONFINITE, "hull_filter16")
+        return surv[:c]
 
     def survivors(self, pts, stream=None):
         """Ascending survivor indices as an int32 device tensor (synchronises)."""
@@ -392,7 +425,7 @@ class Server:
 def exported_symbols():
     """Names of the C-ABI functions the binding expects."""
     return ["hullf_create", "hullf_destroy", "hullf_workspace", "hullf_status_str", "hullf_octagon", "hull_filter",
-            "convex_hull", "hullf_flags", "hull_from_survivors", "hull_filter_batched", "hull_filter_segments",
+            "hullf_polygon16", "hull_filter16", "convex_hull", "hullf_flags", "hull_from_survivors", "hull_filter_batched", "hull_filter_segments",
             "hull_filter_batched_shape", "hullf_autotune_batched", "hullf_timing_enable",
             "hullf_timing_read", "hullf_skip_stats", "hullf_server_create", "hullf_server_destroy", "hullf_server_submit",
             "hullf_server_wait", "hullf_server_stats"]

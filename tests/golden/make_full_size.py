@@ -17,6 +17,9 @@ Outputs:
   batch_4096.txt  the 4096-set batch (seed 6): one line per set with the
                   set's survivor count, hull length, and 16-hex-digit
                   prefixes of the survivor and hull hashes
+  full_size16.json  the 16-direction filter of the related work (Sec. 2)
+                  on the same single-set workloads: its 16 vertex indices and
+                  the survivor count and hash
 """
 from __future__ import annotations
 
@@ -38,6 +41,7 @@ import oracle  # noqa: E402
 from paper_2303_10581_amd import workloads  # noqa: E402
 
 FULL = os.path.join(HERE, "full_size.json")
+FULL16 = os.path.join(HERE, "full_size16.json")
 BATCH = os.path.join(HERE, "batch_4096.txt")
 
 # (name, kind, n, seed): the single-set workloads of the study cases
@@ -70,6 +74,18 @@ def single(name, kind, n, seed):
     return rec
 
 
+def single16(name, kind, n, seed):
+    t0 = time.time()
+    xy = workloads.by_kind(kind, n, seed)
+    rec = {"kind": kind, "n": n, "seed": seed, "points_sha256": sha(xy)}
+    rec["vertices"] = [int(v) for v in oracle.extremes16(xy)]
+    surv = oracle.survivors16(xy)
+    rec["survivors"] = int(surv.size)
+    rec["survivors_sha256"] = sha(surv.astype("<u4"))
+    print(f"{name} (16 directions): {rec['survivors']} survivors ({time.time() - t0:.0f} s)", flush=True)
+    return rec
+
+
 def batch_lines():
     pts, off, _ = workloads.batch(S=4096, seed=6)
     lines = [f"# sha256(points)={sha(pts)} S=4096 seed=6 n_total={pts.shape[0]}",
@@ -86,17 +102,28 @@ def batch_lines():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--only", nargs="*", default=None)
+    ap.add_argument("--filter16", action="store_true", help="only the 16-direction records")
     args = ap.parse_args()
     want = set(args.only) if args.only else None
     data = {}
     if os.path.exists(FULL):
         with open(FULL) as f:
             data = json.load(f)
+    data16 = {}
+    if os.path.exists(FULL16):
+        with open(FULL16) as f:
+            data16 = json.load(f)
     for name, kind, n, seed in SINGLE:
         if want is None or name in want:
-            data[name] = single(name, kind, n, seed)
-            with open(FULL, "w") as f:
-                json.dump(data, f, indent=1, sort_keys=True)
+            if not args.filter16:
+                data[name] = single(name, kind, n, seed)
+                with open(FULL, "w") as f:
+                    json.dump(data, f, indent=1, sort_keys=True)
+            data16[name] = single16(name, kind, n, seed)
+            with open(FULL16, "w") as f:
+                json.dump(data16, f, indent=1, sort_keys=True)
+    if args.filter16:
+        return
     if want is None or "batch_4096" in want:
         t0 = time.time()
         lines = batch_lines()

@@ -115,3 +115,22 @@ def test_out_of_range_survivor_index(ctx, torch_dev, m):
     assert e.value.status == hullf.EINVAL
     s[m // 2] = m // 2
     assert np.array_equal(ctx.hull_from_survivors(t, s), oracle.hull(xy))
+
+
+@pytest.mark.parametrize("radius", [100.0, 1000.0, 30000.0])
+def test_grid_snapped_circle_device_finish(ctx, torch_dev, radius):
+    """Circle points rounded to an integer grid: long runs of repeated
+    points, runs of equal x across chunk boundaries (vertical runs at both
+    ends), and collinear points on the hull, through the chunk chains and
+    the device merge of the chunk chains."""
+    c = workloads.circle(1_000_003, 71)
+    xy = np.round(c.astype(np.float64) * radius).astype(np.float32)
+    _hull_check(ctx, torch_dev, xy, f"grid-snapped circle r={radius}")
+
+
+def test_merge_tree_many_chunks(ctx, torch_dev):
+    """A displaced circumference large enough that the chunk levels stop
+    with many chunk chains, so the merge tree runs many rounds, with an odd
+    number of chains in some of them."""
+    xy = workloads.displaced(6_000_037, 73)
+    _hull_check(ctx, torch_dev, xy, "displaced 6e6")

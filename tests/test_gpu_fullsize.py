@@ -104,3 +104,29 @@ def test_full_batched_config_survivors_and_hulls(ctx, torch_dev):
         if h.size != nhull or _sha(h)[:16] != hh:
             bad.append(("hull", s, h.size, nhull))
     assert not bad, bad[:10]
+
+
+def _full16():
+    with open(os.path.join(GOLDEN, "full_size16.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["normal_1e8", "circle_1e8", "displaced_1e8", "circle_jitter_5e8"])
+def test_full_size_filter16(ctx, torch_dev, name):
+    """The 16-direction filter (Sec. 2) at the full sizes: its 16 vertices
+    and its survivor list, bit for bit."""
+    import torch
+    rec = _full16()[name]
+    say(f"[gpu] full size filter16 {name}: n={rec['n']} seed={rec['seed']}")
+    xy = workloads.by_kind(rec["kind"], rec["n"], rec["seed"])
+    assert _sha(xy) == rec["points_sha256"], "the input generator changed; rerun make_full_size.py"
+    t = torch.from_numpy(xy).to(torch_dev)
+    del xy
+    assert ctx.polygon16(t).tolist() == rec["vertices"], name
+    surv, count = ctx.hull_filter16(t)
+    c = int(count.item())
+    assert c == rec["survivors"], (name, c, rec["survivors"])
+    got = surv[:c].cpu().numpy().astype("<u4")
+    assert _sha(got) == rec["survivors_sha256"], name
+    del surv, got, t
+    torch.cuda.empty_cache()

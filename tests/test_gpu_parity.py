@@ -249,3 +249,26 @@ def test_launch_settings(torch_dev, monkeypatch, shape, compact, skip, per_cu):
 def test_config_small_normal_1e6(ctx, torch_dev):
     xy = workloads.normal(1_000_000, 1)
     _check_all(ctx, torch_dev, xy, "normal 1e6 seed 1")
+
+
+def test_region_skip_misaligned(ctx, torch_dev):
+    """Region skip with 8-byte (not 16-byte) aligned points: blocks that read
+    only the few groups outside their passing boxes load them with 8-byte
+    loads."""
+    base = cases.named_sets(1_000_003, 59)["normal"]
+    xy = cases.with_near_edge_points(base, oracle.extremes, per_edge=300, seed=19)
+    xy = xy[np.random.default_rng(11).permutation(xy.shape[0])]
+    _check_all(ctx, torch_dev, xy, "scattered near-edge normal, misaligned", hull=False, offset=1)
+
+
+def test_skipping_and_dense_blocks_in_one_set(ctx, torch_dev):
+    """A normal cloud (most groups inside the discard region) followed by a
+    ring around it (every group read): blocks that list the few groups to
+    read and blocks that stream every group run in the same launch."""
+    cloud = workloads.normal(3_000_017, 61)
+    ring = (workloads.circle(2_000_003, 62).astype(np.float64) * 6.0).astype(np.float32)
+    xy = np.concatenate([cloud, ring, cloud[:500_000]], axis=0)
+    ctx.skip_stats()
+    _check_all(ctx, torch_dev, xy, "cloud then ring", hull=False)
+    read, total = ctx.skip_stats()
+    assert 0 < read < total, (read, total)
