@@ -170,6 +170,24 @@ hullf_status hull_filter16(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
                            uint32_t *d_surv, uint64_t cap, uint64_t *d_count,
                            void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the same work
+ * and results as hull_filter, with no context.  Its scratch (partial extreme
+ * records, octagon record, block counts, keep bits, region-skip boxes) lives
+ * in a fixed device array of HULLF_NOALLOC_SCRATCH_BYTES that every device
+ * the library runs on holds until the process ends; the call allocates
+ * nothing.  Runs on the current device; the first call on a device looks
+ * up that device's array (make it outside any graph capture).  n above
+ * HULLF_NOALLOC_MAX_POINTS returns HULLF_ENOMEM with nothing enqueued and
+ * the outputs untouched; other arguments and results as for hull_filter.
+ * Every call on one device shares that device's array and the array keeps
+ * the last call's contents, so calls that overlap on one device (other
+ * streams, other host threads) race: the caller must order them. */
+#define HULLF_NOALLOC_MAX_POINTS (1ull << 25)
+#define HULLF_NOALLOC_SCRATCH_BYTES (6ull << 20)
+hullf_status hull_filter_noalloc(const hullf_pt *d_pts, uint64_t n, uint32_t *d_surv,
+                                 uint64_t cap, uint64_t *d_count, void *stream);
+
 /* Debug export of the bit vector of Sec. 3.2 (one byte per point, 1 =
  * survives), asynchronous.  d_flags: n device bytes.  If a coordinate is not
  * finite every flag is set to 2. */

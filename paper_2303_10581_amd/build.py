@@ -21,7 +21,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhullf.so")
 ARCH = os.environ.get("HULLF_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["hullf_kernels.hip", "hullf_finish.hip"]
+HIP_SOURCES = ["hullf_kernels.hip", "hullf_finish.hip", "hullf_noalloc.hip"]
 HOST_SOURCES = ["hullf_runtime.cpp", "hullf_server.cpp", "hull_host.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", INCLUDE, "-I", CSRC]

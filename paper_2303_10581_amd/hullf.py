@@ -44,6 +44,7 @@ def _load():
         "hullf_status_str": ([st], ctypes.c_char_p),
         "hullf_octagon": ([P, P, U64, P, P], st),
         "hull_filter": ([P, P, U64, P, U64, P, P], st),
+        "hull_filter_noalloc": ([P, U64, P, U64, P, P], st),
         "hullf_polygon16": ([P, P, U64, P, P], st),
         "hull_filter16": ([P, P, U64, P, U64, P, P], st),
         "convex_hull": ([P, P, U64, P, U64, P, P], st),
@@ -422,10 +423,31 @@ class Server:
         return _fields(s)
 
 
+NOALLOC_MAX_POINTS = 1 << 25
+
+
+def hull_filter_noalloc(pts, surv=None, count=None, cap=None, stream=None):
+    """hull_filter without a context and without device allocation inside the
+    library (scratch in a fixed device array).  Enqueues on the current
+    device; returns (surv int32[cap], count int64[1]) device tensors."""
+    torch = _torch()
+    pts = _points(pts)
+    n = pts.shape[0]
+    if surv is None:
+        surv = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=pts.device)
+    if cap is None:
+        cap = surv.numel()
+    _check(_load().hull_filter_noalloc(pts.data_ptr(), n, surv.data_ptr(), int(cap), count.data_ptr(),
+                                       _stream(stream)), "hull_filter_noalloc")
+    return surv, count
+
+
 def exported_symbols():
     """Names of the C-ABI functions the binding expects."""
     return ["hullf_create", "hullf_destroy", "hullf_workspace", "hullf_status_str", "hullf_octagon", "hull_filter",
-            "hullf_polygon16", "hull_filter16", "convex_hull", "hullf_flags", "hull_from_survivors", "hull_filter_batched", "hull_filter_segments",
+            "hull_filter_noalloc", "hullf_polygon16", "hull_filter16", "convex_hull", "hullf_flags", "hull_from_survivors", "hull_filter_batched", "hull_filter_segments",
             "hull_filter_batched_shape", "hullf_autotune_batched", "hullf_timing_enable",
             "hullf_timing_read", "hullf_skip_stats", "hullf_server_create", "hullf_server_destroy", "hullf_server_submit",
             "hullf_server_wait", "hullf_server_stats"]
