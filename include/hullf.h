@@ -95,7 +95,8 @@ typedef enum {
  *   HULLF_REGION_SKIP=0           no region skip (every group is read)
  *   HULLF_CLASSIFY_PER_CU=k       inside-test blocks per compute unit
  *   HULLF_COMPACT_BLOCK=b         compaction block size (256|512|1024)
- *   HULLF_REDUCE_GRID=g           reduction blocks, 1..4096 (default 8 per CU)
+ *   HULLF_REDUCE_GRID=g           reduction blocks, 1..4096 (default 4 per CU)
+ *   HULLF_BATCH_REDUCE_PER_CU=k   batched reduction blocks per CU (1..16)
  *   HULLF_FINISH=host             hull finishing always on the host
  *   HULLF_TUNE_CACHE=path         tune cache file of the batched launch
  *                                 (default $XDG_CACHE_HOME/hullf/tune.txt or
@@ -143,7 +144,7 @@ hullf_status convex_hull(hullf_ctx_t ctx, const hullf_pt *d_pts, uint64_t n,
  * hull_filter and the batched calls write them; every index must be below n
  * (otherwise HULLF_EINVAL).  h_hull / cap / h_count as for convex_hull: the
  * hull of the listed points, by indices into d_pts; of repeated
- * coordinates the first listed index is kept.  From 2^18 survivors on the
+ * coordinates the first listed index is kept.  From 2^14 survivors on the
  * points are sorted, reduced by chunked monotone chains and the chunk
  * chains merged on the device; only the lower and upper hull chains are
  * copied back. */

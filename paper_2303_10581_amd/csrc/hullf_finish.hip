@@ -1,12 +1,17 @@
 // Hull finishing on the device (the monotone chain of Sec. 3.3 for large
-// survivor sets): lexicographic sort of the survivors, then monotone chains
-// over fixed chunks of the sorted sequence, repeated on the chain vertices
-// until few points remain; the host chains what is left.
+// survivor sets): sort of the survivors by x, one representative point per
+// run of equal x and side, monotone chains over fixed chunks of the
+// representatives, repeated on the chain vertices while that pays, then a
+// merge tree of the chunk chains; only the lower and the upper hull chains
+// go back to the host.
 //
 //   k_fin_keys     64-bit key (x, then y, order-preserving bits, -0 = +0)
 //                  and the point index of every survivor
-//   k_rs_*         stable LSD radix sort of (key, index), 8 passes of 8 bits
-//   k_chain        one thread per chunk: strict lower and upper chains of the
+//   k_rs_*         stable LSD radix sort of (key, index), passes of 8 bits
+//                  (the hull path sorts by the key's x half only)
+//   k_runs         per run of equal x, the first point of least (lower
+//                  side) or greatest (upper side) y
+//   k_chain        one thread per chunk: strict lower or upper chain of the
 //                  chunk (positions into the sorted sequence)
 //   k_scan_counts  exclusive scan of the chunk chain lengths (one block)
 //   k_chain_gather the chain vertices of all chunks, in order
@@ -18,15 +23,18 @@
 // Why chunks are enough: a point that is not a vertex of its chunk's lower
 // chain lies on or above a segment between two points of the chunk, so it
 // is not a strict vertex of the lower hull of all points (likewise upper).
-// Equal coordinates sort together with the lowest index first (the sort is
-// stable and the survivors come in ascending index order); only the first
-// of a run enters a chain.
+// The sort is stable and the survivors come in ascending index order, so a
+// run of equal x holds its points in index order and its representative is
+// the lowest index among equal coordinates; representatives are distinct
+// and strictly increasing in x.
 //
 // Orientation is exact: binary64 determinant with Shewchuk's error bound
-// first; otherwise the determinant of FP32 coordinates is the sum of six
-// products that binary64 represents exactly, summed as a floating-point
-// expansion (Two-Sum, Grow-Expansion), whose largest component gives the
-// sign.  Built with -ffp-contract=off.
+// first; then, if the coordinate differences and the two products are exact
+// in binary64 (checked), the sign of the determinant's one rounding;
+// otherwise the determinant of FP32 coordinates is the sum of six products
+// that binary64 represents exactly, summed as a floating-point expansion
+// (Two-Sum, Grow-Expansion), whose largest component gives the sign.  Built
+// with -ffp-contract=off.
 
 #include <hip/hip_runtime.h>
 
@@ -110,12 +118,16 @@ __global__ __launch_bounds__(256) void k_rs_rowsum(const uint32_t* __restrict__ 
 }
 
 // Block d: output positions of digit d per tile = (items of smaller digits)
-// + (items of digit d in earlier tiles).
+// + (items of digit d in earlier tiles).  Each round scans 1024 tiles: four
+// consecutive per thread, a shuffle scan inside each wave, one LDS exchange
+// of the four wave totals.
 __global__ __launch_bounds__(256) void k_rs_rowscan(uint32_t* __restrict__ hist, uint32_t tiles,
                                                     const uint32_t* __restrict__ rowsum) {
+    constexpr int NW = 256 / 64;
     __shared__ uint32_t s[256];
+    __shared__ uint32_t wsum[NW];
     __shared__ uint32_t carry;
-    const uint32_t d = blockIdx.x, t = threadIdx.x;
+    const uint32_t d = blockIdx.x, t = threadIdx.x, lane = t & 63u, wave = t >> 6;
     s[t] = (t < d) ? rowsum[t] : 0u;
     __syncthreads();
     for (uint32_t o = 128; o > 0; o >>= 1) {
@@ -125,22 +137,38 @@ __global__ __launch_bounds__(256) void k_rs_rowscan(uint32_t* __restrict__ hist,
     if (t == 0) carry = s[0];
     __syncthreads();
     uint32_t* row = hist + (uint64_t)d * tiles;
-    for (uint32_t b = 0; b < tiles; b += 256) {
-        const uint32_t i = b + t;
-        const uint32_t v = (i < tiles) ? row[i] : 0u;
-        s[t] = v;
-        __syncthreads();
-        for (uint32_t o = 1; o < 256; o <<= 1) {
-            const uint32_t u = (t >= o) ? s[t - o] : 0u;
-            __syncthreads();
-            s[t] += u;
-            __syncthreads();
+    for (uint32_t b = 0; b < tiles; b += 1024u) {
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = b + 4u * t + (uint32_t)q;
+            v[q] = (i < tiles) ? row[i] : 0u;
+            sum += v[q];
         }
-        const uint32_t excl = carry + s[t] - v;
-        if (i < tiles) row[i] = excl;
-        const uint32_t tot = s[255];
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+            if ((int)lane >= o) incl += u;
+        }
+        if (lane == 63u) wsum[wave] = incl;
         __syncthreads();
-        if (t == 0) carry += tot;
+        uint32_t before = carry, all = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t x = wsum[w];
+            if (w < (int)wave) before += x;
+            all += x;
+        }
+        uint32_t e = before + incl - sum;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = b + 4u * t + (uint32_t)q;
+            if (i < tiles) row[i] = e;
+            e += v[q];
+        }
+        __syncthreads();   // every thread has read carry and wsum
+        if (t == 0) carry += all;
         __syncthreads();
     }
 }
@@ -296,13 +324,33 @@ __device__ __noinline__ int orient_exact_dev(float ox, float oy, float ax, float
     return 0;
 }
 
+// True if a - b of two binary32 values is exact in binary64: with
+// a = Ma 2^(Ea-23), b = Mb 2^(Eb-23) (|M| < 2^24, E from the exponent field,
+// at least -126), the difference is K 2^(min(Ea,Eb)-23) with
+// |K| < 2^(25 + |Ea - Eb|), so |Ea - Eb| <= 28 keeps K within 53 bits.
+__device__ __forceinline__ bool diff_exact(float a, float b) {
+    const int ea = max((int)((__float_as_uint(a) >> 23) & 0xFFu), 1);
+    const int eb = max((int)((__float_as_uint(b) >> 23) & 0xFFu), 1);
+    return abs(ea - eb) <= 28;
+}
+
 __device__ __forceinline__ int orient_dev(float ox, float oy, float ax, float ay, float bx, float by) {
-    const double l = ((double)ax - (double)ox) * ((double)by - (double)oy);
-    const double r = ((double)ay - (double)oy) * ((double)bx - (double)ox);
+    const double dx1 = (double)ax - (double)ox, dy2 = (double)by - (double)oy;
+    const double dy1 = (double)ay - (double)oy, dx2 = (double)bx - (double)ox;
+    const double l = dx1 * dy2;
+    const double r = dy1 * dx2;
     const double det = l - r;
     const double bound = 0x1.8000000000004p-52 * (fabs(l) + fabs(r));
     if (det > bound) return 1;
     if (-det > bound) return -1;
+    // Near-degenerate (nearly collinear points, as on a densely sampled
+    // circle): when the four differences and the two products are exact
+    // (an FMA returns each product's rounding error, zero iff it is exact;
+    // no underflow is possible for binary32 inputs), det is the one rounding
+    // of the exact determinant and has its sign.
+    if (diff_exact(ax, ox) && diff_exact(by, oy) && diff_exact(ay, oy) && diff_exact(bx, ox) &&
+        fma(dx1, dy2, -l) == 0.0 && fma(dy1, dx2, -r) == 0.0)
+        return (det > 0.0) ? 1 : ((det < 0.0) ? -1 : 0);
     return orient_exact_dev(ox, oy, ax, ay, bx, by);
 }
 
@@ -369,6 +417,75 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
     }
     uint32_t* o = out + (uint64_t)b;
     for (uint32_t j = 0; j < len; ++j) o[j] = b + st[64u * j];
+    cnt[c] = len;
+}
+
+// Run representatives of keys sorted by x alone (stable, so every run of
+// equal x holds its points in ascending index order): for the lower side
+// (sign 1) the first point of least y of each run, for the upper side the
+// first point of greatest y.  A point above (below) another of the same x is
+// no strict vertex of the lower (upper) hull, except the two ends of the
+// hull's chains: the lexicographically greatest point ends the lower chain
+// and the smallest starts the upper one; the host adds those two back when
+// it joins the chains.  Thread c owns the runs whose first point lies in
+// positions [c*C, (c+1)*C) and walks each to its end (past the chunk if it
+// must); it writes the representatives' positions to out[c*C ...] (at most
+// C of them) and their number to cnt[c].  Keys are read kChainPrefetch at a
+// time.
+__global__ __launch_bounds__(64) void k_runs(const uint64_t* __restrict__ keys, uint32_t m, uint32_t C, int sign,
+                                             uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
+    const uint32_t c = blockIdx.x * 64u + threadIdx.x;
+    const uint32_t nch = (m + C - 1) / C;
+    if (c >= nch) return;
+    const uint32_t b = c * C, e = min(m, b + C);
+    uint32_t* o = out + (uint64_t)b;
+    uint32_t len = 0;
+    bool have = false;        // a run is open
+    uint32_t rx = 0;          // its x (ordered bits)
+    uint32_t best = 0, bpos = 0;
+    // the run open at b (if any) belongs to an earlier chunk
+    uint32_t prevx = (b > 0) ? (uint32_t)(keys[b - 1] >> 32) : 0u;
+    bool skipping = b > 0;
+    for (uint32_t i0 = b; i0 < m; i0 += kChainPrefetch) {
+        uint64_t kb[kChainPrefetch];
+#pragma unroll
+        for (uint32_t u = 0; u < kChainPrefetch; ++u) kb[u] = (i0 + u < m) ? keys[i0 + u] : 0ull;
+        bool done = false;
+#pragma unroll
+        for (uint32_t u = 0; u < kChainPrefetch; ++u) {
+            const uint32_t i = i0 + u;
+            if (i >= m) {
+                done = true;
+                break;
+            }
+            const uint32_t kx = (uint32_t)(kb[u] >> 32), ky = (uint32_t)kb[u];
+            if (skipping) {
+                if (kx == prevx && i < e) continue;   // still in the earlier chunk's run
+                skipping = false;
+            }
+            if (have && kx == rx) {   // same run
+                if (sign > 0 ? ky < best : ky > best) {
+                    best = ky;
+                    bpos = i;
+                }
+                continue;
+            }
+            if (have) {   // the open run ended at i - 1
+                o[len++] = bpos;
+                have = false;
+            }
+            if (i >= e) {   // no more runs start in this chunk
+                done = true;
+                break;
+            }
+            have = true;
+            rx = kx;
+            best = ky;
+            bpos = i;
+        }
+        if (done) break;
+    }
+    if (have) o[len++] = bpos;
     cnt[c] = len;
 }
 
@@ -524,28 +641,30 @@ __global__ __launch_bounds__(256) void k_bridge(const uint64_t* __restrict__ key
     }
 }
 
-// The merged chains in order: pair p's chain goes to noff[p].
+// The merged chains in order: pair p's chain goes to noff[p].  Task
+// (p, c) copies part c of pair p's merged chain (bpp parts per pair), so
+// that the last rounds, with few and long chains, still spread the copy
+// over many waves.
 __global__ __launch_bounds__(256) void k_merge_gather(const uint64_t* __restrict__ keys,
                                                       const uint32_t* __restrict__ vals,
                                                       const uint32_t* __restrict__ off, uint32_t nc,
                                                       const uint2* __restrict__ br,
-                                                      const uint32_t* __restrict__ noff, uint64_t* __restrict__ kout,
-                                                      uint32_t* __restrict__ vout) {
-    const uint32_t lane = threadIdx.x & 63u;
+                                                      const uint32_t* __restrict__ noff, uint32_t bpp,
+                                                      uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
     const uint32_t np = (nc + 1u) / 2u;
-    for (uint32_t p = blockIdx.x * 4u + (threadIdx.x >> 6); p < np; p += gridDim.x * 4u) {
+    const uint64_t tasks = (uint64_t)np * bpp;
+    for (uint64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
+        const uint32_t p = (uint32_t)(task / bpp), c = (uint32_t)(task % bpp);
         const uint32_t a0 = off[2u * p], a1 = off[2u * p + 1u];
         const uint32_t b1 = (2u * p + 1u < nc) ? off[2u * p + 2u] : a1;
         const uint2 r = br[p];
         const uint32_t o = noff[p];
-        for (uint32_t k = lane; k < r.x; k += 64u) {
-            kout[o + k] = keys[a0 + k];
-            vout[o + k] = vals[a0 + k];
-        }
-        const uint32_t nb = (b1 - a1) - r.y;
-        for (uint32_t k = lane; k < nb; k += 64u) {
-            kout[o + r.x + k] = keys[a1 + r.y + k];
-            vout[o + r.x + k] = vals[a1 + r.y + k];
+        const uint32_t len = r.x + ((b1 - a1) - r.y);
+        const uint32_t k0 = (uint32_t)((uint64_t)len * c / bpp), k1 = (uint32_t)((uint64_t)len * (c + 1u) / bpp);
+        for (uint32_t k = k0 + threadIdx.x; k < k1; k += 256u) {
+            const uint32_t src = (k < r.x) ? a0 + k : a1 + r.y + (k - r.x);
+            kout[o + k] = keys[src];
+            vout[o + k] = vals[src];
         }
     }
 }
@@ -567,13 +686,13 @@ hipError_t launch_finish_keys(const float2* pts, uint64_t n, const uint32_t* sur
 }
 
 hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
-                              uint32_t* hist, uint32_t* rowsum, hipStream_t stream) {
+                              uint32_t* hist, uint32_t* rowsum, uint32_t first_shift, hipStream_t stream) {
     const uint32_t tiles = finish_sort_tiles(m);
     uint64_t* ka = keys;
     uint32_t* va = vals;
     uint64_t* kb = keys2;
     uint32_t* vb = vals2;
-    for (uint32_t shift = 0; shift < 64; shift += 8) {
+    for (uint32_t shift = first_shift; shift < 64; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(kRsBlock), 0, stream, ka, m, shift, tiles, hist);
         hipLaunchKernelGGL(k_rs_rowsum, dim3(kRsBins), dim3(256), 0, stream, hist, tiles, rowsum);
         hipLaunchKernelGGL(k_rs_rowscan, dim3(kRsBins), dim3(256), 0, stream, hist, tiles, rowsum);
@@ -584,7 +703,7 @@ hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, u
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    return hipSuccess;   // eight passes: the result is back in keys / vals
+    return hipSuccess;   // an even number of passes: the result is back in keys / vals
 }
 
 hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, int dedup, uint32_t* chain,
@@ -592,6 +711,14 @@ hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, 
     if (C == 0 || C > kChainMaxC) return hipErrorInvalidValue;
     const uint32_t nch = (m + C - 1) / C;
     hipLaunchKernelGGL(k_chain, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup, chain, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_runs(const uint64_t* keys, uint32_t m, uint32_t C, int sign, uint32_t* reps, uint32_t* cnt,
+                       hipStream_t stream) {
+    if (C == 0) return hipErrorInvalidValue;
+    const uint32_t nch = (m + C - 1) / C;
+    hipLaunchKernelGGL(k_runs, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, reps, cnt);
     return hipGetLastError();
 }
 
@@ -622,7 +749,12 @@ hipError_t launch_bridge(const uint64_t* keys, const uint32_t* off, uint32_t nc,
 hipError_t launch_merge_gather(const uint64_t* keys, const uint32_t* vals, const uint32_t* off, uint32_t nc,
                                const uint2* br, const uint32_t* noff, uint64_t* kout, uint32_t* vout, int grid,
                                hipStream_t stream) {
-    hipLaunchKernelGGL(k_merge_gather, dim3(grid), dim3(256), 0, stream, keys, vals, off, nc, br, noff, kout, vout);
+    const uint32_t np = (nc + 1u) / 2u;
+    const uint32_t bpp = std::max<uint32_t>(1u, (uint32_t)grid / std::max<uint32_t>(np, 1u));
+    const uint64_t tasks = (uint64_t)np * bpp;
+    const int g = (int)std::min<uint64_t>(tasks, (uint64_t)std::max(grid, 1));
+    hipLaunchKernelGGL(k_merge_gather, dim3(g), dim3(256), 0, stream, keys, vals, off, nc, br, noff, bpp, kout,
+                       vout);
     return hipGetLastError();
 }
 

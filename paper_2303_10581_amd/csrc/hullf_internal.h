@@ -149,7 +149,8 @@ hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t
 hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
                         SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
                         Octagon* octs, uint64_t* bits, uint32_t* blkcnt, uint32_t max_items, uint32_t* surv,
-                        uint64_t* counts, float4* box, Shape shape, int cus, hipStream_t stream);
+                        uint64_t* counts, float4* box, Shape shape, int cus, int reduce_per_cu,
+                        hipStream_t stream);
 uint64_t batch_max_items(uint64_t n_total, uint32_t S);
 uint32_t batch_item_words();
 uint64_t batch_max_rtiles(uint64_t n_total, uint32_t S);
@@ -165,8 +166,14 @@ uint32_t finish_sort_tiles(uint32_t m);
 // An index >= n sets *bad (a word the caller zeroed) instead of being read.
 hipError_t launch_finish_keys(const float2* pts, uint64_t n, const uint32_t* surv, uint32_t m, uint64_t* keys,
                               uint32_t* vals, uint64_t* bad, int grid, hipStream_t stream);
+// Stable LSD passes of 8 bits from bit first_shift up to bit 63 (0: the
+// whole key; 32: x alone); first_shift must leave an even number of passes.
 hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
-                              uint32_t* hist, uint32_t* rowsum, hipStream_t stream);
+                              uint32_t* hist, uint32_t* rowsum, uint32_t first_shift, hipStream_t stream);
+// Run representatives of keys sorted by x alone (see k_runs): positions into
+// reps (chunk c's at c*C), counts per chunk into cnt.
+hipError_t launch_runs(const uint64_t* keys, uint32_t m, uint32_t C, int sign, uint32_t* reps, uint32_t* cnt,
+                       hipStream_t stream);
 // Chains of chunks of C sorted points: chain holds m words (chunk c's
 // chain at c*C), cnt ceil(m/C) words.  sign 1 = lower, -1 = upper.
 hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, int dedup, uint32_t* chain,

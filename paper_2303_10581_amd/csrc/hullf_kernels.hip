@@ -952,80 +952,66 @@ __device__ __forceinline__ uint32_t scan_chunk(const float2* __restrict__ pts, u
     return lowest;
 }
 
-// One point set, pass 2 (one block of 8 waves): merge the `nblocks` partial
-// records (max per direction, OR of the NaN flags); wave j then finds the
-// lowest index attaining E_j in the chunk that won direction j, and wave 0
-// builds the octagon.
-constexpr int kSetupBlock = 512;
-__global__ __launch_bounds__(kSetupBlock) void k_setup(const float2* __restrict__ pts, uint64_t n, Octagon* oct,
-                                                       const unsigned long long* __restrict__ part,
-                                                       uint32_t nblocks) {
-    constexpr int NW = kSetupBlock / 64;
-    static_assert(NW == 8, "one wave per direction");
-    __shared__ unsigned long long sh_m[9][NW];
-    __shared__ unsigned long long sh_k[8];
-    __shared__ float2 sh_pt[8];
-    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-    unsigned long long m[9];
+// One point set, pass 2 (one block of NV waves): wave j merges direction j
+// of the `nblocks` partial records (direction-major rows: a wave reads its
+// row with lane-strided loads, all issued before any is used, then a wave
+// maximum; wave 0 also ORs the NaN-flag row), finds the lowest index
+// attaining key j in the chunk that won it, and wave 0 builds the polygon
+// record.  No barrier separates a direction's merge from its scan: two
+// dependent memory round trips in all.  NV = 8: the octagon (keys as the
+// reduction tracks them, the "min" directions negated); NV = 16: the
+// 16-direction polygon (every key a maximum).
+template <int NV>
+__global__ __launch_bounds__(64 * NV) void k_setup(const float2* __restrict__ pts, uint64_t n, Poly<NV>* poly,
+                                                   const unsigned long long* __restrict__ part, uint32_t nblocks) {
+    constexpr uint32_t R = kReduceMaxGrid / 64;   // words per lane of a full row
+    __shared__ unsigned long long sh_k[NV];
+    __shared__ unsigned long long sh_nf;
+    __shared__ float2 sh_pt[NV];
+    const uint32_t lane = lane_id(), j = threadIdx.x >> 6;
+    const unsigned long long* row = part + (uint64_t)j * kReduceMaxGrid;
+    const unsigned long long* nfrow = part + (uint64_t)NV * kReduceMaxGrid;
+    unsigned long long m = 0ull, nf = 0ull;
+    // lanes read words lane, lane + 64, ...: 16 at a time, all loads of a
+    // batch issued before the maxima (one round trip for up to 1024 blocks)
+#pragma unroll 1
+    for (uint32_t k0 = 0; k0 < R && 64u * k0 < nblocks; k0 += 16u) {
+        unsigned long long w[16], f[16];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) m[j] = 0ull;
-    // Records are direction-major (part[j * kReduceMaxGrid + block]): thread
-    // t reads blocks 4t..4t+3 of every direction as two 16-byte loads, all
-    // issued before any is used (one memory round trip for 2048 blocks).
-    // Words past nblocks (stale records of earlier launches) are replaced
-    // by 0, the identity of both the maximum and the OR.
-    static_assert(kReduceMaxGrid % (4 * kSetupBlock) == 0, "whole rounds of records");
-    const uint32_t rounds = (nblocks + 4u * kSetupBlock - 1u) / (4u * kSetupBlock);
-    for (uint32_t r = 0; r < rounds; ++r) {
-        const uint32_t b0 = 4u * (r * kSetupBlock + t);
-        ulonglong2 w[9][2];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            const ulonglong2* src = reinterpret_cast<const ulonglong2*>(part + (uint64_t)j * kReduceMaxGrid + b0);
-            w[j][0] = src[0];
-            w[j][1] = src[1];
+        for (uint32_t k = 0; k < 16; ++k) {
+            const uint32_t b = lane + 64u * (k0 + k);
+            w[k] = (b < nblocks) ? row[b] : 0ull;
+            f[k] = (j == 0 && b < nblocks) ? nfrow[b] : 0ull;
         }
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            const unsigned long long e0 = (b0 + 0u < nblocks) ? w[j][0].x : 0ull;
-            const unsigned long long e1 = (b0 + 1u < nblocks) ? w[j][0].y : 0ull;
-            const unsigned long long e2 = (b0 + 2u < nblocks) ? w[j][1].x : 0ull;
-            const unsigned long long e3 = (b0 + 3u < nblocks) ? w[j][1].y : 0ull;
-            m[j] = (j == 8) ? (m[j] | e0 | e1 | e2 | e3) : max(max(m[j], max(e0, e1)), max(e2, e3));
+        for (uint32_t k = 0; k < 16; ++k) {
+            m = max(m, w[k]);
+            nf |= f[k];
         }
     }
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
-        unsigned long long v = m[j];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, 64);
-            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, 64);
-            const unsigned long long u = ((unsigned long long)hi << 32) | lo;
-            v = (j == 8) ? (v | u) : max(v, u);
-        }
-        if (lane == 0) sh_m[j][wave] = v;
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)m, o, 64);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(m >> 32), o, 64);
+        m = max(m, ((unsigned long long)hi << 32) | lo);
+        const uint32_t flo = (uint32_t)__shfl_xor((int)(uint32_t)nf, o, 64);
+        const uint32_t fhi = (uint32_t)__shfl_xor((int)(uint32_t)(nf >> 32), o, 64);
+        nf |= ((unsigned long long)fhi << 32) | flo;
     }
-    __syncthreads();
-    {
-        const int j = (int)wave;
-        unsigned long long key = 0ull;
-        for (int w = 0; w < NW; ++w) key = max(key, sh_m[j][w]);
-        unsigned long long res = 0ull;
-        if (key != 0ull) {
-            const bool is_max = (j == 0 || j == 1 || j == 2 || j == 7);
-            const float kv = from_ordered((uint32_t)(key >> 32));
-            const uint32_t idx = scan_chunk(pts, 0, n, unpack_idx(key), j, is_max ? kv : -kv, &sh_pt[j]);
-            if (idx != 0xFFFFFFFFu) res = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - idx);
-        }
-        if (lane == 0) sh_k[j] = res;
+    m = uniform_u64(m);
+    unsigned long long res = 0ull;
+    if (m != 0ull) {
+        const float kv = from_ordered((uint32_t)(m >> 32));
+        const bool neg = (NV == 8) && !(j == 0 || j == 1 || j == 2 || j == 7);
+        const uint32_t idx = scan_chunk<NV>(pts, 0, n, unpack_idx(m), (int)j, neg ? -kv : kv, &sh_pt[j]);
+        if (idx != 0xFFFFFFFFu) res = (m & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - idx);
+    }
+    if (lane == 0) {
+        sh_k[j] = res;
+        if (j == 0) sh_nf = nf;
     }
     __syncthreads();
-    if (t < 64) {
-        unsigned long long nf = 0ull;
-        for (int w = 0; w < NW; ++w) nf |= sh_m[8][w];
-        (void)setup_octagon(pts, 0, n, sh_k[lane & 7u], (uint32_t)nf, oct, sh_pt);
-    }
+    if (j == 0) (void)setup_octagon<NV>(pts, 0, n, sh_k[lane & (NV - 1)], (uint32_t)sh_nf, poly, sh_pt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1036,7 +1022,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const float2* __restrict_
 // Every key is tracked as a maximum (keys k + 8 as the negated minimum of
 // line k), with the chunk in which it last strictly improved; the block
 // records (key, first point of the lowest such chunk over its holders + 1),
-// and k_setup16 scans that chunk for the lowest index.  Up to 128 registers
+// and k_setup<16> scans that chunk for the lowest index.  Up to 128 registers
 // per lane (32 running values and chunks, 16 coordinates).
 constexpr int kR16PerCU = 4;   // blocks per CU at the occupancy the registers allow
 
@@ -1154,75 +1140,6 @@ __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
             (c != 0xFFFFFFFFu) ? pack_key(best, (uint32_t)((uint64_t)c * CH + 1u)) : 0ull;
     } else if (t == 16) {
         part[16ull * kReduceMaxGrid + blockIdx.x] = any_bad ? 1ull : 0ull;
-    }
-}
-
-// Pass 2 of the 16-direction filter (one block of 16 waves): merge the
-// partial records (17 words per block, direction-major), then wave j finds
-// the lowest index attaining key j in the chunk that won it, and wave 0
-// builds the polygon record.
-constexpr int kSetup16Block = 1024;
-__global__ __launch_bounds__(kSetup16Block) void k_setup16(const float2* __restrict__ pts, uint64_t n,
-                                                           Poly16* poly, const unsigned long long* __restrict__ part,
-                                                           uint32_t nblocks) {
-    constexpr int NW = kSetup16Block / 64;
-    static_assert(NW == 16, "one wave per direction");
-    static_assert(kReduceMaxGrid == 4 * kSetup16Block, "one round of records");
-    __shared__ unsigned long long sh_m[17][NW];
-    __shared__ unsigned long long sh_k[16];
-    __shared__ float2 sh_pt[16];
-    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-    const uint32_t b0 = 4u * t;
-    // two halves of the directions, each one memory round trip: thread t
-    // reads blocks 4t..4t+3 of every direction of the half as two 16-byte
-    // loads; words past nblocks are replaced by 0 (identity of max and OR)
-    auto merge = [&](auto jfirst_c, auto jcount_c) {
-        constexpr int J0 = decltype(jfirst_c)::value, JN = decltype(jcount_c)::value;
-        ulonglong2 w[JN][2];
-#pragma unroll
-        for (int i = 0; i < JN; ++i) {
-            const ulonglong2* src = reinterpret_cast<const ulonglong2*>(part + (uint64_t)(J0 + i) * kReduceMaxGrid + b0);
-            w[i][0] = src[0];
-            w[i][1] = src[1];
-        }
-#pragma unroll
-        for (int i = 0; i < JN; ++i) {
-            const int j = J0 + i;
-            const unsigned long long e0 = (b0 + 0u < nblocks) ? w[i][0].x : 0ull;
-            const unsigned long long e1 = (b0 + 1u < nblocks) ? w[i][0].y : 0ull;
-            const unsigned long long e2 = (b0 + 2u < nblocks) ? w[i][1].x : 0ull;
-            const unsigned long long e3 = (b0 + 3u < nblocks) ? w[i][1].y : 0ull;
-            unsigned long long v = (j == 16) ? (e0 | e1 | e2 | e3) : max(max(e0, e1), max(e2, e3));
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, 64);
-                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, 64);
-                const unsigned long long u = ((unsigned long long)hi << 32) | lo;
-                v = (j == 16) ? (v | u) : max(v, u);
-            }
-            if (lane == 0) sh_m[j][wave] = v;
-        }
-    };
-    merge(std::integral_constant<int, 0>{}, std::integral_constant<int, 9>{});
-    merge(std::integral_constant<int, 9>{}, std::integral_constant<int, 8>{});
-    __syncthreads();
-    {
-        const int j = (int)wave;
-        unsigned long long key = 0ull;
-        for (int w = 0; w < NW; ++w) key = max(key, sh_m[j][w]);
-        unsigned long long res = 0ull;
-        if (key != 0ull) {
-            const float kv = from_ordered((uint32_t)(key >> 32));
-            const uint32_t idx = scan_chunk<16>(pts, 0, n, unpack_idx(key), j, kv, &sh_pt[j]);
-            if (idx != 0xFFFFFFFFu) res = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - idx);
-        }
-        if (lane == 0) sh_k[j] = res;
-    }
-    __syncthreads();
-    if (t < 64) {
-        unsigned long long nf = 0ull;
-        for (int w = 0; w < NW; ++w) nf |= sh_m[16][w];
-        (void)setup_octagon<16>(pts, 0, n, sh_k[lane & 15u], (uint32_t)nf, poly, sh_pt);
     }
 }
 
@@ -1441,12 +1358,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     }
     if (sparse) {
         const uint32_t nl = sh_nlist;
-        // zero keep words for the groups that are not read
-        for (uint64_t gb = g0 + (uint64_t)wave * 64u; gb < g1; gb += (uint64_t)NW * 64u) {
-            const uint64_t g = gb + lane;
-            if (g < g1 && group_skipped(sh_skip, g, w0, nw))
-                *reinterpret_cast<ulonglong2*>(bits + 2 * g) = make_ulonglong2(0ull, 0ull);
-        }
         // the listed groups, NP per wave at a time
         for (uint32_t b = wave * (uint32_t)NP; b < nl; b += (uint32_t)(NW * NP)) {
             const uint32_t cnt = min((uint32_t)NP, nl - b);
@@ -1460,6 +1371,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
                 *reinterpret_cast<ulonglong2*>(bits + 2 * g) = make_ulonglong2(m0, m1);
             }
             groups += cnt;
+        }
+        // zero keep words for the groups that were not read, needed only if
+        // the block kept a point: the compaction skips blocks whose count is 0
+        if (lane == 0) sh_g[wave] = total;
+        __syncthreads();
+        uint32_t any = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) any |= sh_g[w];
+        __syncthreads();   // sh_g is rewritten below
+        if (any != 0u) {
+            for (uint64_t gb = g0 + (uint64_t)wave * 64u; gb < g1; gb += (uint64_t)NW * 64u) {
+                const uint64_t g = gb + lane;
+                if (g < g1 && group_skipped(sh_skip, g, w0, nw))
+                    *reinterpret_cast<ulonglong2*>(bits + 2 * g) = make_ulonglong2(0ull, 0ull);
+            }
         }
     }
     for (uint64_t sb = r0; !sparse && sb < r1; sb += ST) {
@@ -1626,6 +1552,10 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const uint64_t* __restrict__ 
 #pragma unroll
     for (int w = 0; w < NW; ++w) base += sh_part[w];
     base = uniform_u64(base);
+    if (blkcnt[blockIdx.x] == 0u) {   // nothing to write; its keep words are not read
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *count = base;
+        return;
+    }
 
     const uint64_t r0 = (uint64_t)blockIdx.x * spans * kSpan;
     const uint64_t r1 = min<uint64_t>(n, r0 + (uint64_t)spans * kSpan);
@@ -2060,7 +1990,7 @@ hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part
 hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsigned long long* part,
                         uint32_t nblocks, hipStream_t stream) {
     if (nblocks < 1 || nblocks > (uint32_t)kReduceMaxGrid) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupBlock), 0, stream, pts, n, oct, part, nblocks);
+    hipLaunchKernelGGL(k_setup<8>, dim3(1), dim3(512), 0, stream, pts, n, oct, part, nblocks);
     return hipGetLastError();
 }
 
@@ -2083,7 +2013,7 @@ hipError_t launch_reduce16(const float2* pts, uint64_t n, unsigned long long* pa
 hipError_t launch_setup16(const float2* pts, uint64_t n, Poly16* poly, const unsigned long long* part,
                           uint32_t nblocks, hipStream_t stream) {
     if (nblocks < 1 || nblocks > (uint32_t)kReduceMaxGrid) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_setup16, dim3(1), dim3(kSetup16Block), 0, stream, pts, n, poly, part, nblocks);
+    hipLaunchKernelGGL(k_setup<16>, dim3(1), dim3(1024), 0, stream, pts, n, poly, part, nblocks);
     return hipGetLastError();
 }
 
@@ -2092,7 +2022,9 @@ uint32_t compact_span_points() { return kSpan; }
 FilterPlan plan_filter(uint64_t n, int cus, Shape shape, int per_cu, int reduce_grid_max) {
     FilterPlan p;
     const uint64_t nch = (n + kRChunk - 1) / kRChunk;
-    const uint64_t want = reduce_grid_max > 0 ? (uint64_t)reduce_grid_max : (uint64_t)cus * 8;
+    // 4 blocks per CU: measured faster than 2, 6, 8, 12 or 16 (1e8 points:
+    // 122 us against 130-136 us with 8)
+    const uint64_t want = reduce_grid_max > 0 ? (uint64_t)reduce_grid_max : (uint64_t)cus * 4;
     const uint64_t g = std::min<uint64_t>(want, (uint64_t)kReduceMaxGrid);
     p.reduce_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(nch, g));
     p.shape = classify_shape_supported(shape) ? shape : Shape{512, 16};
@@ -2212,7 +2144,8 @@ uint32_t batch_tile_boxes() { return kBatchTileBoxes; }
 hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32_t S, uint64_t n_total,
                         SetInfo* sets, BatchTotals* tot, unsigned long long* part, uint32_t max_rtiles,
                         Octagon* octs, uint64_t* bits, uint32_t* blkcnt, uint32_t max_items, uint32_t* surv,
-                        uint64_t* counts, float4* box, Shape shape, int cus, hipStream_t stream) {
+                        uint64_t* counts, float4* box, Shape shape, int cus, int reduce_per_cu,
+                        hipStream_t stream) {
     if (!shape_supported(shape)) return hipErrorInvalidValue;
     if (seg)
         hipLaunchKernelGGL(k_batch_plan<true>, dim3(1), dim3(1024), 0, stream, off, S, sets, tot, counts, max_items,
@@ -2223,7 +2156,7 @@ hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const bool v = is_vec4(pts);
-    const int rgrid = cus * 8;
+    const int rgrid = cus * (reduce_per_cu > 0 ? reduce_per_cu : 8);
     if (v)
         hipLaunchKernelGGL(k_batch_reduce<true>, dim3(rgrid), dim3(kRBlock), 0, stream, pts, S, sets, tot, part,
                            box);

@@ -89,7 +89,8 @@ struct hullf_ctx {
     bool host_finish = false;              // hull finishing always on the host
     int classify_per_cu = 0;               // classify blocks per CU (0: what occupancy allows)
     int compact_block = 512;               // threads per compaction block
-    int reduce_grid_max = 0;               // reduction blocks (0: 8 per CU)
+    int reduce_grid_max = 0;               // reduction blocks (0: 4 per CU)
+    int batch_reduce_per_cu = 0;           // batched reduction blocks per CU (0: default)
     uint64_t* bits = nullptr;              // keep bits, 2 words per 128 points
     uint64_t bits_cap = 0;
     uint32_t* blkcnt = nullptr;            // kMaxBlocks survivor counts
@@ -337,7 +338,7 @@ hullf_status enqueue_filter16(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, u
 }
 
 constexpr uint32_t kChainChunk = 256;          // sorted points per chain thread
-constexpr uint64_t kDeviceFinishMin = 1u << 18;   // survivors from which the device sorts and chains
+constexpr uint64_t kDeviceFinishMin = 1u << 14;   // survivors from which the device sorts and chains
 constexpr uint32_t kLevelStop = 1u << 16;         // chunk levels stop at this many candidates
 
 hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
@@ -396,15 +397,31 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
     CHECK_HIP(hipMemcpyAsync(c->h_count, bad, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     CHECK_HIP(hipStreamSynchronize(s));
     if (*c->h_count != 0) return HULLF_EINVAL;
-    CHECK_HIP(launch_finish_sort(c->fk[0], c->fv[0], c->fk[1], c->fv[1], mm, c->fhist, c->frow, s));
+    // sort by x alone (four passes over the key's high half, stable)
+    CHECK_HIP(launch_finish_sort(c->fk[0], c->fv[0], c->fk[1], c->fv[1], mm, c->fhist, c->frow, 32, s));
     std::vector<HostPt> lists[2];
     uint32_t* const off_b = c->fchain + c->f_cap / 2;   // second offset array of the merge rounds
     uint2* const br = reinterpret_cast<uint2*>(c->fchain);
     for (int side = 0; side < 2; ++side) {
         const int sign = side == 0 ? 1 : -1;
+        // the side's representative of every run of equal x, in order
+        // (distinct points, sorted by (x, y))
+        int cur = 1;
+        uint32_t cm = 0, nc = 0;
+        {
+            const uint32_t nch = (mm + kChainChunk - 1) / kChainChunk;
+            CHECK_HIP(launch_runs(c->fk[0], mm, kChainChunk, sign, c->fchain, c->fcnt, s));
+            CHECK_HIP(launch_scan_counts(c->fcnt, nch, c->frow + 256, s));
+            CHECK_HIP(hipMemcpyAsync(c->h_total, c->frow + 256, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            CHECK_HIP(hipStreamSynchronize(s));
+            cm = *c->h_total;
+            if (cm == 0 || cm > mm) return HULLF_EDEVICE;
+            const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((nch + 3) / 4, (uint32_t)c->cus * 8));
+            CHECK_HIP(launch_chain_gather(c->fk[0], c->fv[0], mm, kChainChunk, c->fchain, c->fcnt, cm, c->fk[1],
+                                          c->fv[1], gg, s));
+        }
         // chunk levels while they shrink the set well
-        int cur = 0, dedup = 1;
-        uint32_t cm = mm, nc = 0;
+        const int dedup = 0;
         for (;;) {
             const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
             const uint32_t nch = (cm + kChainChunk - 1) / kChainChunk;
@@ -419,7 +436,6 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
                                           c->fk[nxt], c->fv[nxt], gg, s));
             const bool slow = (uint64_t)tot * 4 > (uint64_t)cm * 3;   // little left to gain
             cur = nxt;
-            dedup = 0;
             cm = tot;
             nc = nch;
             if (slow || cm <= kLevelStop) break;
@@ -437,7 +453,7 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
             CHECK_HIP(launch_bridge(c->fk[cur], off_in, nc, sign, br, off_out, gg, s));
             CHECK_HIP(launch_scan_counts(off_out, np, off_out + np, s));
             CHECK_HIP(launch_merge_gather(c->fk[cur], c->fv[cur], off_in, nc, br, off_out, c->fk[nxt], c->fv[nxt],
-                                          gg, s));
+                                          c->cus * 4, s));
             std::swap(off_in, off_out);
             cur = nxt;
             nc = np;
@@ -456,6 +472,12 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
         for (uint32_t k = 0; k < cm; ++k)
             L[k] = HostPt{unord_host((uint32_t)(c->h_fk[k] >> 32)), unord_host((uint32_t)c->h_fk[k]), c->h_fv[k]};
     }
+    // the two chain ends the run representatives leave out: the greatest
+    // point (the upper chain's last) ends the lower chain, the smallest (the
+    // lower chain's first) starts the upper one
+    if (lists[0].empty() || lists[1].empty()) return HULLF_EDEVICE;
+    lists[0].push_back(lists[1].back());
+    lists[1].insert(lists[1].begin(), lists[0].front());
     chain_sorted(lists[0], lists[1], out);
     return HULLF_OK;
 }
@@ -600,7 +622,8 @@ hullf_status enqueue_batched(hullf_ctx* c, const hullf_pt* d_pts, const uint64_t
     CHECK_HIP(launch_batch(pts, d_off, seg, S, n_total, c->b_sets, c->b_tot, c->b_part,
                            (uint32_t)std::min<uint64_t>(c->b_part_cap, 0xFFFFFFFFull), c->b_octs, c->b_bits,
                            c->b_blkcnt, (uint32_t)std::min<uint64_t>(c->b_items_cap, 0xFFFFFFFFull), d_surv,
-                           d_counts, c->region_skip ? c->b_boxes : nullptr, shape, c->cus, s));
+                           d_counts, c->region_skip ? c->b_boxes : nullptr, shape, c->cus, c->batch_reduce_per_cu,
+                           s));
     return HULLF_OK;
 }
 
@@ -652,6 +675,8 @@ hullf_status hullf_create(int device, size_t workspace_bytes, hullf_ctx_t* out) 
     if (const char* e = std::getenv("HULLF_REGION_SKIP")) c->region_skip = std::atoi(e) != 0;
     if (const char* e = std::getenv("HULLF_CLASSIFY_PER_CU")) c->classify_per_cu = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("HULLF_REDUCE_GRID")) c->reduce_grid_max = std::max(0, std::atoi(e));
+    if (const char* e = std::getenv("HULLF_BATCH_REDUCE_PER_CU"))
+        c->batch_reduce_per_cu = std::min(16, std::max(0, std::atoi(e)));
     if (const char* e = std::getenv("HULLF_COMPACT_BLOCK")) {
         const int b = std::atoi(e);
         if (b == 256 || b == 512 || b == 1024) c->compact_block = b;

@@ -1,5 +1,5 @@
 """GPU parity of hull finishing on the device (sort + chunked monotone
-chains, used by convex_hull from 2^18 survivors on): the counter-clockwise
+chains, used by convex_hull from 2^14 survivors on): the counter-clockwise
 hull index list must equal the oracle's bit for bit, also with repeated
 coordinates (lowest index kept), collinear and single-point sets, and must
 equal the host finishing path."""
@@ -15,7 +15,7 @@ from tests.gpu_common import ctx, say, torch_dev, upload  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
-DEVICE_MIN = 1 << 18
+DEVICE_MIN = 1 << 14
 
 
 def _hull_check(ctx, dev, xy, name, need_device=True):
@@ -134,3 +134,25 @@ def test_merge_tree_many_chunks(ctx, torch_dev):
     number of chains in some of them."""
     xy = workloads.displaced(6_000_037, 73)
     _hull_check(ctx, torch_dev, xy, "displaced 6e6")
+
+
+@pytest.mark.parametrize("n", [(1 << 14) - 1, 1 << 14, (1 << 14) + 1, 40_009])
+def test_finish_at_the_device_threshold(ctx, torch_dev, n):
+    """Circle points all survive: just below the threshold the host chains
+    them, from it on the device sorts, chains and merges them."""
+    xy = workloads.circle(n, 79)
+    _hull_check(ctx, torch_dev, xy, f"circle n={n}", need_device=n >= DEVICE_MIN)
+
+
+@pytest.mark.parametrize("lines", [1, 3, 40])
+def test_vertical_runs_device_finish(ctx, torch_dev, lines):
+    """Points on a few vertical lines (every point survives a degenerate or
+    thin octagon): runs of equal x hundreds of thousands long, walked by one
+    thread each, and the chain ends that only the longest runs hold."""
+    rng = np.random.default_rng(83 + lines)
+    n = 300_007
+    xs = rng.integers(0, lines, n).astype(np.float32) * np.float32(0.5)
+    ys = rng.standard_normal(n).astype(np.float32)
+    xy = np.stack([xs, ys], axis=1)
+    xy[rng.choice(n, 50, replace=False)] = xy[rng.choice(n, 50, replace=False)]   # repeats
+    _hull_check(ctx, torch_dev, xy, f"{lines} vertical lines", need_device=False)

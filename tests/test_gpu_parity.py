@@ -189,14 +189,16 @@ def test_region_skip_with_scattered_near_edge_points(ctx, torch_dev, kind):
     _check_all(ctx, torch_dev, xy, "scattered near-edge " + kind, hull=False)
 
 
-@pytest.mark.parametrize("grid", [1, 7, 64])
+@pytest.mark.parametrize("grid", [1, 7, 64, 2048, 4096])
 def test_small_reduce_grid(torch_dev, monkeypatch, grid):
     """Few reduction blocks: every wave reads many chunks (its region-skip
-    boxes are written 64 at a time), and k_setup merges few records."""
+    boxes are written 64 at a time), and the set-up merges few records;
+    many blocks: the set-up merges its rows in several batches of loads."""
     monkeypatch.setenv("HULLF_REDUCE_GRID", str(grid))
     c = hullf.Context(0)
     try:
-        base = cases.named_sets(2_000_003, 41)["normal"]
+        # enough 2048-point chunks for every block of the largest grids
+        base = cases.named_sets(2_000_003 if grid < 2048 else 9_000_011, 41)["normal"]
         xy = cases.with_near_edge_points(base, oracle.extremes, per_edge=200, seed=13)
         xy = xy[np.random.default_rng(7).permutation(xy.shape[0])]
         _check_all(c, torch_dev, xy, f"reduce grid {grid}", hull=False)
