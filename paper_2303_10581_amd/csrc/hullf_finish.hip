@@ -85,10 +85,21 @@ __global__ __launch_bounds__(256) void k_fin_keys(const float2* __restrict__ pts
 // hist[d * tiles + t] = items of tile t with digit d (then, after the two
 // scans, the output position of the first of them).
 
+// Tile of block b of a grid of n blocks, one per tile.  Blocks go to the 8
+// XCDs in turn (block b to XCD b mod 8), each with its own L2; this gives
+// every XCD a contiguous range of tiles, taken in order, so that the runs
+// that neighbouring tiles write next to each other (a digit's run of tile t
+// ends where tile t+1's begins; hist entries of consecutive tiles share
+// lines) meet in one L2 and leave it as whole lines.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+    const uint32_t x = b & 7u, j = b >> 3, q = n >> 3, r = n & 7u;
+    return x * q + min(x, r) + j;
+}
+
 __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t m, uint32_t shift,
                                                       uint32_t tiles, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kRsBins];
-    const uint32_t t = threadIdx.x, tile = blockIdx.x;
+    const uint32_t t = threadIdx.x, tile = xcd_tile(blockIdx.x, tiles);
     h[t] = 0u;
     __syncthreads();
     const uint64_t base = (uint64_t)tile * kRsTile;
@@ -201,7 +212,7 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* __restr
     __shared__ uint32_t tofs[kRsBins];       // tile-level exclusive digit offsets
     __shared__ uint32_t gpos[kRsBins];       // output position of the tile's first item per digit
     __shared__ uint32_t wsum[NW];
-    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6, tile = blockIdx.x;
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6, tile = xcd_tile(blockIdx.x, tiles);
     const uint64_t base = (uint64_t)tile * kRsTile;
     const uint32_t nt = (uint32_t)min<uint64_t>(kRsTile, (uint64_t)m - base);
 #pragma unroll
@@ -366,28 +377,40 @@ __device__ __forceinline__ int orient_dev(float ox, float oy, float ax, float ay
 constexpr uint32_t kChainMaxC = 256;   // a stack entry is a one-byte offset into the chunk
 constexpr uint32_t kChainPrefetch = 16;   // keys loaded together
 
+// CMAX bounds C and sizes the LDS stacks.  Up to 64 points per chunk the
+// stack also holds each entry's coordinates (CMAX * 64 * 9 bytes per
+// block), so a pop reads LDS only; with longer chunks it holds one-byte
+// offsets and a pop reloads the point from memory (the chunk's keys are
+// then too many per compute unit to stay in the L1 or L2 cache).
+template <uint32_t CMAX>
 __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys, uint32_t m, uint32_t C, int sign,
                                               int dedup, uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
-    // Each thread's stack lives in LDS as offsets into its chunk (a push or
-    // pop in global memory cost a dependent round trip each); the chain is
-    // copied to out[c*C ...] at the end.
-    __shared__ uint8_t sh_st[kChainMaxC][64];
+    static_assert(CMAX <= kChainMaxC, "stack entries are one byte");
+    constexpr bool kXY = CMAX <= 64u;
+    __shared__ uint8_t sh_st[CMAX][64];
+    __shared__ float2 sh_xy[kXY ? CMAX : 1u][64];
     const uint32_t c = blockIdx.x * 64u + threadIdx.x;
     const uint32_t nch = (m + C - 1) / C;
     if (c >= nch) return;
     const uint32_t b = c * C, e = min(m, b + C);
     uint8_t* st = &sh_st[0][threadIdx.x];   // entry j at st[64 * j]: lanes hit distinct banks
+    float2* sxy = &sh_xy[0][threadIdx.x];
     uint32_t len = 0;
     float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f;   // top (2) and below-top (1) of the stack
     uint64_t prev = (b > 0) ? keys[b - 1] : 0ull;
     bool have_prev = b > 0;
-    // The chunk's keys are read kChainPrefetch at a time, all loads issued
-    // before the first is used: one memory round trip per batch instead of
-    // one per point (the stack pops below mostly hit the cache).
-    for (uint32_t i0 = b; i0 < e; i0 += kChainPrefetch) {
-        uint64_t kb[kChainPrefetch];
+    // The chunk's keys are read kChainPrefetch at a time, the next batch's
+    // loads issued before the current batch is walked.
+    uint64_t kb[kChainPrefetch];
 #pragma unroll
-        for (uint32_t u = 0; u < kChainPrefetch; ++u) kb[u] = (i0 + u < e) ? keys[i0 + u] : 0ull;
+    for (uint32_t u = 0; u < kChainPrefetch; ++u) kb[u] = (b + u < e) ? keys[b + u] : 0ull;
+    for (uint32_t i0 = b; i0 < e; i0 += kChainPrefetch) {
+        uint64_t kn[kChainPrefetch];
+#pragma unroll
+        for (uint32_t u = 0; u < kChainPrefetch; ++u) {
+            const uint32_t i = i0 + kChainPrefetch + u;
+            kn[u] = (i < e) ? keys[i] : 0ull;
+        }
 #pragma unroll
         for (uint32_t u = 0; u < kChainPrefetch; ++u) {
             const uint32_t i = i0 + u;
@@ -402,18 +425,27 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
                 x2 = x1;
                 y2 = y1;
                 if (len >= 2) {
-                    const uint64_t kp = keys[b + st[64u * (len - 2)]];
-                    x1 = key_x(kp);
-                    y1 = key_y(kp);
+                    if constexpr (kXY) {
+                        const float2 q = sxy[64u * (len - 2)];
+                        x1 = q.x;
+                        y1 = q.y;
+                    } else {
+                        const uint64_t kp = keys[b + st[64u * (len - 2)]];
+                        x1 = key_x(kp);
+                        y1 = key_y(kp);
+                    }
                 }
             }
             st[64u * len] = (uint8_t)(i - b);
+            if constexpr (kXY) sxy[64u * len] = make_float2(x, y);
             ++len;
             x1 = x2;
             y1 = y2;
             x2 = x;
             y2 = y;
         }
+#pragma unroll
+        for (uint32_t u = 0; u < kChainPrefetch; ++u) kb[u] = kn[u];
     }
     uint32_t* o = out + (uint64_t)b;
     for (uint32_t j = 0; j < len; ++j) o[j] = b + st[64u * j];
@@ -427,66 +459,98 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
 // no strict vertex of the lower (upper) hull, except the two ends of the
 // hull's chains: the lexicographically greatest point ends the lower chain
 // and the smallest starts the upper one; the host adds those two back when
-// it joins the chains.  Thread c owns the runs whose first point lies in
-// positions [c*C, (c+1)*C) and walks each to its end (past the chunk if it
-// must); it writes the representatives' positions to out[c*C ...] (at most
-// C of them) and their number to cnt[c].  Keys are read kChainPrefetch at a
-// time.
-__global__ __launch_bounds__(64) void k_runs(const uint64_t* __restrict__ keys, uint32_t m, uint32_t C, int sign,
-                                             uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
-    const uint32_t c = blockIdx.x * 64u + threadIdx.x;
-    const uint32_t nch = (m + C - 1) / C;
-    if (c >= nch) return;
-    const uint32_t b = c * C, e = min(m, b + C);
+// it joins the chains.
+//
+// Wave w owns the runs whose first point lies in its tile, positions
+// [w*T, (w+1)*T) with T = kRunTile, and writes their representatives'
+// positions, in order, to out[w*T ...] (at most T) and their number to
+// cnt[w].  It walks the tile 64 positions a step (lane l reads position
+// i0 + l; the tile's loads are all issued before the first step), and past
+// the tile's end while a run it owns is still open.  In a step a segmented
+// minimum scan over the lanes (a segment starts at each lane whose x differs
+// from its predecessor's) gives every lane the least (y', position) of its
+// run so far, y' the order-preserving bits of y for the lower side and their
+// complement for the upper, so the minimum is the first point of least
+// (greatest) y; the run open at the end of a step is carried into the next.
+constexpr uint32_t kRunSteps = kRunTile / 64u;
+
+struct RunCarry {
+    bool open;       // a run is open before this step
+    bool own;        // the wave owns it
+    uint32_t x;      // its x (ordered bits)
+    uint64_t best;   // least (y', position) of it so far
+};
+
+// One step at positions [i0, i0 + 64); false once the wave is done.
+__device__ __forceinline__ bool run_step(uint64_t k, uint32_t i0, uint32_t m, uint32_t e, int sign, uint32_t lane,
+                                         RunCarry& c, uint32_t* __restrict__ out, uint32_t& len) {
+    const uint32_t i = i0 + lane;
+    const bool valid = i < m;
+    const uint32_t kx = (uint32_t)(k >> 32);
+    const uint32_t ky = sign > 0 ? (uint32_t)k : ~(uint32_t)k;
+    const uint32_t px = (uint32_t)__shfl_up((int)kx, 1, 64);
+    const bool head = !valid || (lane == 0u ? (!c.open || kx != c.x) : kx != px);
+    const uint64_t H = __ballot(head);
+    uint64_t s = ((uint64_t)ky << 32) | i;
+    bool f = head;
+#pragma unroll
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint64_t t = __shfl_up(s, d, 64);
+        const bool tf = __shfl_up((int)f, d, 64) != 0;
+        if (lane >= d) {
+            if (!f) s = min(s, t);
+            f = f || tf;
+        }
+    }
+    const uint64_t upto = (2ull << lane) - 1ull;   // this lane and those below (lane 63: all)
+    const bool carried = (H & upto) == 0ull;       // no run starts at or below this lane
+    if (carried) s = min(s, c.best);
+    const bool own = carried ? c.own : (i0 < e);
+    const bool end = valid && (lane < 63u ? ((H >> lane) & 2ull) != 0ull : i + 1u == m);
+    const bool emit = end && own;
+    const bool cemit = c.open && c.own && (H & 1ull) != 0ull;   // the carried run ended at i0 - 1
+    const uint64_t E = __ballot(emit);
+    const uint32_t base = len + (cemit ? 1u : 0u);
+    if (cemit && lane == 0u) out[len] = (uint32_t)c.best;
+    if (emit) out[base + (uint32_t)__popcll(E & (upto >> 1))] = (uint32_t)s;
+    len = base + (uint32_t)__popcll(E);
+    if (i0 + 64u >= m) return false;
+    c.x = (uint32_t)__shfl((int)kx, 63, 64);
+    c.best = __shfl(s, 63, 64);
+    c.own = __shfl((int)own, 63, 64) != 0;
+    c.open = true;
+    return !(i0 + 64u >= e && !c.own);   // past the tile with no owned run open: done
+}
+
+__global__ __launch_bounds__(256) void k_runs(const uint64_t* __restrict__ keys, uint32_t m, int sign,
+                                              uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint32_t nt = (m + kRunTile - 1u) / kRunTile;
+    if (w >= nt) return;   // whole waves only
+    const uint32_t b = w * kRunTile, e = min(m, b + kRunTile);
+    uint64_t kr[kRunSteps];
+#pragma unroll
+    for (uint32_t u = 0; u < kRunSteps; ++u) {
+        const uint32_t i = b + 64u * u + lane;
+        kr[u] = (i < m) ? keys[i] : 0ull;
+    }
+    // a run open at b started in the previous tile: not this wave's
+    RunCarry c{b > 0u, false, (b > 0u) ? (uint32_t)(keys[b - 1u] >> 32) : 0u, ~0ull};
     uint32_t* o = out + (uint64_t)b;
     uint32_t len = 0;
-    bool have = false;        // a run is open
-    uint32_t rx = 0;          // its x (ordered bits)
-    uint32_t best = 0, bpos = 0;
-    // the run open at b (if any) belongs to an earlier chunk
-    uint32_t prevx = (b > 0) ? (uint32_t)(keys[b - 1] >> 32) : 0u;
-    bool skipping = b > 0;
-    for (uint32_t i0 = b; i0 < m; i0 += kChainPrefetch) {
-        uint64_t kb[kChainPrefetch];
+    bool more = true;
 #pragma unroll
-        for (uint32_t u = 0; u < kChainPrefetch; ++u) kb[u] = (i0 + u < m) ? keys[i0 + u] : 0ull;
-        bool done = false;
-#pragma unroll
-        for (uint32_t u = 0; u < kChainPrefetch; ++u) {
-            const uint32_t i = i0 + u;
-            if (i >= m) {
-                done = true;
-                break;
-            }
-            const uint32_t kx = (uint32_t)(kb[u] >> 32), ky = (uint32_t)kb[u];
-            if (skipping) {
-                if (kx == prevx && i < e) continue;   // still in the earlier chunk's run
-                skipping = false;
-            }
-            if (have && kx == rx) {   // same run
-                if (sign > 0 ? ky < best : ky > best) {
-                    best = ky;
-                    bpos = i;
-                }
-                continue;
-            }
-            if (have) {   // the open run ended at i - 1
-                o[len++] = bpos;
-                have = false;
-            }
-            if (i >= e) {   // no more runs start in this chunk
-                done = true;
-                break;
-            }
-            have = true;
-            rx = kx;
-            best = ky;
-            bpos = i;
-        }
-        if (done) break;
+    for (uint32_t u = 0; u < kRunSteps; ++u) {
+        more = run_step(kr[u], b + 64u * u, m, e, sign, lane, c, o, len);
+        if (!more) break;
     }
-    if (have) o[len++] = bpos;
-    cnt[c] = len;
+    // past the tile: the owned run still open
+    for (uint32_t i0 = b + kRunTile; more; i0 += 64u) {
+        const uint32_t i = i0 + lane;
+        more = run_step((i < m) ? keys[i] : 0ull, i0, m, e, sign, lane, c, o, len);
+    }
+    if (lane == 0u) cnt[w] = len;
 }
 
 // Exclusive scan of n counts in place (one block of 1024); the total goes
@@ -710,15 +774,23 @@ hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, 
                         uint32_t* cnt, hipStream_t stream) {
     if (C == 0 || C > kChainMaxC) return hipErrorInvalidValue;
     const uint32_t nch = (m + C - 1) / C;
-    hipLaunchKernelGGL(k_chain, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup, chain, cnt);
+    if (C <= 32u)
+        hipLaunchKernelGGL(k_chain<32>, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup, chain,
+                           cnt);
+    else if (C <= 64u)
+        hipLaunchKernelGGL(k_chain<64>, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup, chain,
+                           cnt);
+    else
+        hipLaunchKernelGGL(k_chain<kChainMaxC>, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup,
+                           chain, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_runs(const uint64_t* keys, uint32_t m, uint32_t C, int sign, uint32_t* reps, uint32_t* cnt,
+hipError_t launch_runs(const uint64_t* keys, uint32_t m, int sign, uint32_t* reps, uint32_t* cnt,
                        hipStream_t stream) {
-    if (C == 0) return hipErrorInvalidValue;
-    const uint32_t nch = (m + C - 1) / C;
-    hipLaunchKernelGGL(k_runs, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, reps, cnt);
+    const uint32_t nt = (m + kRunTile - 1u) / kRunTile;
+    if (nt == 0u) return hipSuccess;
+    hipLaunchKernelGGL(k_runs, dim3((nt + 3u) / 4u), dim3(256), 0, stream, keys, m, sign, reps, cnt);
     return hipGetLastError();
 }
 

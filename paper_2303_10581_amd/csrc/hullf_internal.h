@@ -171,8 +171,10 @@ hipError_t launch_finish_keys(const float2* pts, uint64_t n, const uint32_t* sur
 hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
                               uint32_t* hist, uint32_t* rowsum, uint32_t first_shift, hipStream_t stream);
 // Run representatives of keys sorted by x alone (see k_runs): positions into
-// reps (chunk c's at c*C), counts per chunk into cnt.
-hipError_t launch_runs(const uint64_t* keys, uint32_t m, uint32_t C, int sign, uint32_t* reps, uint32_t* cnt,
+// reps (m words; tile t's at t*kRunTile), counts per tile into cnt
+// (ceil(m / kRunTile) words).
+constexpr uint32_t kRunTile = 1024;
+hipError_t launch_runs(const uint64_t* keys, uint32_t m, int sign, uint32_t* reps, uint32_t* cnt,
                        hipStream_t stream);
 // Chains of chunks of C sorted points: chain holds m words (chunk c's
 // chain at c*C), cnt ceil(m/C) words.  sign 1 = lower, -1 = upper.

@@ -87,6 +87,7 @@ struct hullf_ctx {
     uint32_t* h_total = nullptr;
     Shape filter_shape{512, 16};
     bool host_finish = false;              // hull finishing always on the host
+    uint32_t chain_chunk = 256;            // sorted points per chain thread (16..256, a power of two)
     int classify_per_cu = 0;               // classify blocks per CU (0: what occupancy allows)
     int compact_block = 512;               // threads per compaction block
     int reduce_grid_max = 0;               // reduction blocks (0: 4 per CU)
@@ -337,7 +338,7 @@ hullf_status enqueue_filter16(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, u
     return HULLF_OK;
 }
 
-constexpr uint32_t kChainChunk = 256;          // sorted points per chain thread
+constexpr uint32_t kChainChunkMin = 16;        // least sorted points per chain thread
 constexpr uint64_t kDeviceFinishMin = 1u << 14;   // survivors from which the device sorts and chains
 constexpr uint32_t kLevelStop = 1u << 16;         // chunk levels stop at this many candidates
 
@@ -362,7 +363,7 @@ hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
             if ((e = ws_alloc(c, &c->fv[k], cap)) != hipSuccess) return e;
         }
         if ((e = ws_alloc(c, &c->fchain, cap)) != hipSuccess) return e;
-        if ((e = ws_alloc(c, &c->fcnt, cap / kChainChunk + 2)) != hipSuccess) return e;
+        if ((e = ws_alloc(c, &c->fcnt, cap / kChainChunkMin + 2)) != hipSuccess) return e;
         c->f_cap = cap;
     }
     const uint64_t hw = 256ull * finish_sort_tiles((uint32_t)m);
@@ -409,30 +410,31 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
         int cur = 1;
         uint32_t cm = 0, nc = 0;
         {
-            const uint32_t nch = (mm + kChainChunk - 1) / kChainChunk;
-            CHECK_HIP(launch_runs(c->fk[0], mm, kChainChunk, sign, c->fchain, c->fcnt, s));
+            const uint32_t nch = (mm + kRunTile - 1) / kRunTile;
+            CHECK_HIP(launch_runs(c->fk[0], mm, sign, c->fchain, c->fcnt, s));
             CHECK_HIP(launch_scan_counts(c->fcnt, nch, c->frow + 256, s));
             CHECK_HIP(hipMemcpyAsync(c->h_total, c->frow + 256, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
             CHECK_HIP(hipStreamSynchronize(s));
             cm = *c->h_total;
             if (cm == 0 || cm > mm) return HULLF_EDEVICE;
             const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((nch + 3) / 4, (uint32_t)c->cus * 8));
-            CHECK_HIP(launch_chain_gather(c->fk[0], c->fv[0], mm, kChainChunk, c->fchain, c->fcnt, cm, c->fk[1],
+            CHECK_HIP(launch_chain_gather(c->fk[0], c->fv[0], mm, kRunTile, c->fchain, c->fcnt, cm, c->fk[1],
                                           c->fv[1], gg, s));
         }
         // chunk levels while they shrink the set well
         const int dedup = 0;
         for (;;) {
             const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
-            const uint32_t nch = (cm + kChainChunk - 1) / kChainChunk;
-            CHECK_HIP(launch_chain(c->fk[cur], cm, kChainChunk, sign, dedup, c->fchain, c->fcnt, s));
+            const uint32_t C = c->chain_chunk;
+            const uint32_t nch = (cm + C - 1) / C;
+            CHECK_HIP(launch_chain(c->fk[cur], cm, C, sign, dedup, c->fchain, c->fcnt, s));
             CHECK_HIP(launch_scan_counts(c->fcnt, nch, c->frow + 256, s));
             CHECK_HIP(hipMemcpyAsync(c->h_total, c->frow + 256, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
             CHECK_HIP(hipStreamSynchronize(s));
             const uint32_t tot = *c->h_total;
             if (tot > cm) return HULLF_EDEVICE;
             const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((nch + 3) / 4, (uint32_t)c->cus * 8));
-            CHECK_HIP(launch_chain_gather(c->fk[cur], c->fv[cur], cm, kChainChunk, c->fchain, c->fcnt, tot,
+            CHECK_HIP(launch_chain_gather(c->fk[cur], c->fv[cur], cm, C, c->fchain, c->fcnt, tot,
                                           c->fk[nxt], c->fv[nxt], gg, s));
             const bool slow = (uint64_t)tot * 4 > (uint64_t)cm * 3;   // little left to gain
             cur = nxt;
@@ -672,6 +674,10 @@ hullf_status hullf_create(int device, size_t workspace_bytes, hullf_ctx_t* out) 
         if (std::sscanf(e, "%d,%d", &sh.block, &sh.ppt) == 2 && shape_supported(sh)) c->filter_shape = sh;
     }
     if (const char* e = std::getenv("HULLF_FINISH")) c->host_finish = std::strcmp(e, "host") == 0;
+    if (const char* e = std::getenv("HULLF_CHAIN_CHUNK")) {
+        const int v = std::atoi(e);
+        if (v >= (int)kChainChunkMin && v <= 256 && (v & (v - 1)) == 0) c->chain_chunk = (uint32_t)v;
+    }
     if (const char* e = std::getenv("HULLF_REGION_SKIP")) c->region_skip = std::atoi(e) != 0;
     if (const char* e = std::getenv("HULLF_CLASSIFY_PER_CU")) c->classify_per_cu = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("HULLF_REDUCE_GRID")) c->reduce_grid_max = std::max(0, std::atoi(e));

@@ -147,8 +147,9 @@ def test_finish_at_the_device_threshold(ctx, torch_dev, n):
 @pytest.mark.parametrize("lines", [1, 3, 40])
 def test_vertical_runs_device_finish(ctx, torch_dev, lines):
     """Points on a few vertical lines (every point survives a degenerate or
-    thin octagon): runs of equal x hundreds of thousands long, walked by one
-    thread each, and the chain ends that only the longest runs hold."""
+    thin octagon): runs of equal x hundreds of thousands long, each walked by
+    the one wave whose tile it starts in, and the chain ends that only the
+    longest runs hold."""
     rng = np.random.default_rng(83 + lines)
     n = 300_007
     xs = rng.integers(0, lines, n).astype(np.float32) * np.float32(0.5)
@@ -156,3 +157,54 @@ def test_vertical_runs_device_finish(ctx, torch_dev, lines):
     xy = np.stack([xs, ys], axis=1)
     xy[rng.choice(n, 50, replace=False)] = xy[rng.choice(n, 50, replace=False)]   # repeats
     _hull_check(ctx, torch_dev, xy, f"{lines} vertical lines", need_device=False)
+
+
+def _runs_set(seed, n):
+    """Runs of equal x whose lengths sit at and around the run pass's step
+    (64) and tile (1024) sizes, x increasing between runs, y random (with
+    repeated points), so run heads, run ends and carried runs fall on every
+    lane and tile position."""
+    rng = np.random.default_rng(seed)
+    lens = np.array([1, 1, 2, 3, 63, 64, 65, 127, 1023, 1024, 1025, 2047, 2049, 5000])
+    parts, x, total = [], 0.0, 0
+    while total < n:
+        k = int(min(rng.choice(lens), n - total))
+        x += float(rng.integers(1, 4))
+        ys = rng.standard_normal(k).astype(np.float32) * np.float32(1 + x / 50.0)
+        if k > 4:
+            ys[rng.integers(0, k, 2)] = ys[rng.integers(0, k)]   # repeated points in the run
+        parts.append(np.stack([np.full(k, x, np.float32), ys], axis=1))
+        total += k
+    return np.concatenate(parts, axis=0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_run_lengths_around_step_and_tile(ctx, torch_dev, seed):
+    """hull_from_survivors over every point of _runs_set: the representative
+    of each run (first lowest / highest y) and the chains built on them."""
+    xy = _runs_set(90 + seed, 400_003)
+    t = upload(xy, torch_dev)
+    import torch
+    s = torch.arange(xy.shape[0], dtype=torch.int32, device=torch_dev)
+    say(f"[gpu] finish runs around 64/1024: seed {seed}, n={xy.shape[0]}")
+    assert np.array_equal(ctx.hull_from_survivors(t, s), oracle.hull(xy))
+
+
+@pytest.mark.parametrize("chunk", [16, 64, 128])
+def test_chain_chunk_sizes(torch_dev, monkeypatch, chunk):
+    """The chain pass with other chunk sizes (HULLF_CHAIN_CHUNK): more chunk
+    levels and a deeper merge tree, the same hull."""
+    monkeypatch.setenv("HULLF_CHAIN_CHUNK", str(chunk))
+    c = hullf.Context(0)
+    try:
+        for kind in ("circle", "grid", "collinear_diag"):
+            xy = cases.named_sets(300_007, 31)[kind]
+            say(f"[gpu] finish chunk {chunk}: {kind}")
+            t = upload(xy, torch_dev)
+            assert np.array_equal(c.convex_hull(t), oracle.hull(xy, oracle.survivors(xy))), (chunk, kind)
+        xy = _runs_set(97, 200_003)
+        import torch
+        s = torch.arange(xy.shape[0], dtype=torch.int32, device=torch_dev)
+        assert np.array_equal(c.hull_from_survivors(upload(xy, torch_dev), s), oracle.hull(xy))
+    finally:
+        c.close()
