@@ -97,6 +97,8 @@ typedef enum {
  *   HULLF_COMPACT_BLOCK=b         compaction block size (256|512|1024)
  *   HULLF_REDUCE_GRID=g           reduction blocks, 1..4096 (default 4 per CU)
  *   HULLF_BATCH_REDUCE_PER_CU=k   batched reduction blocks per CU (1..16)
+ *   HULLF_CHAIN_CHUNK=c           sorted points per hull-chain thread (16..64,
+ *                                 default 32)
  *   HULLF_FINISH=host             hull finishing always on the host
  *   HULLF_TUNE_CACHE=path         tune cache file of the batched launch
  *                                 (default $XDG_CACHE_HOME/hullf/tune.txt or

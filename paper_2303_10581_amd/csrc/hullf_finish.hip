@@ -371,73 +371,95 @@ __device__ __forceinline__ int orient_dev(float ox, float oy, float ax, float ay
 // Thread c takes positions [c*C, min(m, (c+1)*C)) of the sorted keys and
 // writes the positions of its strict lower chain (sign = 1: pop while the
 // turn is not counter-clockwise) or upper chain (sign = -1) to
-// out[c*C ...], their number to cnt[c].  dedup: skip a point whose key
-// equals its predecessor's (the first level only; later levels have no
-// repeats).
-constexpr uint32_t kChainMaxC = 256;   // a stack entry is a one-byte offset into the chunk
+// out[c*C ...], their number to cnt[c].  With toff, the positions are those
+// of the run pass's output packed together: tile t (of kRunTile slots)
+// holds toff[t+1] - toff[t] keys from slot t*kRunTile on (toff is the
+// exclusive scan of the tile counts, ntiles entries, m their total), so
+// position p lies in the tile t with toff[t] <= p < toff[t+1], at slot
+// t*kRunTile + p - toff[t]; the chain's entries are then slots.
+//
+// The stack lives in LDS: per entry its coordinates and its offset in the
+// chunk (CMAX * 64 * 9 bytes per block of 64 threads), so a pop reads LDS
+// only, and the chain is copied out at the end.
+constexpr uint32_t kChainMaxC = 64;
 constexpr uint32_t kChainPrefetch = 16;   // keys loaded together
 
-// CMAX bounds C and sizes the LDS stacks.  Up to 64 points per chunk the
-// stack also holds each entry's coordinates (CMAX * 64 * 9 bytes per
-// block), so a pop reads LDS only; with longer chunks it holds one-byte
-// offsets and a pop reloads the point from memory (the chunk's keys are
-// then too many per compute unit to stay in the L1 or L2 cache).
+// Slot of packed position p, walking forward from tile t (tile t spans
+// packed positions [tb, te)).
+struct TileWalk {
+    uint32_t t, tb, te;
+};
+__device__ __forceinline__ TileWalk tile_of(const uint32_t* __restrict__ toff, uint32_t ntiles, uint32_t m,
+                                            uint32_t p) {
+    uint32_t lo = 0, hi = ntiles - 1;   // the largest t with toff[t] <= p
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1u) / 2u;
+        if (toff[mid] <= p) lo = mid;
+        else hi = mid - 1u;
+    }
+    return TileWalk{lo, toff[lo], (lo + 1u < ntiles) ? toff[lo + 1u] : m};
+}
+__device__ __forceinline__ uint32_t slot_of(const uint32_t* __restrict__ toff, uint32_t ntiles, uint32_t m,
+                                            TileWalk& w, uint32_t p) {
+    while (p >= w.te) {
+        ++w.t;
+        w.tb = w.te;
+        w.te = (w.t + 1u < ntiles) ? toff[w.t + 1u] : m;
+    }
+    return w.t * kRunTile + (p - w.tb);
+}
+
 template <uint32_t CMAX>
 __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys, uint32_t m, uint32_t C, int sign,
-                                              int dedup, uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
-    static_assert(CMAX <= kChainMaxC, "stack entries are one byte");
-    constexpr bool kXY = CMAX <= 64u;
+                                              const uint32_t* __restrict__ toff, uint32_t ntiles,
+                                              uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
+    static_assert(CMAX <= kChainMaxC && CMAX <= 256u, "stack offsets are one byte");
     __shared__ uint8_t sh_st[CMAX][64];
-    __shared__ float2 sh_xy[kXY ? CMAX : 1u][64];
+    __shared__ float2 sh_xy[CMAX][64];
     const uint32_t c = blockIdx.x * 64u + threadIdx.x;
     const uint32_t nch = (m + C - 1) / C;
     if (c >= nch) return;
     const uint32_t b = c * C, e = min(m, b + C);
     uint8_t* st = &sh_st[0][threadIdx.x];   // entry j at st[64 * j]: lanes hit distinct banks
     float2* sxy = &sh_xy[0][threadIdx.x];
+    TileWalk w0{0u, 0u, 0xFFFFFFFFu};
+    if (toff) w0 = tile_of(toff, ntiles, m, b);
+    TileWalk w = w0;
     uint32_t len = 0;
     float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f;   // top (2) and below-top (1) of the stack
-    uint64_t prev = (b > 0) ? keys[b - 1] : 0ull;
-    bool have_prev = b > 0;
     // The chunk's keys are read kChainPrefetch at a time, the next batch's
     // loads issued before the current batch is walked.
     uint64_t kb[kChainPrefetch];
 #pragma unroll
-    for (uint32_t u = 0; u < kChainPrefetch; ++u) kb[u] = (b + u < e) ? keys[b + u] : 0ull;
+    for (uint32_t u = 0; u < kChainPrefetch; ++u) {
+        const uint32_t p = b + u;
+        kb[u] = (p < e) ? keys[toff ? slot_of(toff, ntiles, m, w, p) : p] : 0ull;
+    }
     for (uint32_t i0 = b; i0 < e; i0 += kChainPrefetch) {
         uint64_t kn[kChainPrefetch];
 #pragma unroll
         for (uint32_t u = 0; u < kChainPrefetch; ++u) {
-            const uint32_t i = i0 + kChainPrefetch + u;
-            kn[u] = (i < e) ? keys[i] : 0ull;
+            const uint32_t p = i0 + kChainPrefetch + u;
+            kn[u] = (p < e) ? keys[toff ? slot_of(toff, ntiles, m, w, p) : p] : 0ull;
         }
 #pragma unroll
         for (uint32_t u = 0; u < kChainPrefetch; ++u) {
             const uint32_t i = i0 + u;
             if (i >= e) break;
             const uint64_t k = kb[u];
-            if (dedup && have_prev && k == prev) continue;
-            prev = k;
-            have_prev = true;
             const float x = key_x(k), y = key_y(k);
             while (len >= 2 && orient_dev(x1, y1, x2, y2, x, y) * sign <= 0) {
                 --len;
                 x2 = x1;
                 y2 = y1;
                 if (len >= 2) {
-                    if constexpr (kXY) {
-                        const float2 q = sxy[64u * (len - 2)];
-                        x1 = q.x;
-                        y1 = q.y;
-                    } else {
-                        const uint64_t kp = keys[b + st[64u * (len - 2)]];
-                        x1 = key_x(kp);
-                        y1 = key_y(kp);
-                    }
+                    const float2 q = sxy[64u * (len - 2)];
+                    x1 = q.x;
+                    y1 = q.y;
                 }
             }
             st[64u * len] = (uint8_t)(i - b);
-            if constexpr (kXY) sxy[64u * len] = make_float2(x, y);
+            sxy[64u * len] = make_float2(x, y);
             ++len;
             x1 = x2;
             y1 = y2;
@@ -448,7 +470,10 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
         for (uint32_t u = 0; u < kChainPrefetch; ++u) kb[u] = kn[u];
     }
     uint32_t* o = out + (uint64_t)b;
-    for (uint32_t j = 0; j < len; ++j) o[j] = b + st[64u * j];
+    for (uint32_t j = 0; j < len; ++j) {
+        const uint32_t p = b + st[64u * j];
+        o[j] = toff ? slot_of(toff, ntiles, m, w0, p) : p;
+    }
     cnt[c] = len;
 }
 
@@ -462,28 +487,54 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
 // it joins the chains.
 //
 // Wave w owns the runs whose first point lies in its tile, positions
-// [w*T, (w+1)*T) with T = kRunTile, and writes their representatives'
-// positions, in order, to out[w*T ...] (at most T) and their number to
+// [w*T, (w+1)*T) with T = kRunTile, and writes their representatives, in
+// order, to rk/rv[w*T ...] (key and value; at most T) and their number to
 // cnt[w].  It walks the tile 64 positions a step (lane l reads position
 // i0 + l; the tile's loads are all issued before the first step), and past
-// the tile's end while a run it owns is still open.  In a step a segmented
-// minimum scan over the lanes (a segment starts at each lane whose x differs
-// from its predecessor's) gives every lane the least (y', position) of its
-// run so far, y' the order-preserving bits of y for the lower side and their
-// complement for the upper, so the minimum is the first point of least
-// (greatest) y; the run open at the end of a step is carried into the next.
+// the tile's end while a run it owns is still open.  In a step every lane
+// needs the least (y', position) of its run so far, y' the order-preserving
+// bits of y for the lower side and their complement for the upper, so the
+// least is the first point of least (greatest) y: a prefix minimum over the
+// lanes of (64 - g, y', lane), g the number of run heads at or below the
+// lane, in which lanes of earlier runs (smaller g) never win.  The run open
+// at the end of a step is carried into the next.
 constexpr uint32_t kRunSteps = kRunTile / 64u;
+
+// v from the lane CTRL names (row_shr within rows of 16, or a row
+// broadcast into the rows of ROWS); all ones where there is none.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)(uint32_t)v, CTRL, ROWS, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive prefix minimum over the lanes of the wave: within rows of 16
+// (row_shr 1, 2, 4, 8), then row 0's last lane into row 1 and row 2's into
+// row 3 (row_bcast:15), then lane 31 into rows 2 and 3 (row_bcast:31).
+__device__ __forceinline__ uint64_t wave_prefix_min(uint64_t v) {
+    v = min(v, dpp_u64<0x111, 0xF>(v));
+    v = min(v, dpp_u64<0x112, 0xF>(v));
+    v = min(v, dpp_u64<0x114, 0xF>(v));
+    v = min(v, dpp_u64<0x118, 0xF>(v));
+    v = min(v, dpp_u64<0x142, 0xA>(v));
+    v = min(v, dpp_u64<0x143, 0xC>(v));
+    return v;
+}
 
 struct RunCarry {
     bool open;       // a run is open before this step
     bool own;        // the wave owns it
     uint32_t x;      // its x (ordered bits)
     uint64_t best;   // least (y', position) of it so far
+    uint32_t val;    // the value at that position
 };
 
-// One step at positions [i0, i0 + 64); false once the wave is done.
-__device__ __forceinline__ bool run_step(uint64_t k, uint32_t i0, uint32_t m, uint32_t e, int sign, uint32_t lane,
-                                         RunCarry& c, uint32_t* __restrict__ out, uint32_t& len) {
+// One step at positions [i0, i0 + 64) (key k and value kv per lane); false
+// once the wave is done.
+__device__ __forceinline__ bool run_step(uint64_t k, uint32_t kv, uint32_t i0, uint32_t m, uint32_t e, int sign,
+                                         uint32_t lane, uint64_t upto, RunCarry& c, uint64_t* __restrict__ rk,
+                                         uint32_t* __restrict__ rv, uint32_t& len) {
     const uint32_t i = i0 + lane;
     const bool valid = i < m;
     const uint32_t kx = (uint32_t)(k >> 32);
@@ -491,114 +542,158 @@ __device__ __forceinline__ bool run_step(uint64_t k, uint32_t i0, uint32_t m, ui
     const uint32_t px = (uint32_t)__shfl_up((int)kx, 1, 64);
     const bool head = !valid || (lane == 0u ? (!c.open || kx != c.x) : kx != px);
     const uint64_t H = __ballot(head);
-    uint64_t s = ((uint64_t)ky << 32) | i;
-    bool f = head;
-#pragma unroll
-    for (uint32_t d = 1; d < 64u; d <<= 1) {
-        const uint64_t t = __shfl_up(s, d, 64);
-        const bool tf = __shfl_up((int)f, d, 64) != 0;
-        if (lane >= d) {
-            if (!f) s = min(s, t);
-            f = f || tf;
-        }
+    const uint32_t g = (uint32_t)__popcll(H & upto);   // runs starting at or below this lane
+    const uint64_t v = wave_prefix_min(((uint64_t)(64u - g) << 40) | ((uint64_t)ky << 6) | lane);
+    uint64_t s = ((uint64_t)(uint32_t)(v >> 6) << 32) | (i0 + (uint32_t)(v & 63u));
+    uint32_t sv = (uint32_t)__shfl((int)kv, (int)(v & 63u), 64);
+    const bool carried = g == 0u;   // this lane is in the run carried in
+    if (carried && c.best < s) {
+        s = c.best;
+        sv = c.val;
     }
-    const uint64_t upto = (2ull << lane) - 1ull;   // this lane and those below (lane 63: all)
-    const bool carried = (H & upto) == 0ull;       // no run starts at or below this lane
-    if (carried) s = min(s, c.best);
     const bool own = carried ? c.own : (i0 < e);
     const bool end = valid && (lane < 63u ? ((H >> lane) & 2ull) != 0ull : i + 1u == m);
     const bool emit = end && own;
     const bool cemit = c.open && c.own && (H & 1ull) != 0ull;   // the carried run ended at i0 - 1
     const uint64_t E = __ballot(emit);
     const uint32_t base = len + (cemit ? 1u : 0u);
-    if (cemit && lane == 0u) out[len] = (uint32_t)c.best;
-    if (emit) out[base + (uint32_t)__popcll(E & (upto >> 1))] = (uint32_t)s;
+    if (cemit && lane == 0u) {
+        const uint32_t y = (uint32_t)(c.best >> 32);
+        rk[len] = ((uint64_t)c.x << 32) | (sign > 0 ? y : ~y);
+        rv[len] = c.val;
+    }
+    if (emit) {
+        const uint32_t o = base + (uint32_t)__popcll(E & (upto >> 1));
+        const uint32_t y = (uint32_t)(s >> 32);
+        rk[o] = ((uint64_t)kx << 32) | (sign > 0 ? y : ~y);
+        rv[o] = sv;
+    }
     len = base + (uint32_t)__popcll(E);
     if (i0 + 64u >= m) return false;
     c.x = (uint32_t)__shfl((int)kx, 63, 64);
     c.best = __shfl(s, 63, 64);
+    c.val = (uint32_t)__shfl((int)sv, 63, 64);
     c.own = __shfl((int)own, 63, 64) != 0;
     c.open = true;
     return !(i0 + 64u >= e && !c.own);   // past the tile with no owned run open: done
 }
 
-__global__ __launch_bounds__(256) void k_runs(const uint64_t* __restrict__ keys, uint32_t m, int sign,
-                                              uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
+__global__ __launch_bounds__(256) void k_runs(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                              uint32_t m, int sign, uint64_t* __restrict__ rk,
+                                              uint32_t* __restrict__ rv, uint32_t* __restrict__ cnt) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6);
     const uint32_t nt = (m + kRunTile - 1u) / kRunTile;
     if (w >= nt) return;   // whole waves only
     const uint32_t b = w * kRunTile, e = min(m, b + kRunTile);
+    const uint64_t upto = (2ull << lane) - 1ull;   // this lane and those below (lane 63: all)
     uint64_t kr[kRunSteps];
+    uint32_t vr[kRunSteps];
 #pragma unroll
     for (uint32_t u = 0; u < kRunSteps; ++u) {
         const uint32_t i = b + 64u * u + lane;
         kr[u] = (i < m) ? keys[i] : 0ull;
+        vr[u] = (i < m) ? vals[i] : 0u;
     }
     // a run open at b started in the previous tile: not this wave's
-    RunCarry c{b > 0u, false, (b > 0u) ? (uint32_t)(keys[b - 1u] >> 32) : 0u, ~0ull};
-    uint32_t* o = out + (uint64_t)b;
+    RunCarry c{b > 0u, false, (b > 0u) ? (uint32_t)(keys[b - 1u] >> 32) : 0u, ~0ull, 0u};
+    uint64_t* ok = rk + (uint64_t)b;
+    uint32_t* ov = rv + (uint64_t)b;
     uint32_t len = 0;
     bool more = true;
 #pragma unroll
     for (uint32_t u = 0; u < kRunSteps; ++u) {
-        more = run_step(kr[u], b + 64u * u, m, e, sign, lane, c, o, len);
+        more = run_step(kr[u], vr[u], b + 64u * u, m, e, sign, lane, upto, c, ok, ov, len);
         if (!more) break;
     }
     // past the tile: the owned run still open
     for (uint32_t i0 = b + kRunTile; more; i0 += 64u) {
         const uint32_t i = i0 + lane;
-        more = run_step((i < m) ? keys[i] : 0ull, i0, m, e, sign, lane, c, o, len);
+        more = run_step((i < m) ? keys[i] : 0ull, (i < m) ? vals[i] : 0u, i0, m, e, sign, lane, upto, c, ok, ov,
+                        len);
     }
     if (lane == 0u) cnt[w] = len;
 }
 
-// Exclusive scan of n counts in place (one block of 1024); the total goes
-// to *total.  Each round scans 4096 counts: 4 consecutive per thread, a
-// shuffle scan inside each wave, and one LDS exchange of the 16 wave totals.
-__global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ a, uint32_t n, uint32_t* total) {
+// Exclusive scan in place of a[b, b + 4096) (clipped to n) by a block of
+// 1024, starting from `carry`; returns the segment's total (every thread).
+// Four consecutive counts per thread, a shuffle scan inside each wave, and
+// one LDS exchange of the 16 wave totals.
+__device__ __forceinline__ uint32_t scan_4096(uint32_t* __restrict__ a, uint32_t b, uint32_t n, uint32_t carry,
+                                              uint32_t* wsum) {
     constexpr int NW = 1024 / 64;
-    __shared__ uint32_t wsum[NW];
-    __shared__ uint32_t carry;
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
-    if (t == 0) carry = 0u;
-    __syncthreads();
-    for (uint32_t b = 0; b < n; b += 4096u) {
-        uint32_t v[4], s = 0;
+    uint32_t v[4], s = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t i = b + 4u * t + (uint32_t)q;
-            v[q] = (i < n) ? a[i] : 0u;
-            s += v[q];
-        }
-        uint32_t incl = s;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
-            if ((int)lane >= o) incl += u;
-        }
-        if (lane == 63u) wsum[wave] = incl;
-        __syncthreads();
-        uint32_t before = carry;
-        uint32_t all = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const uint32_t x = wsum[w];
-            if (w < (int)wave) before += x;
-            all += x;
-        }
-        uint32_t e = before + incl - s;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t i = b + 4u * t + (uint32_t)q;
-            if (i < n) a[i] = e;
-            e += v[q];
-        }
-        __syncthreads();   // every thread has read carry and wsum
-        if (t == 0) carry += all;
-        __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = b + 4u * t + (uint32_t)q;
+        v[q] = (i < n) ? a[i] : 0u;
+        s += v[q];
     }
-    if (t == 0) *total = carry;
+    uint32_t incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+        if ((int)lane >= o) incl += u;
+    }
+    if (lane == 63u) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = carry, all = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t x = wsum[w];
+        if (w < (int)wave) before += x;
+        all += x;
+    }
+    uint32_t e = before + incl - s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = b + 4u * t + (uint32_t)q;
+        if (i < n) a[i] = e;
+        e += v[q];
+    }
+    __syncthreads();   // every thread has read wsum
+    return all;
+}
+
+// Exclusive scan of n counts in place (one block of 1024, 4096 counts a
+// round); the total goes to *total.
+__global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ a, uint32_t n, uint32_t* total) {
+    __shared__ uint32_t wsum[16];
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < n; b += 4096u) carry += scan_4096(a, b, n, carry, wsum);
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// Many counts: block k sums a[4096k, 4096(k+1)) into bs[k]; bs is then
+// scanned by k_scan_counts, and k_scan_apply scans each segment from its
+// offset.
+__global__ __launch_bounds__(1024) void k_scan_blocksum(const uint32_t* __restrict__ a, uint32_t n,
+                                                        uint32_t* __restrict__ bs) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+    const uint32_t b = blockIdx.x * 4096u;
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = b + 4u * t + (uint32_t)q;
+        s += (i < n) ? a[i] : 0u;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += (uint32_t)__shfl_xor((int)s, o, 64);
+    if (lane == 0u) wsum[wave] = s;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t all = 0;
+        for (int w = 0; w < 16; ++w) all += wsum[w];
+        bs[blockIdx.x] = all;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(uint32_t* __restrict__ a, uint32_t n,
+                                                     const uint32_t* __restrict__ bs) {
+    __shared__ uint32_t wsum[16];
+    (void)scan_4096(a, blockIdx.x * 4096u, n, bs[blockIdx.x], wsum);
 }
 
 // Chain vertices of every chunk, in order: chunk c's entries out[c*C + j]
@@ -770,32 +865,36 @@ hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, u
     return hipSuccess;   // an even number of passes: the result is back in keys / vals
 }
 
-hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, int dedup, uint32_t* chain,
-                        uint32_t* cnt, hipStream_t stream) {
-    if (C == 0 || C > kChainMaxC) return hipErrorInvalidValue;
+hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, const uint32_t* toff,
+                        uint32_t ntiles, uint32_t* chain, uint32_t* cnt, hipStream_t stream) {
+    if (C == 0 || C > kChainMaxC || (toff && ntiles == 0)) return hipErrorInvalidValue;
     const uint32_t nch = (m + C - 1) / C;
+    if (nch == 0) return hipSuccess;
+    const dim3 grid((nch + 63) / 64);
     if (C <= 32u)
-        hipLaunchKernelGGL(k_chain<32>, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup, chain,
-                           cnt);
-    else if (C <= 64u)
-        hipLaunchKernelGGL(k_chain<64>, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup, chain,
-                           cnt);
+        hipLaunchKernelGGL(k_chain<32>, grid, dim3(64), 0, stream, keys, m, C, sign, toff, ntiles, chain, cnt);
     else
-        hipLaunchKernelGGL(k_chain<kChainMaxC>, dim3((nch + 63) / 64), dim3(64), 0, stream, keys, m, C, sign, dedup,
-                           chain, cnt);
+        hipLaunchKernelGGL(k_chain<64>, grid, dim3(64), 0, stream, keys, m, C, sign, toff, ntiles, chain, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_runs(const uint64_t* keys, uint32_t m, int sign, uint32_t* reps, uint32_t* cnt,
-                       hipStream_t stream) {
+hipError_t launch_runs(const uint64_t* keys, const uint32_t* vals, uint32_t m, int sign, uint64_t* rk, uint32_t* rv,
+                       uint32_t* cnt, hipStream_t stream) {
     const uint32_t nt = (m + kRunTile - 1u) / kRunTile;
     if (nt == 0u) return hipSuccess;
-    hipLaunchKernelGGL(k_runs, dim3((nt + 3u) / 4u), dim3(256), 0, stream, keys, m, sign, reps, cnt);
+    hipLaunchKernelGGL(k_runs, dim3((nt + 3u) / 4u), dim3(256), 0, stream, keys, vals, m, sign, rk, rv, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, hipStream_t stream) {
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, cnt, n, total);
+hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, uint32_t* blk, hipStream_t stream) {
+    const uint32_t nb = (n + 4095u) / 4096u;
+    if (nb <= 4u || blk == nullptr) {
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, cnt, n, total);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_blocksum, dim3(nb), dim3(1024), 0, stream, cnt, n, blk);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, blk, nb, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, stream, cnt, n, blk);
     return hipGetLastError();
 }
 

@@ -170,17 +170,22 @@ hipError_t launch_finish_keys(const float2* pts, uint64_t n, const uint32_t* sur
 // whole key; 32: x alone); first_shift must leave an even number of passes.
 hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
                               uint32_t* hist, uint32_t* rowsum, uint32_t first_shift, hipStream_t stream);
-// Run representatives of keys sorted by x alone (see k_runs): positions into
-// reps (m words; tile t's at t*kRunTile), counts per tile into cnt
-// (ceil(m / kRunTile) words).
+// Run representatives of keys sorted by x alone (see k_runs): their keys
+// and values into rk / rv (m entries each; tile t's at t*kRunTile, cnt[t]
+// of them), counts per tile into cnt (ceil(m / kRunTile) words).
 constexpr uint32_t kRunTile = 1024;
-hipError_t launch_runs(const uint64_t* keys, uint32_t m, int sign, uint32_t* reps, uint32_t* cnt,
-                       hipStream_t stream);
-// Chains of chunks of C sorted points: chain holds m words (chunk c's
-// chain at c*C), cnt ceil(m/C) words.  sign 1 = lower, -1 = upper.
-hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, int dedup, uint32_t* chain,
-                        uint32_t* cnt, hipStream_t stream);
-hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, hipStream_t stream);
+hipError_t launch_runs(const uint64_t* keys, const uint32_t* vals, uint32_t m, int sign, uint64_t* rk, uint32_t* rv,
+                       uint32_t* cnt, hipStream_t stream);
+// Chains of chunks of C sorted points (C at most 64): chain holds m words
+// (chunk c's chain at c*C), cnt ceil(m/C) words.  With toff (the exclusive
+// scan of the run pass's ntiles tile counts, m their total) the points are
+// the run pass's output packed together and the chain entries are its
+// slots.  sign 1 = lower, -1 = upper.
+hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, const uint32_t* toff,
+                        uint32_t ntiles, uint32_t* chain, uint32_t* cnt, hipStream_t stream);
+// Exclusive scan of n counts in place, the total to *total; blk (at least
+// ceil(n / 4096) words, or null for one block) holds partial sums.
+hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, uint32_t* blk, hipStream_t stream);
 // Merge tree over chains c < nc at [off[c], off[c+1]) (off holds nc + 1
 // words): pair p = chains 2p, 2p+1 (the last one alone when nc is odd).
 // launch_bridge writes br[p] = (points kept of the left chain, first point

@@ -76,6 +76,7 @@ struct hullf_ctx {
     uint32_t* fv[3] = {nullptr, nullptr, nullptr};   // point indices
     uint32_t* fchain = nullptr;
     uint32_t* fcnt = nullptr;
+    uint32_t* fblk = nullptr;
     uint32_t* fhist = nullptr;
     uint32_t* frow = nullptr;     // 256 row sums + 1 total
     uint64_t f_cap = 0;           // entries of fk/fv/fchain
@@ -87,7 +88,7 @@ struct hullf_ctx {
     uint32_t* h_total = nullptr;
     Shape filter_shape{512, 16};
     bool host_finish = false;              // hull finishing always on the host
-    uint32_t chain_chunk = 256;            // sorted points per chain thread (16..256, a power of two)
+    uint32_t chain_chunk = 32;             // sorted points per chain thread (16..64)
     int classify_per_cu = 0;               // classify blocks per CU (0: what occupancy allows)
     int compact_block = 512;               // threads per compaction block
     int reduce_grid_max = 0;               // reduction blocks (0: 4 per CU)
@@ -354,8 +355,10 @@ hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
         }
         ws_free(c, c->fchain);
         ws_free(c, c->fcnt);
+        ws_free(c, c->fblk);
         c->fchain = nullptr;
         c->fcnt = nullptr;
+        c->fblk = nullptr;
         c->f_cap = 0;
         const uint64_t cap = m + m / 8 + 1024;
         for (int k = 0; k < 3; ++k) {
@@ -363,7 +366,9 @@ hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
             if ((e = ws_alloc(c, &c->fv[k], cap)) != hipSuccess) return e;
         }
         if ((e = ws_alloc(c, &c->fchain, cap)) != hipSuccess) return e;
-        if ((e = ws_alloc(c, &c->fcnt, cap / kChainChunkMin + 2)) != hipSuccess) return e;
+        // chunk counts / merge offsets, then the run pass's tile counts
+        if ((e = ws_alloc(c, &c->fcnt, cap / kChainChunkMin + 2 + cap / kRunTile + 2)) != hipSuccess) return e;
+        if ((e = ws_alloc(c, &c->fblk, (cap / kChainChunkMin + 2) / 4096 + 2)) != hipSuccess) return e;
         c->f_cap = cap;
     }
     const uint64_t hw = 256ull * finish_sort_tiles((uint32_t)m);
@@ -406,29 +411,26 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
     for (int side = 0; side < 2; ++side) {
         const int sign = side == 0 ? 1 : -1;
         // the side's representative of every run of equal x, in order
-        // (distinct points, sorted by (x, y))
+        // (distinct points, sorted by (x, y)), per tile of the run pass;
+        // the first chunk level reads them through the scanned tile counts
+        uint32_t* const tcnt = c->fcnt + c->f_cap / kChainChunkMin + 2;
+        const uint32_t ntiles = (mm + kRunTile - 1) / kRunTile;
+        CHECK_HIP(launch_runs(c->fk[0], c->fv[0], mm, sign, c->fk[1], c->fv[1], tcnt, s));
+        CHECK_HIP(launch_scan_counts(tcnt, ntiles, c->frow + 256, c->fblk, s));
+        CHECK_HIP(hipMemcpyAsync(c->h_total, c->frow + 256, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        const uint32_t reps = *c->h_total;
+        if (reps == 0 || reps > mm) return HULLF_EDEVICE;
+        const uint32_t* toff = tcnt;
         int cur = 1;
-        uint32_t cm = 0, nc = 0;
-        {
-            const uint32_t nch = (mm + kRunTile - 1) / kRunTile;
-            CHECK_HIP(launch_runs(c->fk[0], mm, sign, c->fchain, c->fcnt, s));
-            CHECK_HIP(launch_scan_counts(c->fcnt, nch, c->frow + 256, s));
-            CHECK_HIP(hipMemcpyAsync(c->h_total, c->frow + 256, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-            CHECK_HIP(hipStreamSynchronize(s));
-            cm = *c->h_total;
-            if (cm == 0 || cm > mm) return HULLF_EDEVICE;
-            const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((nch + 3) / 4, (uint32_t)c->cus * 8));
-            CHECK_HIP(launch_chain_gather(c->fk[0], c->fv[0], mm, kRunTile, c->fchain, c->fcnt, cm, c->fk[1],
-                                          c->fv[1], gg, s));
-        }
+        uint32_t cm = reps, nc = 0;
         // chunk levels while they shrink the set well
-        const int dedup = 0;
         for (;;) {
             const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
             const uint32_t C = c->chain_chunk;
             const uint32_t nch = (cm + C - 1) / C;
-            CHECK_HIP(launch_chain(c->fk[cur], cm, C, sign, dedup, c->fchain, c->fcnt, s));
-            CHECK_HIP(launch_scan_counts(c->fcnt, nch, c->frow + 256, s));
+            CHECK_HIP(launch_chain(c->fk[cur], cm, C, sign, toff, toff ? ntiles : 0u, c->fchain, c->fcnt, s));
+            CHECK_HIP(launch_scan_counts(c->fcnt, nch, c->frow + 256, c->fblk, s));
             CHECK_HIP(hipMemcpyAsync(c->h_total, c->frow + 256, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
             CHECK_HIP(hipStreamSynchronize(s));
             const uint32_t tot = *c->h_total;
@@ -440,6 +442,7 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
             cur = nxt;
             cm = tot;
             nc = nch;
+            toff = nullptr;
             if (slow || cm <= kLevelStop) break;
         }
         // merge tree: the chunk chains of the last level, pairwise, until
@@ -453,7 +456,7 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
             const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
             const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((np + 3) / 4, (uint32_t)c->cus * 8));
             CHECK_HIP(launch_bridge(c->fk[cur], off_in, nc, sign, br, off_out, gg, s));
-            CHECK_HIP(launch_scan_counts(off_out, np, off_out + np, s));
+            CHECK_HIP(launch_scan_counts(off_out, np, off_out + np, c->fblk, s));
             CHECK_HIP(launch_merge_gather(c->fk[cur], c->fv[cur], off_in, nc, br, off_out, c->fk[nxt], c->fv[nxt],
                                           c->cus * 4, s));
             std::swap(off_in, off_out);
@@ -676,7 +679,7 @@ hullf_status hullf_create(int device, size_t workspace_bytes, hullf_ctx_t* out) 
     if (const char* e = std::getenv("HULLF_FINISH")) c->host_finish = std::strcmp(e, "host") == 0;
     if (const char* e = std::getenv("HULLF_CHAIN_CHUNK")) {
         const int v = std::atoi(e);
-        if (v >= (int)kChainChunkMin && v <= 256 && (v & (v - 1)) == 0) c->chain_chunk = (uint32_t)v;
+        if (v >= (int)kChainChunkMin && v <= 64) c->chain_chunk = (uint32_t)v;
     }
     if (const char* e = std::getenv("HULLF_REGION_SKIP")) c->region_skip = std::atoi(e) != 0;
     if (const char* e = std::getenv("HULLF_CLASSIFY_PER_CU")) c->classify_per_cu = std::max(0, std::atoi(e));
@@ -738,8 +741,8 @@ void hullf_destroy(hullf_ctx_t c) {
                    c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_boxes, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
-    void* fin[] = {c->fk[0], c->fk[1], c->fk[2], c->fv[0], c->fv[1], c->fv[2], c->fchain, c->fcnt, c->fhist,
-                   c->frow};
+    void* fin[] = {c->fk[0], c->fk[1], c->fk[2], c->fv[0],   c->fv[1],
+                   c->fv[2], c->fchain, c->fcnt,  c->fblk,  c->fhist, c->frow};
     for (void* p : fin)
         if (p) (void)hipFree(p);
     void* host[] = {c->h_surv, c->h_xy, c->h_count, c->h_oct, c->h_fk, c->h_fv, c->h_total, c->h_poly16};

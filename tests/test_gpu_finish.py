@@ -190,10 +190,11 @@ def test_run_lengths_around_step_and_tile(ctx, torch_dev, seed):
     assert np.array_equal(ctx.hull_from_survivors(t, s), oracle.hull(xy))
 
 
-@pytest.mark.parametrize("chunk", [16, 64, 128])
+@pytest.mark.parametrize("chunk", [16, 48, 64])
 def test_chain_chunk_sizes(torch_dev, monkeypatch, chunk):
-    """The chain pass with other chunk sizes (HULLF_CHAIN_CHUNK): more chunk
-    levels and a deeper merge tree, the same hull."""
+    """The chain pass with other chunk sizes (HULLF_CHAIN_CHUNK; 48 is no
+    divisor of the run pass's tile, so chunks straddle its tiles unevenly):
+    other chunk levels and merge trees, the same hull."""
     monkeypatch.setenv("HULLF_CHAIN_CHUNK", str(chunk))
     c = hullf.Context(0)
     try:
