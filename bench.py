@@ -158,6 +158,36 @@ def stored_traffic():
     return d
 
 
+def e2e_hull(ctx, sets, dpts, reps: int = 3):
+    """convex_hull (filter + finishing, host-synchronous) per set: one
+    untimed call (workspace growth), then the median of `reps`."""
+    e2e = {}
+    for i, (kind, _, _) in enumerate(sets):
+        h = ctx.convex_hull(dpts[i])
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            h = ctx.convex_hull(dpts[i])
+            ts.append((time.perf_counter() - t0) * 1e3)
+        e2e[kind] = {"ms": round(float(np.median(ts)), 2), "hull_vertices": int(h.size)}
+    return e2e
+
+
+def only_e2e(args):
+    """The hull finishing leg alone (for kernel traces of the finishing)."""
+    import torch
+    from paper_2303_10581_amd import hullf
+
+    dev = torch.device("cuda:0")
+    sets = make_sets()
+    ctx = hullf.Context(0)
+    dpts = [torch.from_numpy(xy).to(dev) for _, _, xy in sets]
+    torch.cuda.synchronize()
+    res = {"workload": "convex_hull of each 1e8-point set", "e2e_hull": e2e_hull(ctx, sets, dpts)}
+    ctx.close()
+    return res
+
+
 def run_bench(args):
     import torch
     from paper_2303_10581_amd import hullf
@@ -285,12 +315,7 @@ def run_bench(args):
     }
 
     if not args.no_e2e:
-        e2e = {}
-        for i, (kind, _, _) in enumerate(sets):
-            t0 = time.perf_counter()
-            h = ctx.convex_hull(dpts[i])
-            e2e[kind] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "hull_vertices": int(h.size)}
-        result["e2e_hull"] = e2e
+        result["e2e_hull"] = e2e_hull(ctx, sets, dpts)
 
     if not args.no_e2e:
         result["filter16"] = bench_filter16(ctx, dpts, surv, cnt, [k for k, _, _ in sets], survivors, per_set)
@@ -301,6 +326,7 @@ def run_bench(args):
     if not args.no_e2e:
         result["small_set_1e6"] = bench_small(ctx, dev)
         result["library_compaction"] = bench_library_compaction(ctx, dpts, surv, cnt, [k for k, _, _ in sets])
+        result["single_pass_ab"] = bench_single_pass(dpts, surv, cnt, [k for k, _, _ in sets])
         result["large_set_5e8"] = bench_large(ctx, dev)
 
     ctx.close()
@@ -453,6 +479,64 @@ def bench_small(ctx, dev, reps: int = 50):
     return out
 
 
+def _filter_ms(ctx, t, sv, c, stream, reps: int = 5) -> float:
+    """Median of `reps` hull_filter calls (after one untimed), HIP events on
+    the launch stream."""
+    import torch
+    ms = []
+    for _ in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.hull_filter(t, surv=sv, count=c, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return float(np.median(ms[1:]))
+
+
+def _context(single_pass: bool):
+    """A context whose hull_filter runs in one pass (decoupled look-back) or
+    in two (keep bits, then compaction)."""
+    from paper_2303_10581_amd import hullf
+    old = os.environ.get("HULLF_SINGLE_PASS")
+    os.environ["HULLF_SINGLE_PASS"] = "1" if single_pass else "0"
+    try:
+        return hullf.Context(0)
+    finally:
+        if old is None:
+            del os.environ["HULLF_SINGLE_PASS"]
+        else:
+            os.environ["HULLF_SINGLE_PASS"] = old
+
+
+def bench_single_pass(dpts, surv, cnt, kinds, reps: int = 5):
+    """A/B of the inside test + compaction: two passes (k_classify writes keep
+    bits and block counts, k_compact writes the survivors) against one
+    (k_filter1p: tiles in ticket order, offsets by decoupled look-back), each
+    hull_filter call whole (reduction and set-up included), survivors
+    compared."""
+    import torch
+    stream = torch.cuda.current_stream()
+    two, one = _context(False), _context(True)
+    rows = {}
+    for i, kind in enumerate(kinds):
+        t2 = _filter_ms(two, dpts[i], surv[i], cnt[i], stream, reps)
+        n2 = int(cnt[i].item())
+        s2 = surv[i][:n2].clone()
+        t1 = _filter_ms(one, dpts[i], surv[i], cnt[i], stream, reps)
+        n1 = int(cnt[i].item())
+        same = n1 == n2 and bool(torch.equal(surv[i][:n1], s2))
+        del s2
+        rows[kind] = {"two_pass_us": round(t2 * 1e3, 1), "single_pass_us": round(t1 * 1e3, 1),
+                      "survivors_equal": same}
+    two.close()
+    one.close()
+    s2 = sum(r["two_pass_us"] for r in rows.values())
+    s1 = sum(r["single_pass_us"] for r in rows.values())
+    return {"sets": rows, "step_two_pass_us": round(s2, 1), "step_single_pass_us": round(s1, 1),
+            "faster": "single_pass" if s1 < s2 else "two_pass"}
+
+
 def bench_large(ctx, dev, reps: int = 5):
     """5e8 points on the unit circle with N(0, 0.01) radial jitter (seed 5,
     4 GB): hull_filter at full HBM scale, median of `reps` calls with HIP
@@ -482,11 +566,20 @@ def bench_large(ctx, dev, reps: int = 5):
     surv = int(c.item())
     med = float(np.median(ms[1:]))
     ab = algorithmic_bytes(n, surv, g_read / g_total if g_total else 1.0)
-    del t, sv
+    # the same set through the two-pass and single-pass filters
+    s_ref = sv[:surv].clone()
+    ab_rows = {}
+    for mode in (False, True):
+        cm = _context(mode)
+        ms_m = _filter_ms(cm, t, sv, c, stream, reps)
+        cm.close()
+        ab_rows["single_pass" if mode else "two_pass"] = {
+            "ms": round(ms_m, 3), "survivors_equal": int(c.item()) == surv and bool(torch.equal(sv[:surv], s_ref))}
+    del t, sv, s_ref
     torch.cuda.empty_cache()
     return {"workload": "5e8 points, unit circle + N(0, 0.01) radial jitter, seed 5", "survivors": surv,
             "hull_filter_ms": round(med, 3), "Gpoints_s": round(n / med / 1e6, 1),
-            "hbm_frac": round(sum(ab.values()) / med / 1e6 / HBM_PEAK_GBS, 3)}
+            "hbm_frac": round(sum(ab.values()) / med / 1e6 / HBM_PEAK_GBS, 3), "passes_ab": ab_rows}
 
 
 def bench_library_compaction(ctx, dpts, surv, cnt, kinds, reps: int = 5):
@@ -892,6 +985,8 @@ def main():
     ap.add_argument("--serve-arena", type=int, default=1 << 30)
     ap.add_argument("--serve-finish", type=int, default=4)
     ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--only-e2e", action="store_true",
+                    help="convex_hull of each set only (hull finishing traces; not a bench line)")
     ap.add_argument("--p-sweep", action="store_true",
                     help="discarded fraction and filter time against the displacement p (not a bench line)")
     ap.add_argument("--parse-pmc", default=None)
@@ -914,6 +1009,9 @@ def main():
         return 0
     if args.p_sweep:
         print(json.dumps(p_sweep(args)), flush=True)
+        return 0
+    if args.only_e2e:
+        print(json.dumps(only_e2e(args)), flush=True)
         return 0
     res = run_bench(args)
     print(json.dumps(res), flush=True)

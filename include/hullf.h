@@ -99,6 +99,9 @@ typedef enum {
  *   HULLF_BATCH_REDUCE_PER_CU=k   batched reduction blocks per CU (1..16)
  *   HULLF_CHAIN_CHUNK=c           sorted points per hull-chain thread (16..64,
  *                                 default 32)
+ *   HULLF_SINGLE_PASS=1           hull_filter's inside test and compaction in one
+ *                                 launch (decoupled look-back; slower, kept for
+ *                                 comparison)
  *   HULLF_FINISH=host             hull finishing always on the host
  *   HULLF_TUNE_CACHE=path         tune cache file of the batched launch
  *                                 (default $XDG_CACHE_HOME/hullf/tune.txt or

@@ -96,17 +96,37 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
     return x * q + min(x, r) + j;
 }
 
+// A pass whose digits take few values (the top byte of clustered
+// coordinates) would serialise up to 64 LDS atomics on one address: each
+// round first peels off up to four large groups of lanes with equal digits
+// (one lane adds the group's size); the lanes left add one each.
 __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t m, uint32_t shift,
                                                       uint32_t tiles, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kRsBins];
-    const uint32_t t = threadIdx.x, tile = xcd_tile(blockIdx.x, tiles);
+    const uint32_t t = threadIdx.x, lane = t & 63u, tile = xcd_tile(blockIdx.x, tiles);
     h[t] = 0u;
     __syncthreads();
     const uint64_t base = (uint64_t)tile * kRsTile;
+    uint64_t k[kRsItems];
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
         const uint64_t i = base + (uint32_t)r * kRsBlock + t;
-        if (i < m) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+        k[r] = (i < m) ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        const bool valid = base + (uint32_t)r * kRsBlock + t < m;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+        unsigned long long rem = __ballot(valid);
+        for (int it = 0; it < 4 && rem != 0ull; ++it) {
+            const int leader = __ffsll((long long)rem) - 1;
+            const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)d, leader);
+            const unsigned long long grp = __ballot(valid && d == dl);
+            if (__popcll(grp) < 8) break;   // small groups: plain atomics
+            if (lane == (uint32_t)leader) atomicAdd(&h[dl], (uint32_t)__popcll(grp));
+            rem &= ~grp;
+        }
+        if ((rem >> lane) & 1ull) atomicAdd(&h[d], 1u);
     }
     __syncthreads();
     hist[(uint64_t)t * tiles + tile] = h[t];
@@ -696,23 +716,25 @@ __global__ __launch_bounds__(1024) void k_scan_apply(uint32_t* __restrict__ a, u
     (void)scan_4096(a, blockIdx.x * 4096u, n, bs[blockIdx.x], wsum);
 }
 
-// Chain vertices of every chunk, in order: chunk c's entries out[c*C + j]
+// Chain vertices of every chunk, in order: chunk c's entries chain[c*C + j]
 // (j < its length, i.e. next offset - offset) go to position off[c] + j.
+// One thread per slot of the chain array (chunk chains are short: a wave
+// per chunk left most lanes idle).
 __global__ __launch_bounds__(256) void k_chain_gather(const uint64_t* __restrict__ keys,
                                                       const uint32_t* __restrict__ vals, uint32_t m, uint32_t C,
                                                       const uint32_t* __restrict__ chain,
                                                       const uint32_t* __restrict__ off, uint32_t total,
                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
     const uint32_t nch = (m + C - 1) / C;
-    // one wave per chunk
-    const uint32_t lane = threadIdx.x & 63u;
-    for (uint32_t c = blockIdx.x * 4u + (threadIdx.x >> 6); c < nch; c += gridDim.x * 4u) {
+    const uint32_t slots = nch * C;   // slots + the grid stride < 2^32 (checked at launch)
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < slots; i += gridDim.x * 256u) {
+        const uint32_t c = i / C, j = i - c * C;
         const uint32_t o = off[c];
         const uint32_t end = (c + 1 < nch) ? off[c + 1] : total;
-        for (uint32_t j = lane; o + j < end; j += 64) {
-            const uint32_t p = chain[(uint64_t)c * C + j];
-            kout[o + j] = keys[p];
-            vout[o + j] = vals[p];
+        if (o + j < end) {
+            const uint32_t src = chain[i];
+            kout[o + j] = keys[src];
+            vout[o + j] = vals[src];
         }
     }
 }
@@ -901,6 +923,9 @@ hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, uint32
 hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint32_t m, uint32_t C,
                                const uint32_t* chain, const uint32_t* off, uint32_t total, uint64_t* kout,
                                uint32_t* vout, int grid, hipStream_t stream) {
+    // slot indices and the grid stride stay below 2^32
+    if (C == 0 || grid <= 0 || (uint64_t)((m + C - 1) / C) * C + (uint64_t)grid * 256u >= (1ull << 32))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_chain_gather, dim3(grid), dim3(256), 0, stream, keys, vals, m, C, chain, off, total, kout,
                        vout);
     return hipGetLastError();

@@ -75,9 +75,10 @@ struct Shape {
 // (9 * kReduceMaxGrid words, direction-major: part[j * kReduceMaxGrid + b])
 // and, if box is not null, 4 boxes per reduce_chunk_points() points
 // (box_count(n) float4); launch_setup merges the records and writes the
-// octagon.
+// octagon.  zero[0 .. nzero) is cleared by the same launch (the
+// single-pass filter's status words).
 hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, float4* box, int grid,
-                         hipStream_t stream);
+                         hipStream_t stream, unsigned long long* zero = nullptr, uint32_t nzero = 0);
 hipError_t launch_setup(const float2* pts, uint64_t n, Octagon* oct, const unsigned long long* part,
                         uint32_t nblocks, hipStream_t stream);
 constexpr int kReduceMaxGrid = 4096;
@@ -140,6 +141,14 @@ hipError_t launch_classify(const float2* pts, uint64_t n, const Poly16* poly, ui
 hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t n, uint32_t spans,
                           const Poly16* poly, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,
                           hipStream_t stream);
+// Single-pass filter of one set (inside test and compaction, decoupled
+// look-back; after launch_reduce / launch_setup): st holds
+// filter1p_tiles(n) + 1 words, zero at launch (launch_reduce clears them).
+// Same outputs as launch_classify + launch_compact.
+uint32_t filter1p_tiles(uint64_t n);
+hipError_t launch_filter1p(const float2* pts, uint64_t n, const Octagon* oct, const float4* box, uint64_t nbox,
+                           unsigned long long* st, uint32_t* out, uint64_t cap, uint64_t* count,
+                           unsigned long long* loaded, hipStream_t stream);
 
 // Batched: plan, reduction, octagon set-up, classify and compact (five
 // launches).  part: 9 * max_rtiles uint64 scratch.  off: S+1 CSR offsets,

@@ -897,11 +897,16 @@ constexpr uint32_t kRChunk = kRBlock * kRG * 2;
 // agent-scope release writes back the XCD's L2, and one per block costs more
 // than the whole streaming pass.  k_setup (next launch on the stream) merges
 // the records; the kernel boundary makes them visible.
+//
+// zero[0 .. nzero) is cleared on the way (the single-pass filter's ticket
+// and status words; nothing reads them before the filter launch).
 template <bool VEC4>
 __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_reduce(
-    const float2* __restrict__ pts, uint64_t n, unsigned long long* __restrict__ part, float4* __restrict__ box) {
+    const float2* __restrict__ pts, uint64_t n, unsigned long long* __restrict__ part, float4* __restrict__ box,
+    unsigned long long* __restrict__ zero, uint32_t nzero) {
     constexpr uint32_t CH = kRBlock * kRG * 2;
     const uint32_t nch = (uint32_t)((n + CH - 1) / CH);
+    for (uint32_t i = blockIdx.x * kRBlock + threadIdx.x; i < nzero; i += gridDim.x * kRBlock) zero[i] = 0ull;
     __shared__ unsigned long long rec[9];
     reduce_points<kRBlock, kRG, VEC4, true>(pts, 0, n, 0, blockIdx.x, gridDim.x, nch, rec, box);
     if (threadIdx.x < 9) part[(uint64_t)threadIdx.x * kReduceMaxGrid + blockIdx.x] = rec[threadIdx.x];
@@ -1598,6 +1603,165 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const uint64_t* __restrict__ 
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *count = base;
 }
 
+// ---------------------------------------------------------------------------
+// One set, inside test and compaction in one pass (decoupled look-back)
+// ---------------------------------------------------------------------------
+// Each block takes tiles of one span (kSpan points, 64 groups) in ticket
+// order: a block draws the next tile number from an atomic counter, so a
+// tile only ever waits for tiles whose blocks have already started, and the
+// waits end.  The tile is tested like a k_classify sub-tile (region skip
+// from the tile's 16 reduction boxes), its keep words stay in LDS, and its
+// survivor offset comes from a decoupled look-back over the tiles before it:
+// the tile publishes its count (flag A), wave 0 sums the counts of its
+// predecessors back to the nearest one that has published its inclusive
+// prefix (flag P), then publishes its own prefix.  Survivors are written by
+// compact_span straight from the keep words: no keep bits go through memory
+// and the writes of some tiles overlap the reads of others.
+//
+// st[0] is the ticket counter and st[1 + t] tile t's status word (zeroed
+// before the launch): 0 = nothing yet, A | count, P | inclusive prefix.
+constexpr uint64_t kLbA = 1ull << 62;
+constexpr uint64_t kLbP = 2ull << 62;
+constexpr uint64_t kLbValue = kLbA - 1ull;
+// Polls of one look-back window before the pass gives up (a tile's
+// predecessors have all started, so the waits end; this only turns a defect
+// into an error instead of a hang).
+constexpr uint32_t kLbSpinLimit = 1u << 18;
+
+__device__ __forceinline__ uint64_t lb_load(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(unsigned long long* p, uint64_t v) {
+    __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of tile t's count (wave 0, every lane gets it); `ok`
+// turns false if a window's predecessors did not publish within the limit.
+__device__ __forceinline__ uint64_t lookback(unsigned long long* __restrict__ st, uint32_t t, uint64_t total,
+                                             bool& ok) {
+    const uint32_t lane = lane_id();
+    if (t == 0u) {
+        if (lane == 0) lb_store(st + 1, kLbP | total);
+        return 0ull;
+    }
+    if (lane == 0) lb_store(st + 1 + t, kLbA | total);
+    uint64_t excl = 0;
+    int64_t j = (int64_t)t - 1;   // window: tiles j, j - 1, ..., j - 63 (lane order)
+    for (;;) {
+        const int64_t i = j - (int64_t)lane;
+        uint64_t v = (i >= 0) ? lb_load(st + 1 + i) : kLbP;   // before tile 0: prefix 0
+        uint32_t spins = 0;
+        for (;;) {
+            // lanes up to the nearest inclusive prefix must have published
+            const unsigned long long pm = __ballot((v >> 62) == 2ull);
+            const unsigned long long zm = __ballot((v >> 62) == 0ull);
+            const unsigned long long need = pm ? ((2ull << (__ffsll((long long)pm) - 1)) - 1ull) : ~0ull;
+            if ((zm & need) == 0ull) break;
+            if (++spins > kLbSpinLimit) {
+                ok = false;
+                break;
+            }
+            if ((v >> 62) == 0ull) v = lb_load(st + 1 + i);
+        }
+        const unsigned long long pm = __ballot((v >> 62) == 2ull);
+        if (pm != 0ull) {
+            const uint32_t p = (uint32_t)(__ffsll((long long)pm) - 1);
+            excl += wave_sum_u64(lane <= p ? (v & kLbValue) : 0ull);
+            break;
+        }
+        excl += wave_sum_u64(v & kLbValue);
+        j -= 64;
+    }
+    excl = uniform_u64(excl);
+    if (lane == 0) lb_store(st + 1 + t, kLbP | (excl + total));
+    return excl;
+}
+
+template <int BLOCK, int PPT, bool VEC4, int NV>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_filter1p(
+    const float2* __restrict__ pts, uint64_t n, const Poly<NV>* __restrict__ oct, const float4* __restrict__ box,
+    uint64_t nbox, unsigned long long* __restrict__ st, uint32_t* __restrict__ out, uint64_t cap,
+    uint64_t* count, unsigned long long* loaded) {
+    constexpr int NP = PPT / 2;
+    constexpr int NW = BLOCK / 64;
+    constexpr uint32_t ST = BLOCK * PPT;
+    static_assert(ST == kSpan, "a tile is one span");
+    static_assert(NW * NP == 64, "the tile's 64 groups: pair slot j of wave w is group j * NW + w");
+    __shared__ __attribute__((aligned(16))) uint32_t sh_stage[kStageWords];
+    __shared__ unsigned long long sh_kw[2 * 64];
+    __shared__ uint32_t sh_w[NW], sh_g[NW];
+    __shared__ uint32_t sh_t, sh_skip;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform_u32(threadIdx.x >> 6);
+    const uint32_t ntiles = (uint32_t)((n + ST - 1) / ST);
+    if (oct->status != 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *count = (oct->status == 1) ? kCountNonFinite : kCountInternal;
+        return;
+    }
+    PolyK<NV>* ok = as_const(oct);
+    const bool skipon = box != nullptr && ok->mode == 1 && ok->skip != 0;
+    if (threadIdx.x == 0) sh_t = atomicAdd(reinterpret_cast<unsigned int*>(st), 1u);
+    __syncthreads();
+    const uint32_t t = sh_t;
+    if (t >= ntiles) return;   // more blocks than tiles: nothing drawn
+    const uint64_t sb = (uint64_t)t * ST;
+    const bool full = sb + ST <= n;
+    // region skip: the tile's 16 boxes (4 per 2048-point reduction chunk)
+    if (wave == 0) {
+        bool pass = false;
+        if (skipon && full && lane < 16u) {
+            const uint64_t bi = (uint64_t)t * 16u + lane;
+            pass = bi < nbox && box_inside<NV>(box[bi], ok);
+        }
+        const unsigned long long m = __ballot(pass);
+        if (lane == 0) sh_skip = (uint32_t)m;
+    }
+    __syncthreads();
+    const uint32_t tskip = sh_skip;
+    uint32_t skipm = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const uint32_t g = (uint32_t)(j * NW) + wave;   // group of the tile
+        skipm |= ((tskip >> ((g >> 4) * 4u + (g & 3u))) & 1u) << j;
+    }
+    uint32_t total = 0;
+    unsigned long long m0 = 0ull, m1 = 0ull;
+    if (tskip != 0xFFFFu) {
+        float4 q[NP];
+        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q, full ? skipm : 0u);
+        const EdgeRegsN<NV> ek = load_edges(oct);
+        const uint32_t k = classify_sub<BLOCK, PPT, NV>(oct, ek, pts, sb, q, validm);
+        if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);
+    }
+    if (lane < (uint32_t)NP) {
+        const uint32_t g = lane * NW + wave;
+        sh_kw[2 * g] = m0;
+        sh_kw[2 * g + 1] = m1;
+    }
+    if (lane == 0) {
+        sh_w[wave] = total;
+        sh_g[wave] = (tskip != 0xFFFFu) ? (uint32_t)(NP - __popc(full ? skipm : 0u)) : 0u;
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    uint64_t sum = 0;
+    uint32_t groups = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        sum += sh_w[w];
+        groups += sh_g[w];
+    }
+    bool good = true;
+    const uint64_t excl = lookback(st, t, sum, good);
+    if (lane == 0) {
+        if (loaded && groups) atomicAdd(loaded, (unsigned long long)groups);
+        if (!good) *count = kCountInternal;
+        else if (t == ntiles - 1u) *count = excl + sum;
+    }
+    if (sum != 0ull && good)
+        compact_span(sh_kw[2 * lane], sh_kw[2 * lane + 1], sb, excl, cap, 0u, out, sh_stage);
+}
+
 template <bool VEC4>
 __global__ __launch_bounds__(256) void k_flags(const float2* __restrict__ pts, uint64_t n,
                                                const Octagon* __restrict__ oct, uint8_t* flags) {
@@ -1978,12 +2142,12 @@ bool shape_supported(Shape s) {
 }
 
 hipError_t launch_reduce(const float2* pts, uint64_t n, unsigned long long* part, float4* box, int grid,
-                         hipStream_t stream) {
-    if (grid < 1 || grid > kReduceMaxGrid) return hipErrorInvalidValue;
+                         hipStream_t stream, unsigned long long* zero, uint32_t nzero) {
+    if (grid < 1 || grid > kReduceMaxGrid || (nzero > 0u && zero == nullptr)) return hipErrorInvalidValue;
     if (is_vec4(pts))
-        hipLaunchKernelGGL(k_reduce<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part, box);
+        hipLaunchKernelGGL(k_reduce<true>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part, box, zero, nzero);
     else
-        hipLaunchKernelGGL(k_reduce<false>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part, box);
+        hipLaunchKernelGGL(k_reduce<false>, dim3(grid), dim3(kRBlock), 0, stream, pts, n, part, box, zero, nzero);
     return hipGetLastError();
 }
 
@@ -2102,6 +2266,22 @@ hipError_t launch_compact(const uint64_t* bits, const uint32_t* blkcnt, uint64_t
                           const Poly16* poly, uint32_t* out, uint64_t cap, uint64_t* count, int block, int grid,
                           hipStream_t stream) {
     return compact_launch<16>(bits, blkcnt, n, spans, poly, out, cap, count, block, grid, stream);
+}
+
+uint32_t filter1p_tiles(uint64_t n) { return (uint32_t)((n + kSpan - 1) / kSpan); }
+
+hipError_t launch_filter1p(const float2* pts, uint64_t n, const Octagon* oct, const float4* box, uint64_t nbox,
+                           unsigned long long* st, uint32_t* out, uint64_t cap, uint64_t* count,
+                           unsigned long long* loaded, hipStream_t stream) {
+    const uint32_t tiles = filter1p_tiles(n);
+    if (tiles == 0u) return hipSuccess;
+    if (is_vec4(pts))
+        hipLaunchKernelGGL((k_filter1p<512, 16, true, 8>), dim3(tiles), dim3(512), 0, stream, pts, n, oct, box, nbox,
+                           st, out, cap, count, loaded);
+    else
+        hipLaunchKernelGGL((k_filter1p<512, 16, false, 8>), dim3(tiles), dim3(512), 0, stream, pts, n, oct, box,
+                           nbox, st, out, cap, count, loaded);
+    return hipGetLastError();
 }
 
 hipError_t launch_flags(const float2* pts, uint64_t n, const Octagon* oct, uint8_t* flags, int grid,

@@ -99,6 +99,9 @@ struct hullf_ctx {
     float4* boxes = nullptr;               // reduction boxes (region skip), 4 per 2048 points
     uint64_t boxes_cap = 0;
     unsigned long long* groups_read = nullptr;   // device counter of groups the inside test read
+    unsigned long long* lb = nullptr;            // single-pass filter: ticket + tile status words
+    uint64_t lb_cap = 0;
+    bool single_pass = false;                    // hull_filter in one pass (decoupled look-back)
     uint64_t groups_total = 0;                   // groups it would read without the skip
     bool region_skip = true;
     // batched
@@ -285,6 +288,19 @@ hullf_status enqueue_filter(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, uin
         box = c->boxes;
     }
     const int rg = p.reduce_grid;
+    if (c->single_pass) {
+        // inside test and compaction in one launch; the reduction clears
+        // its ticket and status words
+        const uint32_t tiles = filter1p_tiles(n);
+        CHECK_HIP(grow_device(c, &c->lb, &c->lb_cap, (uint64_t)tiles + 1, s));
+        CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, box, rg, s, c->lb, tiles + 1); }));
+        CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
+        CHECK_HIP(timed(c, 1, s, [&] {
+            return launch_filter1p(pts, n, c->oct, box, nbox, c->lb, d_surv, cap, d_count, c->groups_read, s);
+        }));
+        c->groups_total += (n + 127) / 128;
+        return HULLF_OK;
+    }
     CHECK_HIP(timed(c, 0, s, [&] { return launch_reduce(pts, n, c->part, box, rg, s); }));
     CHECK_HIP(timed(c, 3, s, [&] { return launch_setup(pts, n, c->oct, c->part, (uint32_t)rg, s); }));
     CHECK_HIP(timed(c, 1, s, [&] {
@@ -435,7 +451,8 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
             CHECK_HIP(hipStreamSynchronize(s));
             const uint32_t tot = *c->h_total;
             if (tot > cm) return HULLF_EDEVICE;
-            const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((nch + 3) / 4, (uint32_t)c->cus * 8));
+            const int gg = (int)std::max<uint64_t>(
+                1, std::min<uint64_t>(((uint64_t)nch * C + 255) / 256, (uint64_t)c->cus * 16));
             CHECK_HIP(launch_chain_gather(c->fk[cur], c->fv[cur], cm, C, c->fchain, c->fcnt, tot,
                                           c->fk[nxt], c->fv[nxt], gg, s));
             const bool slow = (uint64_t)tot * 4 > (uint64_t)cm * 3;   // little left to gain
@@ -677,6 +694,7 @@ hullf_status hullf_create(int device, size_t workspace_bytes, hullf_ctx_t* out) 
         if (std::sscanf(e, "%d,%d", &sh.block, &sh.ppt) == 2 && shape_supported(sh)) c->filter_shape = sh;
     }
     if (const char* e = std::getenv("HULLF_FINISH")) c->host_finish = std::strcmp(e, "host") == 0;
+    if (const char* e = std::getenv("HULLF_SINGLE_PASS")) c->single_pass = std::atoi(e) != 0;
     if (const char* e = std::getenv("HULLF_CHAIN_CHUNK")) {
         const int v = std::atoi(e);
         if (v >= (int)kChainChunkMin && v <= 64) c->chain_chunk = (uint32_t)v;
@@ -737,7 +755,7 @@ void hullf_destroy(hullf_ctx_t c) {
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt, c->boxes,
-                   c->groups_read, c->poly16, c->part16,
+                   c->groups_read, c->poly16, c->part16, c->lb,
                    c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_boxes, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
