@@ -665,6 +665,31 @@ def bench_batched(ctx, dev):
     same = bool(np.array_equal(cb, cp)) and all(
         np.array_equal(a[offs[s]:offs[s] + int(cb[s])], b[offs[s]:offs[s] + int(cb[s])]) for s in range(S))
     del surv2
+    # hulls of all sets: the graph filter, then every set's hull in one
+    # batched finishing call, against the filter per set followed by
+    # hull_from_survivors per set (host-synchronous both)
+    ctx.hull_filter_batched(tp, to, surv=surv, counts=counts, stream=stream)
+    hulls, hoff = ctx.hulls_batched(tp, to, surv, counts, stream=stream)   # workspace growth
+    hb = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.hull_filter_batched(tp, to, surv=surv, counts=counts, stream=stream)
+        hulls, hoff = ctx.hulls_batched(tp, to, surv, counts, stream=stream)
+        hb.append((time.perf_counter() - t0) * 1e3)
+    hb_ms = float(np.median(hb))
+    surv2 = torch.empty_like(surv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hull_same = True
+    for s in range(S):
+        ctx.hull_filter(views[s], surv=surv2[offs[s]:], count=c1[s:s + 1], cap=offs[s + 1] - offs[s],
+                        stream=stream)
+        k = int(c1[s].item())
+        h = ctx.hull_from_survivors(views[s], surv2[offs[s]:offs[s] + k], k, stream=stream)
+        hull_same = hull_same and bool(np.array_equal(h, hulls[hoff[s]:hoff[s + 1]]))
+    hp_ms = (time.perf_counter() - t0) * 1e3
+    del surv2
     n = int(pts.shape[0])
     return {
         "workload": "4096 sets, sizes log-uniform [1e2, 1e6], kinds uniform, seed 6",
@@ -677,9 +702,20 @@ def bench_batched(ctx, dev):
         "per_set_sets_filtered_per_s": round(S / (p_ms / 1e3), 1),
         "speedup": round(p_ms / b_ms, 2),
         "survivors_match_per_set": same,
-        "note": "filter and compaction only (Algorithm 1 without the hull step); hulls of these sets are "
-                "compared with the oracle in the GPU tests",
+        "hulls": {
+            "batched_ms": round(hb_ms, 2),
+            "hulls_per_s": round(S / (hb_ms / 1e3), 1),
+            "per_set_ms": round(hp_ms, 1),
+            "per_set_hulls_per_s": round(S / (hp_ms / 1e3), 1),
+            "speedup": round(hp_ms / hb_ms, 2),
+            "hull_vertices": int(hulls.size),
+            "hulls_match_per_set": hull_same,
+            "note": "hull_filter_batched + hull_from_survivors_batched against hull_filter + "
+                    "hull_from_survivors per set, host-synchronous; hulls are also compared with the "
+                    "oracle's in the GPU tests",
+        },
     }
+
 
 
 def _pool(count: int, seed: int):

@@ -216,6 +216,24 @@ hullf_status hull_filter_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
                                  uint64_t n_total, uint32_t *d_surv,
                                  uint64_t *d_counts, void *stream);
 
+/* Hull finishing (Sec. 3.3) of every set of a batch at once, synchronous:
+ * the survivors of hull_filter_batched (same d_pts, d_off, S, n_total,
+ * d_surv, d_counts) go through one device sort in which every set is
+ * sorted on its own, then run representatives, chunked monotone chains and
+ * merge rounds that never cross a set; only the sets' hull chains come back
+ * to the host.  Set s's hull (counter-clockwise, set-local indices, the
+ * conventions of convex_hull) goes to h_hull[h_hull_off[s] ..
+ * h_hull_off[s+1]); h_hull_off: S + 1 host words, written also when cap is
+ * too small (then HULLF_ECAPACITY and h_hull untouched).  A set counted
+ * HULLF_COUNT_NONFINITE gives HULLF_ENONFINITE; a count above its set's
+ * size or a survivor index outside its set gives HULLF_EINVAL. */
+hullf_status hull_from_survivors_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
+                                         const uint64_t *d_off, uint32_t S,
+                                         uint64_t n_total, const uint32_t *d_surv,
+                                         const uint64_t *d_counts, uint32_t *h_hull,
+                                         uint64_t cap, uint64_t *h_hull_off,
+                                         void *stream);
+
 /* Same work as hull_filter_batched for sets placed anywhere in d_pts,
  * launched directly (no graph).  d_seg: S (begin, count) pairs of device
  * uint64; set s is d_pts[begin .. begin+count).  Sets must be in ascending

@@ -61,6 +61,20 @@ __device__ __forceinline__ float unord32(uint32_t k) {
 __device__ __forceinline__ float key_x(uint64_t k) { return unord32((uint32_t)(k >> 32)); }
 __device__ __forceinline__ float key_y(uint64_t k) { return unord32((uint32_t)k); }
 
+// Piece k of a batch split: its set s and its items [b, e) (binary search
+// for the set: the largest s with first[s] <= k, which skips empty sets).
+__device__ __forceinline__ void piece_of(const SetSplit& sp, uint32_t k, uint32_t& s, uint32_t& b, uint32_t& e) {
+    uint32_t lo = 0, hi = sp.S - 1u;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1u) / 2u;
+        if (sp.first[mid] <= k) lo = mid;
+        else hi = mid - 1u;
+    }
+    s = lo;
+    b = sp.start[s] + (k - sp.first[s]) * sp.size;
+    e = min(sp.start[s + 1u], b + sp.size);
+}
+
 // ---------------------------------------------------------------------------
 // keys
 // ---------------------------------------------------------------------------
@@ -79,9 +93,35 @@ __global__ __launch_bounds__(256) void k_fin_keys(const float2* __restrict__ pts
     }
 }
 
+// Batched keys.  Block k takes sort tile k of the split (items [b, e) of set
+// s, sp.start = the exclusive prefix of the survivor counts): item i is set
+// s's survivor j = i - sp.start[s], whose set-local index is
+// surv[off[s] + j] and whose point is pts[off[s] + that index].  A local
+// index >= the set's size sets *bad and takes the point (0, 0).
+__global__ __launch_bounds__(256) void k_bfin_keys(const float2* __restrict__ pts, const uint64_t* __restrict__ off,
+                                                   const uint32_t* __restrict__ surv, SetSplit sp,
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                   uint64_t* bad) {
+    uint32_t set, b, e;
+    piece_of(sp, blockIdx.x, set, b, e);
+    const uint64_t o = off[set];
+    const uint64_t ns = off[set + 1] - o;
+    const uint32_t j0 = b - sp.start[set];
+    for (uint32_t i = threadIdx.x; b + i < e; i += 256u) {
+        const uint32_t loc = surv[o + j0 + i];
+        float2 q = make_float2(0.0f, 0.0f);
+        if (loc < ns) q = pts[o + loc];
+        else *bad = 1ull;
+        keys[b + i] = ((uint64_t)ord32(q.x) << 32) | ord32(q.y);
+        vals[b + i] = loc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // radix sort
 // ---------------------------------------------------------------------------
+// Tiles are kRsTile consecutive items, or, for a batch of sets sorted each
+// on its own, the pieces of a split of size kRsTile (never crossing a set).
 // hist[d * tiles + t] = items of tile t with digit d (then, after the two
 // scans, the output position of the first of them).
 
@@ -101,21 +141,28 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
 // round first peels off up to four large groups of lanes with equal digits
 // (one lane adds the group's size); the lanes left add one each.
 __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t m, uint32_t shift,
-                                                      uint32_t tiles, uint32_t* __restrict__ hist) {
+                                                      uint32_t tiles, SetSplit sp, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kRsBins];
     const uint32_t t = threadIdx.x, lane = t & 63u, tile = xcd_tile(blockIdx.x, tiles);
     h[t] = 0u;
     __syncthreads();
-    const uint64_t base = (uint64_t)tile * kRsTile;
+    uint64_t base = (uint64_t)tile * kRsTile;
+    uint32_t nt = (uint32_t)min<uint64_t>(kRsTile, (uint64_t)m - base);
+    if (sp.first) {
+        uint32_t set, b, e;
+        piece_of(sp, tile, set, b, e);
+        base = b;
+        nt = e - b;
+    }
     uint64_t k[kRsItems];
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
-        const uint64_t i = base + (uint32_t)r * kRsBlock + t;
-        k[r] = (i < m) ? keys[i] : 0ull;
+        const uint32_t i = (uint32_t)r * kRsBlock + t;
+        k[r] = (i < nt) ? keys[base + i] : 0ull;
     }
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
-        const bool valid = base + (uint32_t)r * kRsBlock + t < m;
+        const bool valid = (uint32_t)r * kRsBlock + t < nt;
         const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
         unsigned long long rem = __ballot(valid);
         for (int it = 0; it < 4 && rem != 0ull; ++it) {
@@ -152,14 +199,18 @@ __global__ __launch_bounds__(256) void k_rs_rowsum(const uint32_t* __restrict__ 
 // + (items of digit d in earlier tiles).  Each round scans 1024 tiles: four
 // consecutive per thread, a shuffle scan inside each wave, one LDS exchange
 // of the four wave totals.
+//
+// With rowend (tile tables: every set sorted on its own) the row is scanned
+// from 0 instead, and its total goes to rowend[d]; k_rs_setpre then turns
+// the prefixes into positions inside each set.
 __global__ __launch_bounds__(256) void k_rs_rowscan(uint32_t* __restrict__ hist, uint32_t tiles,
-                                                    const uint32_t* __restrict__ rowsum) {
+                                                    const uint32_t* __restrict__ rowsum, uint32_t* rowend) {
     constexpr int NW = 256 / 64;
     __shared__ uint32_t s[256];
     __shared__ uint32_t wsum[NW];
     __shared__ uint32_t carry;
     const uint32_t d = blockIdx.x, t = threadIdx.x, lane = t & 63u, wave = t >> 6;
-    s[t] = (t < d) ? rowsum[t] : 0u;
+    s[t] = (!rowend && t < d) ? rowsum[t] : 0u;
     __syncthreads();
     for (uint32_t o = 128; o > 0; o >>= 1) {
         if (t < o) s[t] += s[t + o];
@@ -202,6 +253,37 @@ __global__ __launch_bounds__(256) void k_rs_rowscan(uint32_t* __restrict__ hist,
         if (t == 0) carry += all;
         __syncthreads();
     }
+    if (rowend && t == 0) rowend[d] = carry;
+}
+
+// Batched sort, block per set s (thread per digit): digit d of set s starts
+// at ipos[s] + (items of s with smaller digits); tile t of s, with row
+// prefix P[d][t] (k_rs_rowscan from 0), puts its first digit-d item at
+// that start + P[d][t] - P[d][first tile of s].  sdp[s][d] receives the
+// start minus P[d][first tile of s], so the scatter adds P[d][t].  ipos
+// and sft: the split's item starts and first tiles.
+__global__ __launch_bounds__(256) void k_rs_setpre(const uint32_t* __restrict__ hist, uint32_t tiles,
+                                                   const uint32_t* __restrict__ rowend, SetSplit sp,
+                                                   uint32_t* __restrict__ sdp) {
+    const uint32_t* __restrict__ sft = sp.first;
+    const uint32_t* __restrict__ ipos = sp.start;
+    __shared__ uint32_t wsum[4];
+    const uint32_t s = blockIdx.x, d = threadIdx.x, lane = d & 63u, wave = d >> 6;
+    const uint32_t t0 = sft[s], t1 = sft[s + 1];
+    auto P = [&](uint32_t t) { return t < tiles ? hist[(uint64_t)d * tiles + t] : rowend[d]; };
+    const uint32_t p0 = (t0 < t1) ? P(t0) : 0u;
+    const uint32_t c = (t0 < t1) ? P(t1) - p0 : 0u;   // items of set s with digit d
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+        if ((int)lane >= o) incl += u;
+    }
+    if (lane == 63u) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w) before += wsum[w];
+    sdp[(uint64_t)s * kRsBins + d] = ipos[s] + before + incl - c - p0;
 }
 
 // Stable scatter of one tile.  Items are ranked in tile order (round r,
@@ -212,7 +294,8 @@ __global__ __launch_bounds__(256) void k_rs_rowscan(uint32_t* __restrict__ hist,
 __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin, uint32_t m,
                                                          uint32_t shift, uint32_t tiles,
-                                                         const uint32_t* __restrict__ hist,
+                                                         const uint32_t* __restrict__ hist, SetSplit sp,
+                                                         const uint32_t* __restrict__ sdp,
                                                          uint64_t* __restrict__ kout,
                                                          uint32_t* __restrict__ vout) {
     // Wave w ranks the tile's items [w*IW, (w+1)*IW) by itself: in each round
@@ -233,11 +316,18 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* __restr
     __shared__ uint32_t gpos[kRsBins];       // output position of the tile's first item per digit
     __shared__ uint32_t wsum[NW];
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6, tile = xcd_tile(blockIdx.x, tiles);
-    const uint64_t base = (uint64_t)tile * kRsTile;
-    const uint32_t nt = (uint32_t)min<uint64_t>(kRsTile, (uint64_t)m - base);
+    uint64_t base = (uint64_t)tile * kRsTile;
+    uint32_t nt = (uint32_t)min<uint64_t>(kRsTile, (uint64_t)m - base);
+    uint32_t set = 0;
+    if (sp.first) {
+        uint32_t b, e;
+        piece_of(sp, tile, set, b, e);
+        base = b;
+        nt = e - b;
+    }
 #pragma unroll
     for (int w = 0; w < NW; ++w) wcnt[w][t] = 0u;
-    gpos[t] = hist[(uint64_t)t * tiles + tile];
+    gpos[t] = hist[(uint64_t)t * tiles + tile] + (sp.first ? sdp[(uint64_t)set * kRsBins + t] : 0u);
     __syncthreads();
     uint64_t k[RW];
     uint32_t v[RW], rk[RW];
@@ -429,17 +519,27 @@ __device__ __forceinline__ uint32_t slot_of(const uint32_t* __restrict__ toff, u
     return w.t * kRunTile + (p - w.tb);
 }
 
+//
+// With a split sp (pieces of C: a batch, chunks never cross a set) chunk c
+// is piece c instead; its chain still goes to out[c*C ...].
 template <uint32_t CMAX>
 __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys, uint32_t m, uint32_t C, int sign,
-                                              const uint32_t* __restrict__ toff, uint32_t ntiles,
-                                              uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
+                                              const uint32_t* __restrict__ toff, uint32_t ntiles, SetSplit sp,
+                                              uint32_t nct, uint32_t* __restrict__ out, uint32_t* __restrict__ cnt) {
     static_assert(CMAX <= kChainMaxC && CMAX <= 256u, "stack offsets are one byte");
     __shared__ uint8_t sh_st[CMAX][64];
     __shared__ float2 sh_xy[CMAX][64];
     const uint32_t c = blockIdx.x * 64u + threadIdx.x;
-    const uint32_t nch = (m + C - 1) / C;
+    const uint32_t nch = sp.first ? nct : (m + C - 1) / C;
     if (c >= nch) return;
-    const uint32_t b = c * C, e = min(m, b + C);
+    uint32_t b, e;
+    if (sp.first) {
+        uint32_t set;
+        piece_of(sp, c, set, b, e);
+    } else {
+        b = c * C;
+        e = min(m, b + C);
+    }
     uint8_t* st = &sh_st[0][threadIdx.x];   // entry j at st[64 * j]: lanes hit distinct banks
     float2* sxy = &sh_xy[0][threadIdx.x];
     TileWalk w0{0u, 0u, 0xFFFFFFFFu};
@@ -489,7 +589,7 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
 #pragma unroll
         for (uint32_t u = 0; u < kChainPrefetch; ++u) kb[u] = kn[u];
     }
-    uint32_t* o = out + (uint64_t)b;
+    uint32_t* o = out + (uint64_t)c * C;
     for (uint32_t j = 0; j < len; ++j) {
         const uint32_t p = b + st[64u * j];
         o[j] = toff ? slot_of(toff, ntiles, m, w0, p) : p;
@@ -598,38 +698,54 @@ __device__ __forceinline__ bool run_step(uint64_t k, uint32_t kv, uint32_t i0, u
     return !(i0 + 64u >= e && !c.own);   // past the tile with no owned run open: done
 }
 
+// With a split sp (pieces of kRunTile) the keys are a batch of sets sorted
+// each on its own: wave w takes the runs that start in its piece, walks at
+// most to its set's end (runs never cross sets), and a piece that starts a
+// set has no run open before it.
 __global__ __launch_bounds__(256) void k_runs(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                                              uint32_t m, int sign, uint64_t* __restrict__ rk,
+                                              uint32_t m, int sign, SetSplit sp, uint64_t* __restrict__ rk,
                                               uint32_t* __restrict__ rv, uint32_t* __restrict__ cnt) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6);
-    const uint32_t nt = (m + kRunTile - 1u) / kRunTile;
+    const uint32_t nt = sp.first ? sp.first[sp.S] : (m + kRunTile - 1u) / kRunTile;
     if (w >= nt) return;   // whole waves only
-    const uint32_t b = w * kRunTile, e = min(m, b + kRunTile);
+    uint32_t b, e, se;
+    bool first;
+    if (sp.first) {
+        uint32_t set;
+        piece_of(sp, w, set, b, e);
+        se = sp.start[set + 1u];
+        first = w == sp.first[set];
+    } else {
+        b = w * kRunTile;
+        e = min(m, b + kRunTile);
+        se = m;
+        first = b == 0u;
+    }
     const uint64_t upto = (2ull << lane) - 1ull;   // this lane and those below (lane 63: all)
     uint64_t kr[kRunSteps];
     uint32_t vr[kRunSteps];
 #pragma unroll
     for (uint32_t u = 0; u < kRunSteps; ++u) {
         const uint32_t i = b + 64u * u + lane;
-        kr[u] = (i < m) ? keys[i] : 0ull;
-        vr[u] = (i < m) ? vals[i] : 0u;
+        kr[u] = (i < se) ? keys[i] : 0ull;
+        vr[u] = (i < se) ? vals[i] : 0u;
     }
     // a run open at b started in the previous tile: not this wave's
-    RunCarry c{b > 0u, false, (b > 0u) ? (uint32_t)(keys[b - 1u] >> 32) : 0u, ~0ull, 0u};
-    uint64_t* ok = rk + (uint64_t)b;
-    uint32_t* ov = rv + (uint64_t)b;
+    RunCarry c{!first, false, first ? 0u : (uint32_t)(keys[b - 1u] >> 32), ~0ull, 0u};
+    uint64_t* ok = rk + (uint64_t)w * kRunTile;   // tile w's slots
+    uint32_t* ov = rv + (uint64_t)w * kRunTile;
     uint32_t len = 0;
     bool more = true;
 #pragma unroll
     for (uint32_t u = 0; u < kRunSteps; ++u) {
-        more = run_step(kr[u], vr[u], b + 64u * u, m, e, sign, lane, upto, c, ok, ov, len);
+        more = run_step(kr[u], vr[u], b + 64u * u, se, e, sign, lane, upto, c, ok, ov, len);
         if (!more) break;
     }
     // past the tile: the owned run still open
     for (uint32_t i0 = b + kRunTile; more; i0 += 64u) {
         const uint32_t i = i0 + lane;
-        more = run_step((i < m) ? keys[i] : 0ull, (i < m) ? vals[i] : 0u, i0, m, e, sign, lane, upto, c, ok, ov,
+        more = run_step((i < se) ? keys[i] : 0ull, (i < se) ? vals[i] : 0u, i0, se, e, sign, lane, upto, c, ok, ov,
                         len);
     }
     if (lane == 0u) cnt[w] = len;
@@ -721,11 +837,10 @@ __global__ __launch_bounds__(1024) void k_scan_apply(uint32_t* __restrict__ a, u
 // One thread per slot of the chain array (chunk chains are short: a wave
 // per chunk left most lanes idle).
 __global__ __launch_bounds__(256) void k_chain_gather(const uint64_t* __restrict__ keys,
-                                                      const uint32_t* __restrict__ vals, uint32_t m, uint32_t C,
+                                                      const uint32_t* __restrict__ vals, uint32_t nch, uint32_t C,
                                                       const uint32_t* __restrict__ chain,
                                                       const uint32_t* __restrict__ off, uint32_t total,
                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-    const uint32_t nch = (m + C - 1) / C;
     const uint32_t slots = nch * C;   // slots + the grid stride < 2^32 (checked at launch)
     for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < slots; i += gridDim.x * 256u) {
         const uint32_t c = i / C, j = i - c * C;
@@ -791,14 +906,31 @@ __device__ __forceinline__ uint32_t tangent_from(const uint64_t* __restrict__ B,
     return lo;
 }
 
+// Pair p merges chains 2p and 2p+1 (if there is one), or, in a batch, the
+// one or two chains of piece p of a split of size 2 over each set's chains:
+// the pairs never cross a set.
+__device__ __forceinline__ void pair_of(const SetSplit& sp, uint32_t nc, uint32_t p, uint32_t& left, bool& right) {
+    if (sp.first) {
+        uint32_t set, e;
+        piece_of(sp, p, set, left, e);
+        right = e - left == 2u;
+    } else {
+        left = 2u * p;
+        right = 2u * p + 1u < nc;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_bridge(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ off,
-                                                uint32_t nc, int sign, uint2* __restrict__ br,
-                                                uint32_t* __restrict__ len) {
+                                                uint32_t nc, int sign, SetSplit sp, uint32_t np_tab,
+                                                uint2* __restrict__ br, uint32_t* __restrict__ len) {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t np = (nc + 1u) / 2u;
+    const uint32_t np = sp.first ? np_tab : (nc + 1u) / 2u;
     for (uint32_t p = blockIdx.x * 4u + (threadIdx.x >> 6); p < np; p += gridDim.x * 4u) {
-        const uint32_t a0 = off[2u * p], a1 = off[2u * p + 1u];
-        const uint32_t b1 = (2u * p + 1u < nc) ? off[2u * p + 2u] : a1;
+        uint32_t left;
+        bool right;
+        pair_of(sp, nc, p, left, right);
+        const uint32_t a0 = off[left], a1 = off[left + 1u];
+        const uint32_t b1 = right ? off[left + 2u] : a1;
         const uint32_t la = a1 - a0, lb = b1 - a1;
         uint32_t keep = la, j = 0;   // A[0..keep) ++ B[j..lb)
         if (la > 0u && lb > 0u) {
@@ -829,15 +961,18 @@ __global__ __launch_bounds__(256) void k_bridge(const uint64_t* __restrict__ key
 __global__ __launch_bounds__(256) void k_merge_gather(const uint64_t* __restrict__ keys,
                                                       const uint32_t* __restrict__ vals,
                                                       const uint32_t* __restrict__ off, uint32_t nc,
-                                                      const uint2* __restrict__ br,
+                                                      SetSplit sp, uint32_t np_tab, const uint2* __restrict__ br,
                                                       const uint32_t* __restrict__ noff, uint32_t bpp,
                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-    const uint32_t np = (nc + 1u) / 2u;
+    const uint32_t np = sp.first ? np_tab : (nc + 1u) / 2u;
     const uint64_t tasks = (uint64_t)np * bpp;
     for (uint64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
         const uint32_t p = (uint32_t)(task / bpp), c = (uint32_t)(task % bpp);
-        const uint32_t a0 = off[2u * p], a1 = off[2u * p + 1u];
-        const uint32_t b1 = (2u * p + 1u < nc) ? off[2u * p + 2u] : a1;
+        uint32_t left;
+        bool right;
+        pair_of(sp, nc, p, left, right);
+        const uint32_t a0 = off[left], a1 = off[left + 1u];
+        const uint32_t b1 = right ? off[left + 2u] : a1;
         const uint2 r = br[p];
         const uint32_t o = noff[p];
         const uint32_t len = r.x + ((b1 - a1) - r.y);
@@ -851,6 +986,12 @@ __global__ __launch_bounds__(256) void k_merge_gather(const uint64_t* __restrict
 }
 
 __global__ void k_copy_u32(uint32_t* dst, const uint32_t* src) { *dst = *src; }
+
+// dst[i] = src[idx[i]] for i < n.
+__global__ __launch_bounds__(256) void k_take_u32(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx,
+                                                  uint32_t n, uint32_t* __restrict__ dst) {
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) dst[i] = src[idx[i]];
+}
 
 }  // namespace
 
@@ -874,11 +1015,11 @@ hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, u
     uint64_t* kb = keys2;
     uint32_t* vb = vals2;
     for (uint32_t shift = first_shift; shift < 64; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(kRsBlock), 0, stream, ka, m, shift, tiles, hist);
+        hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(kRsBlock), 0, stream, ka, m, shift, tiles, SetSplit{}, hist);
         hipLaunchKernelGGL(k_rs_rowsum, dim3(kRsBins), dim3(256), 0, stream, hist, tiles, rowsum);
-        hipLaunchKernelGGL(k_rs_rowscan, dim3(kRsBins), dim3(256), 0, stream, hist, tiles, rowsum);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(kRsBlock), 0, stream, ka, va, m, shift, tiles, hist, kb,
-                           vb);
+        hipLaunchKernelGGL(k_rs_rowscan, dim3(kRsBins), dim3(256), 0, stream, hist, tiles, rowsum, nullptr);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(kRsBlock), 0, stream, ka, va, m, shift, tiles, hist,
+                           SetSplit{}, nullptr, kb, vb);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         std::swap(ka, kb);
@@ -887,24 +1028,58 @@ hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, u
     return hipSuccess;   // an even number of passes: the result is back in keys / vals
 }
 
+hipError_t launch_finish_sort_sets(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
+                                   const SetSplit& sp, uint32_t tiles, uint32_t* hist, uint32_t* rowend, uint32_t* sdp,
+                                   hipStream_t stream) {
+    if (tiles == 0u) return hipSuccess;
+    if (sp.first == nullptr || sp.size != kRsTile) return hipErrorInvalidValue;
+    uint64_t* ka = keys;
+    uint32_t* va = vals;
+    uint64_t* kb = keys2;
+    uint32_t* vb = vals2;
+    for (uint32_t shift = 32; shift < 64; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(kRsBlock), 0, stream, ka, m, shift, tiles, sp, hist);
+        hipLaunchKernelGGL(k_rs_rowscan, dim3(kRsBins), dim3(256), 0, stream, hist, tiles, nullptr, rowend);
+        hipLaunchKernelGGL(k_rs_setpre, dim3(sp.S), dim3(kRsBins), 0, stream, hist, tiles, rowend, sp, sdp);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(kRsBlock), 0, stream, ka, va, m, shift, tiles, hist, sp,
+                           sdp, kb, vb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    return hipSuccess;   // four passes: the result is back in keys / vals
+}
+
+hipError_t launch_bfin_keys(const float2* pts, const uint64_t* off, const uint32_t* surv, const SetSplit& sp,
+                            uint32_t tiles, uint64_t* keys, uint32_t* vals, uint64_t* bad, hipStream_t stream) {
+    if (tiles == 0u) return hipSuccess;
+    hipLaunchKernelGGL(k_bfin_keys, dim3(tiles), dim3(256), 0, stream, pts, off, surv, sp, keys, vals, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, const uint32_t* toff,
-                        uint32_t ntiles, uint32_t* chain, uint32_t* cnt, hipStream_t stream) {
-    if (C == 0 || C > kChainMaxC || (toff && ntiles == 0)) return hipErrorInvalidValue;
-    const uint32_t nch = (m + C - 1) / C;
+                        uint32_t ntiles, uint32_t* chain, uint32_t* cnt, hipStream_t stream, const SetSplit& sp,
+                        uint32_t nsp) {
+    if (C == 0 || C > kChainMaxC || (toff && ntiles == 0) || (sp.first && sp.size != C))
+        return hipErrorInvalidValue;
+    const uint32_t nch = sp.first ? nsp : (m + C - 1) / C;
     if (nch == 0) return hipSuccess;
     const dim3 grid((nch + 63) / 64);
     if (C <= 32u)
-        hipLaunchKernelGGL(k_chain<32>, grid, dim3(64), 0, stream, keys, m, C, sign, toff, ntiles, chain, cnt);
+        hipLaunchKernelGGL(k_chain<32>, grid, dim3(64), 0, stream, keys, m, C, sign, toff, ntiles, sp, nsp, chain,
+                           cnt);
     else
-        hipLaunchKernelGGL(k_chain<64>, grid, dim3(64), 0, stream, keys, m, C, sign, toff, ntiles, chain, cnt);
+        hipLaunchKernelGGL(k_chain<64>, grid, dim3(64), 0, stream, keys, m, C, sign, toff, ntiles, sp, nsp, chain,
+                           cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_runs(const uint64_t* keys, const uint32_t* vals, uint32_t m, int sign, uint64_t* rk, uint32_t* rv,
-                       uint32_t* cnt, hipStream_t stream) {
-    const uint32_t nt = (m + kRunTile - 1u) / kRunTile;
+                       uint32_t* cnt, hipStream_t stream, const SetSplit& sp, uint32_t nsp) {
+    const uint32_t nt = sp.first ? nsp : (m + kRunTile - 1u) / kRunTile;
     if (nt == 0u) return hipSuccess;
-    hipLaunchKernelGGL(k_runs, dim3((nt + 3u) / 4u), dim3(256), 0, stream, keys, vals, m, sign, rk, rv, cnt);
+    hipLaunchKernelGGL(k_runs, dim3((nt + 3u) / 4u), dim3(256), 0, stream, keys, vals, m, sign, sp, rk, rv, cnt);
     return hipGetLastError();
 }
 
@@ -920,13 +1095,14 @@ hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, uint32
     return hipGetLastError();
 }
 
-hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint32_t m, uint32_t C,
+hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint32_t nch, uint32_t C,
                                const uint32_t* chain, const uint32_t* off, uint32_t total, uint64_t* kout,
                                uint32_t* vout, int grid, hipStream_t stream) {
     // slot indices and the grid stride stay below 2^32
-    if (C == 0 || grid <= 0 || (uint64_t)((m + C - 1) / C) * C + (uint64_t)grid * 256u >= (1ull << 32))
+    if (C == 0 || grid <= 0 || (uint64_t)nch * C + (uint64_t)grid * 256u >= (1ull << 32))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chain_gather, dim3(grid), dim3(256), 0, stream, keys, vals, m, C, chain, off, total, kout,
+    if (nch == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chain_gather, dim3(grid), dim3(256), 0, stream, keys, vals, nch, C, chain, off, total, kout,
                        vout);
     return hipGetLastError();
 }
@@ -936,21 +1112,31 @@ hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, hipStream_t strea
     return hipGetLastError();
 }
 
+hipError_t launch_take_u32(const uint32_t* src, const uint32_t* idx, uint32_t n, uint32_t* dst, hipStream_t stream) {
+    if (n == 0u) return hipSuccess;
+    const uint32_t grid = std::min<uint32_t>((n + 255u) / 256u, 1024u);
+    hipLaunchKernelGGL(k_take_u32, dim3(grid), dim3(256), 0, stream, src, idx, n, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_bridge(const uint64_t* keys, const uint32_t* off, uint32_t nc, int sign, uint2* br, uint32_t* len,
-                         int grid, hipStream_t stream) {
-    hipLaunchKernelGGL(k_bridge, dim3(grid), dim3(256), 0, stream, keys, off, nc, sign, br, len);
+                         int grid, hipStream_t stream, const SetSplit& sp, uint32_t nsp) {
+    if (sp.first && sp.size != 2u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bridge, dim3(grid), dim3(256), 0, stream, keys, off, nc, sign, sp, nsp, br, len);
     return hipGetLastError();
 }
 
 hipError_t launch_merge_gather(const uint64_t* keys, const uint32_t* vals, const uint32_t* off, uint32_t nc,
                                const uint2* br, const uint32_t* noff, uint64_t* kout, uint32_t* vout, int grid,
-                               hipStream_t stream) {
-    const uint32_t np = (nc + 1u) / 2u;
+                               hipStream_t stream, const SetSplit& sp, uint32_t nsp) {
+    if (sp.first && sp.size != 2u) return hipErrorInvalidValue;
+    const uint32_t np = sp.first ? nsp : (nc + 1u) / 2u;
+    if (np == 0u) return hipSuccess;
     const uint32_t bpp = std::max<uint32_t>(1u, (uint32_t)grid / std::max<uint32_t>(np, 1u));
     const uint64_t tasks = (uint64_t)np * bpp;
     const int g = (int)std::min<uint64_t>(tasks, (uint64_t)std::max(grid, 1));
-    hipLaunchKernelGGL(k_merge_gather, dim3(g), dim3(256), 0, stream, keys, vals, off, nc, br, noff, bpp, kout,
-                       vout);
+    hipLaunchKernelGGL(k_merge_gather, dim3(g), dim3(256), 0, stream, keys, vals, off, nc, sp, nsp, br, noff, bpp,
+                       kout, vout);
     return hipGetLastError();
 }
 

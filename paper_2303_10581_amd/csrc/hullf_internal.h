@@ -179,35 +179,67 @@ hipError_t launch_finish_keys(const float2* pts, uint64_t n, const uint32_t* sur
 // whole key; 32: x alone); first_shift must leave an even number of passes.
 hipError_t launch_finish_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
                               uint32_t* hist, uint32_t* rowsum, uint32_t first_shift, hipStream_t stream);
+// A batch of sets cut into pieces (sort tiles, run tiles, chain chunks,
+// merge pairs): set s's items [start[s], start[s+1]) in pieces of `size`;
+// piece k belongs to the set s with first[s] <= k < first[s+1] (first and
+// start: S + 1 words, first[S] the number of pieces).  first == nullptr:
+// not a batch.
+struct SetSplit {
+    const uint32_t* first = nullptr;
+    const uint32_t* start = nullptr;
+    uint32_t S = 0;
+    uint32_t size = 0;
+};
+// A batch of sets, items of set s at [sp.start[s], sp.start[s+1]) (m in
+// all), sort tiles = pieces of kRsTile.  launch_bfin_keys writes the keys
+// and set-local indices of every set's survivors (off: S + 1 point offsets;
+// surv: set s's survivors at surv + off[s]; `tiles` pieces);
+// launch_finish_sort_sets sorts each set's items by x alone (stable, 4
+// passes), in place.  Scratch: hist 256 * tiles words, rowend 256, sdp
+// 256 * S.
+hipError_t launch_bfin_keys(const float2* pts, const uint64_t* off, const uint32_t* surv, const SetSplit& sp,
+                            uint32_t tiles, uint64_t* keys, uint32_t* vals, uint64_t* bad, hipStream_t stream);
+hipError_t launch_finish_sort_sets(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
+                                   const SetSplit& sp, uint32_t tiles, uint32_t* hist, uint32_t* rowend, uint32_t* sdp,
+                                   hipStream_t stream);
 // Run representatives of keys sorted by x alone (see k_runs): their keys
-// and values into rk / rv (m entries each; tile t's at t*kRunTile, cnt[t]
-// of them), counts per tile into cnt (ceil(m / kRunTile) words).
+// and values into rk / rv (tile t's at t*kRunTile, cnt[t] of them), counts
+// per tile into cnt: ceil(m / kRunTile) tiles, or with a split sp (pieces
+// of kRunTile, a batch) its nsp pieces.
 constexpr uint32_t kRunTile = 1024;
 hipError_t launch_runs(const uint64_t* keys, const uint32_t* vals, uint32_t m, int sign, uint64_t* rk, uint32_t* rv,
-                       uint32_t* cnt, hipStream_t stream);
-// Chains of chunks of C sorted points (C at most 64): chain holds m words
-// (chunk c's chain at c*C), cnt ceil(m/C) words.  With toff (the exclusive
-// scan of the run pass's ntiles tile counts, m their total) the points are
-// the run pass's output packed together and the chain entries are its
-// slots.  sign 1 = lower, -1 = upper.
+                       uint32_t* cnt, hipStream_t stream, const SetSplit& sp = SetSplit{}, uint32_t nsp = 0);
+// Chains of chunks of C sorted points (C at most 64): chain holds a slot
+// per point (chunk c's chain at c*C), cnt one word per chunk: ceil(m/C)
+// chunks, or with a split sp (pieces of C, never crossing a set) its nsp
+// pieces.  With toff (the exclusive scan of the run pass's ntiles tile
+// counts, m their total) the points are the run pass's output packed
+// together and the chain entries are its slots.  sign 1 = lower, -1 =
+// upper.
 hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, const uint32_t* toff,
-                        uint32_t ntiles, uint32_t* chain, uint32_t* cnt, hipStream_t stream);
+                        uint32_t ntiles, uint32_t* chain, uint32_t* cnt, hipStream_t stream,
+                        const SetSplit& sp = SetSplit{}, uint32_t nsp = 0);
 // Exclusive scan of n counts in place, the total to *total; blk (at least
 // ceil(n / 4096) words, or null for one block) holds partial sums.
 hipError_t launch_scan_counts(uint32_t* cnt, uint32_t n, uint32_t* total, uint32_t* blk, hipStream_t stream);
 // Merge tree over chains c < nc at [off[c], off[c+1]) (off holds nc + 1
-// words): pair p = chains 2p, 2p+1 (the last one alone when nc is odd).
-// launch_bridge writes br[p] = (points kept of the left chain, first point
-// kept of the right one) and len[p] = the merged length; after an exclusive
-// scan of len into noff (np + 1 words, the total last), launch_merge_gather
-// writes the merged chains.
+// words): pair p = chains 2p, 2p+1 (the last one alone when nc is odd), or
+// with a split sp of size 2 over each set's chains (a batch) its nsp
+// pieces.  launch_bridge writes br[p] = (points kept of the left chain,
+// first point kept of the right one) and len[p] = the merged length; after
+// an exclusive scan of len into noff (np + 1 words, the total last),
+// launch_merge_gather writes the merged chains.
 hipError_t launch_bridge(const uint64_t* keys, const uint32_t* off, uint32_t nc, int sign, uint2* br, uint32_t* len,
-                         int grid, hipStream_t stream);
+                         int grid, hipStream_t stream, const SetSplit& sp = SetSplit{}, uint32_t nsp = 0);
 hipError_t launch_merge_gather(const uint64_t* keys, const uint32_t* vals, const uint32_t* off, uint32_t nc,
                                const uint2* br, const uint32_t* noff, uint64_t* kout, uint32_t* vout, int grid,
-                               hipStream_t stream);
+                               hipStream_t stream, const SetSplit& sp = SetSplit{}, uint32_t nsp = 0);
 hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, hipStream_t stream);
-hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint32_t m, uint32_t C,
+// dst[i] = src[idx[i]], i < n.
+hipError_t launch_take_u32(const uint32_t* src, const uint32_t* idx, uint32_t n, uint32_t* dst, hipStream_t stream);
+// The chain vertices of nch chunks (chunk c's at chain[c*C ...], off: the
+// exclusive scan of their lengths, total last) packed in order.
+hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint32_t nch, uint32_t C,
                                const uint32_t* chain, const uint32_t* off, uint32_t total, uint64_t* kout,
                                uint32_t* vout, int grid, hipStream_t stream);
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -12,6 +13,7 @@
 #include <string>
 #include <sys/stat.h>
 #include <unistd.h>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -77,6 +79,8 @@ struct hullf_ctx {
     uint32_t* fchain = nullptr;
     uint32_t* fcnt = nullptr;
     uint32_t* fblk = nullptr;
+    uint32_t* bws = nullptr;               // batched finishing: split arrays and set digit prefixes
+    uint64_t bws_cap = 0;
     uint32_t* fhist = nullptr;
     uint32_t* frow = nullptr;     // 256 row sums + 1 total
     uint64_t f_cap = 0;           // entries of fk/fv/fchain
@@ -85,6 +89,10 @@ struct hullf_ctx {
     uint32_t* h_fv = nullptr;
     uint64_t h_f_cap = 0;
     uint64_t h_fv_cap = 0;
+    uint64_t* h_bk[2] = {nullptr, nullptr};   // batched finishing: each side's chains
+    uint32_t* h_bv[2] = {nullptr, nullptr};
+    uint64_t h_bk_cap[2] = {0, 0};
+    uint64_t h_bv_cap[2] = {0, 0};
     uint32_t* h_total = nullptr;
     Shape filter_shape{512, 16};
     bool host_finish = false;              // hull finishing always on the host
@@ -356,6 +364,8 @@ hullf_status enqueue_filter16(hullf_ctx* c, const hullf_pt* d_pts, uint64_t n, u
 }
 
 constexpr uint32_t kChainChunkMin = 16;        // least sorted points per chain thread
+constexpr uint32_t kChainMaxChunk = 64;        // most sorted points per chain thread
+constexpr uint32_t kRsTileItems = 4096;        // items per radix-sort tile
 constexpr uint64_t kDeviceFinishMin = 1u << 14;   // survivors from which the device sorts and chains
 constexpr uint32_t kLevelStop = 1u << 16;         // chunk levels stop at this many candidates
 
@@ -453,7 +463,7 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
             if (tot > cm) return HULLF_EDEVICE;
             const int gg = (int)std::max<uint64_t>(
                 1, std::min<uint64_t>(((uint64_t)nch * C + 255) / 256, (uint64_t)c->cus * 16));
-            CHECK_HIP(launch_chain_gather(c->fk[cur], c->fv[cur], cm, C, c->fchain, c->fcnt, tot,
+            CHECK_HIP(launch_chain_gather(c->fk[cur], c->fv[cur], nch, C, c->fchain, c->fcnt, tot,
                                           c->fk[nxt], c->fv[nxt], gg, s));
             const bool slow = (uint64_t)tot * 4 > (uint64_t)cm * 3;   // little left to gain
             cur = nxt;
@@ -501,6 +511,241 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
     lists[0].push_back(lists[1].back());
     lists[1].insert(lists[1].begin(), lists[0].front());
     chain_sorted(lists[0], lists[1], out);
+    return HULLF_OK;
+}
+
+// Hulls of every set of a batch from its survivors (hull_filter_batched's
+// layout: set s = pts[off[s] .. off[s+1]), its counts[s] survivors as
+// set-local indices at surv + off[s]), all sets at once: one sort in which
+// every set is sorted on its own (tiles never cross a set), then the run
+// pass, chunk levels and merge rounds of finish_on_device over splits of
+// every set (pieces never cross a set; each kernel finds a piece's set by
+// binary search in S + 1 words).  hull: the sets' hulls one after another
+// (set-local indices), hoff: S + 1 offsets into it.
+hullf_status finish_batch(hullf_ctx* c, const float2* pts, const uint64_t* d_off, uint32_t S, uint64_t n_total,
+                          const uint32_t* d_surv, const uint64_t* d_counts, uint32_t* h_hull, uint64_t cap,
+                          uint64_t* hoff, hipStream_t s) {
+    std::fill(hoff, hoff + (size_t)S + 1, 0ull);
+    std::vector<uint64_t> off((size_t)S + 1), cnt(S);
+    CHECK_HIP(hipMemcpyAsync(off.data(), d_off, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipMemcpyAsync(cnt.data(), d_counts, cnt.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    if (off[0] != 0 || off[S] > n_total) return HULLF_EINVAL;
+    const uint32_t S1 = S + 1;
+    std::vector<uint32_t> ipos(S1), sft(S1), rft(S1);
+    uint64_t M = 0, T1 = 0, NRT = 0;
+    for (uint32_t k = 0; k < S; ++k) {
+        if (off[k + 1] < off[k]) return HULLF_EINVAL;
+        if (cnt[k] == kCountNonFinite) return HULLF_ENONFINITE;
+        if (cnt[k] > off[k + 1] - off[k]) return HULLF_EINVAL;   // also the other error codes
+        ipos[k] = (uint32_t)M;
+        sft[k] = (uint32_t)T1;
+        rft[k] = (uint32_t)NRT;
+        M += cnt[k];
+        T1 += (cnt[k] + kRsTileItems - 1) / kRsTileItems;
+        NRT += (cnt[k] + kRunTile - 1) / kRunTile;
+    }
+    ipos[S] = (uint32_t)M;
+    sft[S] = (uint32_t)T1;
+    rft[S] = (uint32_t)NRT;
+    if (M == 0) return HULLF_OK;
+    const uint64_t need = std::max<uint64_t>(M + (uint64_t)S * kChainMaxChunk, NRT * kRunTile);
+    if (need + need / 8 + 4096 >= (1ull << 32)) return HULLF_EINVAL;
+    CHECK_HIP(ensure_finish(c, need, s));
+    CHECK_HIP(grow_device(c, &c->fhist, &c->fhist_cap, 256ull * std::max<uint64_t>(T1, 1), s));
+    // split arrays: ipos, sft, rft, level ranges, level first chunks, take
+    // indices, take results, set digit prefixes, then the merge rounds'
+    // (first, start) pairs
+    constexpr uint32_t kMaxRounds = 34;
+    const uint64_t words = 7ull * S1 + 256ull * S + 2ull * kMaxRounds * S1;
+    CHECK_HIP(grow_device(c, &c->bws, &c->bws_cap, words, s));
+    uint32_t* const d_ipos = c->bws;
+    uint32_t* const d_sft = d_ipos + S1;
+    uint32_t* const d_rft = d_sft + S1;
+    uint32_t* const d_rng = d_rft + S1;
+    uint32_t* const d_fcs = d_rng + S1;
+    uint32_t* const d_tix = d_fcs + S1;
+    uint32_t* const d_tout = d_tix + S1;
+    uint32_t* const d_sdp = d_tout + S1;
+    uint32_t* const d_rounds = d_sdp + 256ull * S;
+    CHECK_HIP(hipMemcpyAsync(d_ipos, ipos.data(), S1 * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    CHECK_HIP(hipMemcpyAsync(d_sft, sft.data(), S1 * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    CHECK_HIP(hipMemcpyAsync(d_rft, rft.data(), S1 * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    const uint32_t mm = (uint32_t)M;
+    uint64_t* bad = reinterpret_cast<uint64_t*>(c->frow + 258);
+    CHECK_HIP(launch_write_count(bad, 0, s));
+    const SetSplit sp_sort{d_sft, d_ipos, S, kRsTileItems};
+    CHECK_HIP(launch_bfin_keys(pts, d_off, d_surv, sp_sort, (uint32_t)T1, c->fk[0], c->fv[0], bad, s));
+    CHECK_HIP(hipMemcpyAsync(c->h_count, bad, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    if (*c->h_count != 0) return HULLF_EINVAL;
+    CHECK_HIP(launch_finish_sort_sets(c->fk[0], c->fv[0], c->fk[1], c->fv[1], mm, sp_sort, (uint32_t)T1, c->fhist,
+                                      c->frow, d_sdp, s));
+    // S + 1 words of src at the host indices idx (through d_tix / d_tout)
+    std::vector<uint32_t> took(S1);
+    auto take = [&](const uint32_t* src, const uint32_t* d_idx) -> hipError_t {
+        hipError_t e = launch_take_u32(src, d_idx, S1, d_tout, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(took.data(), d_tout, S1 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e;
+    };
+    std::vector<uint32_t> soff[2];   // per side: each set's chain in the side's host arrays
+    uint32_t* const off_b = c->fchain + c->f_cap / 2;   // second offset array of the merge rounds
+    uint2* const br = reinterpret_cast<uint2*>(c->fchain);
+    uint32_t* const tcnt = c->fcnt + c->f_cap / kChainChunkMin + 2;
+    const uint32_t C = c->chain_chunk;
+    std::vector<uint32_t> rng(S1), fcs(S1), rounds;
+    for (int side = 0; side < 2; ++side) {
+        const int sign = side == 0 ? 1 : -1;
+        // run representatives per run tile, then each set's range of them
+        const SetSplit sp_run{d_rft, d_ipos, S, kRunTile};
+        CHECK_HIP(launch_runs(c->fk[0], c->fv[0], mm, sign, c->fk[1], c->fv[1], tcnt, s, sp_run, (uint32_t)NRT));
+        CHECK_HIP(launch_scan_counts(tcnt, (uint32_t)NRT, c->frow + 256, c->fblk, s));
+        CHECK_HIP(launch_copy_u32(tcnt + NRT, c->frow + 256, s));   // toff[NRT] = the total
+        CHECK_HIP(take(tcnt, d_rft));
+        rng = took;
+        if (rng[S] == 0 || rng[S] > mm) return HULLF_EDEVICE;
+        // chunk levels
+        const uint32_t* toff = tcnt;
+        int cur = 1;
+        uint32_t cm = rng[S], nc = 0;
+        for (;;) {
+            const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
+            uint64_t nct = 0;
+            for (uint32_t k = 0; k < S; ++k) {
+                fcs[k] = (uint32_t)nct;
+                nct += (rng[k + 1] - rng[k] + C - 1) / C;
+            }
+            fcs[S] = (uint32_t)nct;
+            CHECK_HIP(hipMemcpyAsync(d_rng, rng.data(), S1 * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+            CHECK_HIP(hipMemcpyAsync(d_fcs, fcs.data(), S1 * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+            const SetSplit sp_chunk{d_fcs, d_rng, S, C};
+            CHECK_HIP(launch_chain(c->fk[cur], cm, C, sign, toff, toff ? (uint32_t)NRT : 0u, c->fchain, c->fcnt, s,
+                                   sp_chunk, (uint32_t)nct));
+            CHECK_HIP(launch_scan_counts(c->fcnt, (uint32_t)nct, c->frow + 256, c->fblk, s));
+            CHECK_HIP(launch_copy_u32(c->fcnt + nct, c->frow + 256, s));
+            CHECK_HIP(take(c->fcnt, d_fcs));   // each set's first chain vertex
+            const uint32_t tot = took[S];
+            if (tot > cm) return HULLF_EDEVICE;
+            const int gg = (int)std::max<uint64_t>(1, std::min<uint64_t>((nct * C + 255) / 256, (uint64_t)c->cus * 16));
+            CHECK_HIP(launch_chain_gather(c->fk[cur], c->fv[cur], (uint32_t)nct, C, c->fchain, c->fcnt, tot,
+                                          c->fk[nxt], c->fv[nxt], gg, s));
+            const bool slow = (uint64_t)tot * 4 > (uint64_t)cm * 3;
+            cur = nxt;
+            cm = tot;
+            nc = (uint32_t)nct;
+            toff = nullptr;
+            rng = took;
+            if (slow || cm <= kLevelStop) break;
+        }
+        // merge rounds inside each set: its chains [fcs[k], fcs[k+1]) of
+        // the last level, pairwise, until one per set; every round's split
+        // (pairs per set, each set's first chain) is known on the host
+        std::vector<uint32_t> kch(S), cs(fcs.begin(), fcs.end());
+        uint32_t maxk = 0;
+        for (uint32_t k = 0; k < S; ++k) {
+            kch[k] = fcs[k + 1] - fcs[k];
+            maxk = std::max(maxk, kch[k]);
+        }
+        rounds.clear();
+        uint32_t nr = 0;
+        std::vector<uint32_t> nps;
+        while (maxk > 1) {
+            if (nr == kMaxRounds) return HULLF_EDEVICE;
+            std::vector<uint32_t> pps(S1);
+            uint64_t np = 0;
+            maxk = 0;
+            for (uint32_t k = 0; k < S; ++k) {
+                pps[k] = (uint32_t)np;
+                np += (kch[k] + 1) / 2;
+                kch[k] = (kch[k] + 1) / 2;
+                maxk = std::max(maxk, kch[k]);
+            }
+            pps[S] = (uint32_t)np;
+            rounds.insert(rounds.end(), pps.begin(), pps.end());   // the round's first pairs
+            rounds.insert(rounds.end(), cs.begin(), cs.end());     // and its first chains
+            nps.push_back((uint32_t)np);
+            cs = pps;
+            ++nr;
+        }
+        if (nr) CHECK_HIP(hipMemcpyAsync(d_rounds, rounds.data(), rounds.size() * sizeof(uint32_t),
+                                         hipMemcpyHostToDevice, s));
+        CHECK_HIP(launch_copy_u32(c->fcnt + nc, c->frow + 256, s));   // off[nc] = total
+        uint32_t* off_in = c->fcnt;
+        uint32_t* off_out = off_b;
+        uint32_t ncur = nc;
+        for (uint32_t r = 0; r < nr; ++r) {
+            const uint32_t np = nps[r];
+            const int nxt = (cur == 1) ? 2 : 1;
+            const SetSplit sp_pair{d_rounds + 2ull * r * S1, d_rounds + 2ull * r * S1 + S1, S, 2u};
+            const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((np + 3) / 4, (uint32_t)c->cus * 8));
+            CHECK_HIP(launch_bridge(c->fk[cur], off_in, ncur, sign, br, off_out, gg, s, sp_pair, np));
+            CHECK_HIP(launch_scan_counts(off_out, np, off_out + np, c->fblk, s));
+            CHECK_HIP(launch_merge_gather(c->fk[cur], c->fv[cur], off_in, ncur, br, off_out, c->fk[nxt], c->fv[nxt],
+                                          c->cus * 4, s, sp_pair, np));
+            std::swap(off_in, off_out);
+            cur = nxt;
+            ncur = np;
+        }
+        // each set's chain (none for a set without survivors)
+        CHECK_HIP(hipMemcpyAsync(d_tix, cs.data(), S1 * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        CHECK_HIP(take(off_in, d_tix));
+        const uint32_t total = took[S];
+        if (total > mm) return HULLF_EDEVICE;
+        CHECK_HIP(grow_host(&c->h_bk[side], &c->h_bk_cap[side], total));
+        CHECK_HIP(grow_host(&c->h_bv[side], &c->h_bv_cap[side], total));
+        CHECK_HIP(hipMemcpyAsync(c->h_bk[side], c->fk[cur], (uint64_t)total * sizeof(uint64_t),
+                                 hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipMemcpyAsync(c->h_bv[side], c->fv[cur], (uint64_t)total * sizeof(uint32_t),
+                                 hipMemcpyDeviceToHost, s));
+        soff[side] = took;
+    }
+    CHECK_HIP(hipStreamSynchronize(s));
+    // per set, on a pool of host threads: the two chain ends the run
+    // representatives leave out, then the join; sets in blocks of 16
+    std::vector<std::vector<uint32_t>> outs(S);
+    std::atomic<uint32_t> next{0};
+    std::atomic<bool> bad_chain{false};
+    auto work = [&] {
+        std::vector<HostPt> lo, up;
+        for (;;) {
+            const uint32_t k0 = next.fetch_add(16);
+            if (k0 >= S) break;
+            for (uint32_t k = k0; k < std::min(S, k0 + 16); ++k) {
+                if (cnt[k] == 0) continue;
+                lo.clear();
+                up.clear();
+                for (int side = 0; side < 2; ++side) {
+                    std::vector<HostPt>& L = side == 0 ? lo : up;
+                    const uint64_t* hk = c->h_bk[side];
+                    const uint32_t* hv = c->h_bv[side];
+                    for (uint32_t q = soff[side][k]; q < soff[side][k + 1]; ++q)
+                        L.push_back(HostPt{unord_host((uint32_t)(hk[q] >> 32)), unord_host((uint32_t)hk[q]), hv[q]});
+                }
+                if (lo.empty() || up.empty()) {
+                    bad_chain = true;
+                    continue;
+                }
+                lo.push_back(up.back());
+                up.insert(up.begin(), lo.front());
+                chain_sorted(lo, up, outs[k]);
+            }
+        }
+    };
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (std::thread& t : pool) t.join();
+    if (bad_chain) return HULLF_EDEVICE;
+    uint64_t total = 0;
+    for (uint32_t k = 0; k < S; ++k) {
+        hoff[k] = total;
+        total += outs[k].size();
+    }
+    hoff[S] = total;
+    if (total > cap) return HULLF_ECAPACITY;
+    for (uint32_t k = 0; k < S; ++k) std::copy(outs[k].begin(), outs[k].end(), h_hull + hoff[k]);
     return HULLF_OK;
 }
 
@@ -755,7 +1000,7 @@ void hullf_destroy(hullf_ctx_t c) {
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     void* dev[] = {c->oct, c->part, c->count, c->surv, c->gather, c->bits, c->blkcnt, c->boxes,
-                   c->groups_read, c->poly16, c->part16, c->lb,
+                   c->groups_read, c->poly16, c->part16, c->lb, c->bws,
                    c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_boxes, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -763,7 +1008,8 @@ void hullf_destroy(hullf_ctx_t c) {
                    c->fv[2], c->fchain, c->fcnt,  c->fblk,  c->fhist, c->frow};
     for (void* p : fin)
         if (p) (void)hipFree(p);
-    void* host[] = {c->h_surv, c->h_xy, c->h_count, c->h_oct, c->h_fk, c->h_fv, c->h_total, c->h_poly16};
+    void* host[] = {c->h_surv, c->h_xy,   c->h_count, c->h_oct,  c->h_fk,   c->h_fv,
+                    c->h_total, c->h_poly16, c->h_bk[0], c->h_bk[1], c->h_bv[0], c->h_bv[1]};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     if (c->capture) (void)hipStreamDestroy(c->capture);
@@ -886,6 +1132,22 @@ hullf_status hull_from_survivors(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t 
     if (out.size() > cap) return HULLF_ECAPACITY;
     std::copy(out.begin(), out.end(), h_hull);
     return HULLF_OK;
+}
+
+hullf_status hull_from_survivors_batched(hullf_ctx_t c, const hullf_pt* d_pts, const uint64_t* d_off, uint32_t S,
+                                         uint64_t n_total, const uint32_t* d_surv, const uint64_t* d_counts,
+                                         uint32_t* h_hull, uint64_t cap, uint64_t* h_hull_off, void* stream) {
+    if (!h_hull_off || (cap > 0 && !h_hull)) return HULLF_EINVAL;
+    hullf_status st = check_batch_args(c, d_pts, d_off, S, n_total, const_cast<uint32_t*>(d_surv),
+                                       const_cast<uint64_t*>(d_counts));
+    if (st != HULLF_OK) return st;
+    if (S == 0) {
+        h_hull_off[0] = 0;
+        return HULLF_OK;
+    }
+    DeviceGuard g(c->device);
+    return finish_batch(c, reinterpret_cast<const float2*>(d_pts), d_off, S, n_total, d_surv, d_counts, h_hull, cap,
+                        h_hull_off, (hipStream_t)stream);
 }
 
 hullf_status hull_filter_batched_shape(hullf_ctx_t c, const hullf_pt* d_pts, const uint64_t* d_off,

@@ -50,6 +50,7 @@ def _load():
         "convex_hull": ([P, P, U64, P, U64, P, P], st),
         "hullf_flags": ([P, P, U64, P, P], st),
         "hull_from_survivors": ([P, P, U64, P, U64, P, U64, P, P], st),
+        "hull_from_survivors_batched": ([P, P, P, U32, U64, P, P, P, U64, P, P], st),
         "hull_filter_batched": ([P, P, P, U32, U64, P, P, P], st),
         "hull_filter_segments": ([P, P, P, U32, U64, P, P, P], st),
         "hull_filter_batched_shape": ([P, P, P, U32, U64, P, P, I, I, P], st),
@@ -220,6 +221,25 @@ class Context:
                                            out.ctypes.data, cap, ctypes.byref(h), _stream(stream)),
                "hull_from_survivors")
         return out[:h.value].copy()
+
+    def hulls_batched(self, pts, off, surv, counts, n_total=None, stream=None):
+        """Hulls of every set of a batch from hull_filter_batched's survivors
+        (device tensors: pts (n_total, 2) float32, off S+1 int64, surv
+        n_total int32, counts S int64), all sets finished together.  Returns
+        (hulls, offsets): set s's counter-clockwise hull, set-local indices,
+        is hulls[offsets[s]:offsets[s+1]]."""
+        pts = _points(pts)
+        S = off.numel() - 1
+        if n_total is None:
+            n_total = pts.shape[0]
+        hoff = np.zeros(S + 1, dtype=np.uint64)
+        cap = max(int(n_total), 1)
+        out = np.zeros(cap, dtype=np.uint32)
+        _check(_load().hull_from_survivors_batched(self.handle, pts.data_ptr(), off.data_ptr(), S, int(n_total),
+                                                   surv.data_ptr(), counts.data_ptr(), out.ctypes.data, cap,
+                                                   hoff.ctypes.data, _stream(stream)),
+               "hull_from_survivors_batched")
+        return out[:int(hoff[S])].copy(), hoff.astype(np.int64)
 
     # -- batched -------------------------------------------------------------
     def hull_filter_batched(self, pts, off, n_total=None, surv=None, counts=None, stream=None,
@@ -447,7 +467,8 @@ def hull_filter_noalloc(pts, surv=None, count=None, cap=None, stream=None):
 def exported_symbols():
     """Names of the C-ABI functions the binding expects."""
     return ["hullf_create", "hullf_destroy", "hullf_workspace", "hullf_status_str", "hullf_octagon", "hull_filter",
-            "hull_filter_noalloc", "hullf_polygon16", "hull_filter16", "convex_hull", "hullf_flags", "hull_from_survivors", "hull_filter_batched", "hull_filter_segments",
+            "hull_filter_noalloc", "hullf_polygon16", "hull_filter16", "convex_hull", "hullf_flags",
+            "hull_from_survivors", "hull_from_survivors_batched", "hull_filter_batched", "hull_filter_segments",
             "hull_filter_batched_shape", "hullf_autotune_batched", "hullf_timing_enable",
             "hullf_timing_read", "hullf_skip_stats", "hullf_server_create", "hullf_server_destroy", "hullf_server_submit",
             "hullf_server_wait", "hullf_server_stats"]
