@@ -7,8 +7,8 @@
  * owns:
  *  1. admits requests in arrival order while a request slot and room in the
  *     device arena are free (admission by device memory);
- *  2. copies each admitted request's points into its arena region, on a copy
- *     stream, while earlier batches run;
+ *  2. copies each admitted request's points into its arena region, on two
+ *     copy streams (two copies in flight), while earlier batches run;
  *  3. whenever the device is idle, launches one batched filter over every
  *     request whose points are resident (hull_filter_segments in hullf.h:
  *     extremes, inside test and compaction per request, one launch set);

@@ -4,8 +4,9 @@
 // Threads and what each one owns:
 //  - scheduler: admission (arena regions, slots), residency checks, batch
 //    launches on the compute stream, batch completion;
-//  - copier: host-to-device copies of admitted requests on the copy stream
-//    (direct from page-locked memory, else through pinned staging slots);
+//  - copiers (kCopiers): host-to-device copies of admitted requests, each on
+//    its own copy stream (direct from page-locked memory, else through its
+//    pinned staging slots), so that several copies are in flight;
 //  - finishers: survivor copies back (one stream each), arena release, and
 //    the host monotone chain.
 // Every request moves queue -> copy -> loading -> ready -> batch -> finish
@@ -35,7 +36,8 @@ using Clock = std::chrono::steady_clock;
 
 constexpr uint64_t kGranule = 64;               // arena allocation unit (points): 512-byte aligned regions
 constexpr uint64_t kStagePoints = 1ull << 20;   // pinned staging slot (8 MiB)
-constexpr int kStageSlots = 4;
+constexpr int kStageSlots = 4;                  // per copier
+constexpr int kCopiers = 2;                     // copier threads, each with its own copy stream
 constexpr uint64_t kCountNonFinite = UINT64_MAX;
 
 double us_between(Clock::time_point a, Clock::time_point b) {
@@ -120,10 +122,10 @@ struct hullf_server {
     // pinned host memory
     uint64_t* h_seg = nullptr;
     uint64_t* h_counts = nullptr;
-    hullf_pt* stage[kStageSlots] = {};
-    hipEvent_t stage_ev[kStageSlots] = {};
+    hullf_pt* stage[kCopiers][kStageSlots] = {};
+    hipEvent_t stage_ev[kCopiers][kStageSlots] = {};
     // streams and events
-    hipStream_t compute = nullptr, copy = nullptr;
+    hipStream_t compute = nullptr, copy[kCopiers] = {};
     hipEvent_t batch_ev = nullptr;
     std::vector<hipEvent_t> ev_pool;
 
@@ -139,7 +141,7 @@ struct hullf_server {
     Clock::time_point batch_t0;
     hullf_server_counters st{};
 
-    std::thread sched_th, copy_th;
+    std::thread sched_th, copy_th[kCopiers];
     std::vector<std::thread> finish_th;
     std::vector<hullf_ctx_t> fctx;   // one context per finisher thread
 
@@ -158,7 +160,7 @@ struct hullf_server {
             ++inflight;
             copy_q.push_back(r);
         }
-        if (!copy_q.empty()) cv_copy.notify_one();
+        if (!copy_q.empty()) cv_copy.notify_all();
     }
 
     void fail_locked(Req* r, hullf_status s) {
@@ -255,25 +257,27 @@ struct hullf_server {
     }
 
     // -- copier -------------------------------------------------------------
-    hipError_t upload(Req* r, uint64_t& slot) {
+    hipError_t upload(Req* r, uint64_t& slot, int id) {
         hullf_pt* dst = d_pts + r->begin;
         if (r->pinned)
-            return hipMemcpyAsync(dst, r->h, r->n * sizeof(hullf_pt), hipMemcpyHostToDevice, copy);
+            return hipMemcpyAsync(dst, r->h, r->n * sizeof(hullf_pt), hipMemcpyHostToDevice, copy[id]);
         for (uint64_t o = 0; o < r->n; o += kStagePoints) {
             const uint64_t m = std::min<uint64_t>(kStagePoints, r->n - o);
             const int k = (int)(slot++ % kStageSlots);
-            hipError_t e = hipEventSynchronize(stage_ev[k]);
+            hipError_t e = hipEventSynchronize(stage_ev[id][k]);
             if (e != hipSuccess) return e;
-            std::memcpy(stage[k], r->h + o, m * sizeof(hullf_pt));
-            e = hipMemcpyAsync(dst + o, stage[k], m * sizeof(hullf_pt), hipMemcpyHostToDevice, copy);
+            std::memcpy(stage[id][k], r->h + o, m * sizeof(hullf_pt));
+            e = hipMemcpyAsync(dst + o, stage[id][k], m * sizeof(hullf_pt), hipMemcpyHostToDevice, copy[id]);
             if (e != hipSuccess) return e;
-            e = hipEventRecord(stage_ev[k], copy);
+            e = hipEventRecord(stage_ev[id][k], copy[id]);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
 
-    void copy_loop() {
+    // Copier `id`: takes admitted requests in turn with the other copiers,
+    // on its own stream, so that two host-to-device copies are in flight.
+    void copy_loop(int id) {
         (void)hipSetDevice(device);
         uint64_t slot = 0;
         std::unique_lock<std::mutex> lk(mu);
@@ -290,8 +294,8 @@ struct hullf_server {
             lk.unlock();
             hipError_t e = hipSuccess;
             if (!ev) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            if (e == hipSuccess) e = upload(r, slot);
-            if (e == hipSuccess) e = hipEventRecord(ev, copy);
+            if (e == hipSuccess) e = upload(r, slot, id);
+            if (e == hipSuccess) e = hipEventRecord(ev, copy[id]);
             lk.lock();
             if (e != hipSuccess) {
                 if (ev) ev_pool.push_back(ev);
@@ -360,23 +364,26 @@ struct hullf_server {
     void release_all() {
         (void)hipSetDevice(device);
         if (compute) (void)hipStreamSynchronize(compute);
-        if (copy) (void)hipStreamSynchronize(copy);
+        for (hipStream_t q : copy)
+            if (q) (void)hipStreamSynchronize(q);
         void* dev[] = {d_pts, d_surv, d_seg, d_counts};
         for (void* q : dev)
             if (q) (void)hipFree(q);
         if (h_seg) (void)hipHostFree(h_seg);
         if (h_counts) (void)hipHostFree(h_counts);
-        for (int k = 0; k < kStageSlots; ++k) {
-            if (stage[k]) (void)hipHostFree(stage[k]);
-            if (stage_ev[k]) (void)hipEventDestroy(stage_ev[k]);
-        }
+        for (int i = 0; i < kCopiers; ++i)
+            for (int k = 0; k < kStageSlots; ++k) {
+                if (stage[i][k]) (void)hipHostFree(stage[i][k]);
+                if (stage_ev[i][k]) (void)hipEventDestroy(stage_ev[i][k]);
+            }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (auto& kv : reqs)
             if (kv.second->loaded) (void)hipEventDestroy(kv.second->loaded);
         if (batch_ev) (void)hipEventDestroy(batch_ev);
         for (hullf_ctx_t f : fctx) hullf_destroy(f);
         if (compute) (void)hipStreamDestroy(compute);
-        if (copy) (void)hipStreamDestroy(copy);
+        for (hipStream_t q : copy)
+            if (q) (void)hipStreamDestroy(q);
         if (ctx) hullf_destroy(ctx);
     }
 };
@@ -412,12 +419,14 @@ hullf_status hullf_server_create(int device, const hullf_server_config* cfg, hul
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_counts, 8ull * M);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_seg, 16ull * M, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_counts, 8ull * M, hipHostMallocDefault);
-    for (int k = 0; k < kStageSlots && e == hipSuccess; ++k) {
-        e = hipHostMalloc((void**)&s->stage[k], kStagePoints * sizeof(hullf_pt), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->stage_ev[k], hipEventDisableTiming);
-    }
+    for (int i = 0; i < kCopiers; ++i)
+        for (int k = 0; k < kStageSlots && e == hipSuccess; ++k) {
+            e = hipHostMalloc((void**)&s->stage[i][k], kStagePoints * sizeof(hullf_pt), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->stage_ev[i][k], hipEventDisableTiming);
+        }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+    for (int i = 0; i < kCopiers && e == hipSuccess; ++i)
+        e = hipStreamCreateWithFlags(&s->copy[i], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->batch_ev, hipEventDisableTiming);
     // one launch over max_inflight empty segments sizes the batched scratch
     // for the largest batch, so serving allocates nothing later
@@ -442,7 +451,7 @@ hullf_status hullf_server_create(int device, const hullf_server_config* cfg, hul
     s->arena.reset(new Arena(A));
     s->st.arena_points = A;
     s->sched_th = std::thread([s] { s->sched_loop(); });
-    s->copy_th = std::thread([s] { s->copy_loop(); });
+    for (int i = 0; i < kCopiers; ++i) s->copy_th[i] = std::thread([s, i] { s->copy_loop(i); });
     for (uint32_t k = 0; k < c.finish_threads; ++k) {
         hullf_ctx_t f = s->fctx[k];
         s->finish_th.emplace_back([s, f] { s->finish_loop(f); });
@@ -465,7 +474,7 @@ void hullf_server_destroy(hullf_server_t s) {
     }
     s->cv_copy.notify_all();
     s->cv_finish.notify_all();
-    s->copy_th.join();
+    for (std::thread& t : s->copy_th) t.join();
     for (auto& t : s->finish_th) t.join();
     s->release_all();
     delete s;
