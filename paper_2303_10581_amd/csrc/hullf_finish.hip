@@ -598,18 +598,19 @@ __global__ __launch_bounds__(64) void k_chain(const uint64_t* __restrict__ keys,
 }
 
 // Run representatives of keys sorted by x alone (stable, so every run of
-// equal x holds its points in ascending index order): for the lower side
-// (sign 1) the first point of least y of each run, for the upper side the
-// first point of greatest y.  A point above (below) another of the same x is
-// no strict vertex of the lower (upper) hull, except the two ends of the
-// hull's chains: the lexicographically greatest point ends the lower chain
-// and the smallest starts the upper one; the host adds those two back when
-// it joins the chains.
+// equal x holds its points in ascending index order), both sides in one
+// pass: for the lower side (rk0 / rv0) the first point of least y of each
+// run, for the upper side (rk1 / rv1) the first point of greatest y.  A
+// point above (below) another of the same x is no strict vertex of the
+// lower (upper) hull, except the two ends of the hull's chains: the
+// lexicographically greatest point ends the lower chain and the smallest
+// starts the upper one; the host adds those two back when it joins the
+// chains.
 //
 // Wave w owns the runs whose first point lies in its tile, positions
 // [w*T, (w+1)*T) with T = kRunTile, and writes their representatives, in
-// order, to rk/rv[w*T ...] (key and value; at most T) and their number to
-// cnt[w].  It walks the tile 64 positions a step (lane l reads position
+// order, to rk0/rv0 and rk1/rv1 [w*T ...] (key and value; at most T) and
+// their number to cnt[w].  It walks the tile 64 positions a step (lane l reads position
 // i0 + l; the tile's loads are all issued before the first step), and past
 // the tile's end while a run it owns is still open.  In a step every lane
 // needs the least (y', position) of its run so far, y' the order-preserving
@@ -646,30 +647,39 @@ struct RunCarry {
     bool open;       // a run is open before this step
     bool own;        // the wave owns it
     uint32_t x;      // its x (ordered bits)
-    uint64_t best;   // least (y', position) of it so far
-    uint32_t val;    // the value at that position
+    uint64_t best[2];   // per side: least (y', position) of it so far
+    uint32_t val[2];    // the value at that position
 };
 
-// One step at positions [i0, i0 + 64) (key k and value kv per lane); false
-// once the wave is done.
-__device__ __forceinline__ bool run_step(uint64_t k, uint32_t kv, uint32_t i0, uint32_t m, uint32_t e, int sign,
-                                         uint32_t lane, uint64_t upto, RunCarry& c, uint64_t* __restrict__ rk,
-                                         uint32_t* __restrict__ rv, uint32_t& len) {
+// One step at positions [i0, i0 + 64) (key k and value kv per lane), both
+// sides at once (the runs, and so the output slots, are the same; side 0
+// takes y' = the ordered bits of y, side 1 their complement); false once
+// the wave is done.
+__device__ __forceinline__ bool run_step(uint64_t k, uint32_t kv, uint32_t i0, uint32_t m, uint32_t e, uint32_t lane,
+                                         uint64_t upto, RunCarry& c, uint64_t* __restrict__ rk0,
+                                         uint32_t* __restrict__ rv0, uint64_t* __restrict__ rk1,
+                                         uint32_t* __restrict__ rv1, uint32_t& len) {
     const uint32_t i = i0 + lane;
     const bool valid = i < m;
     const uint32_t kx = (uint32_t)(k >> 32);
-    const uint32_t ky = sign > 0 ? (uint32_t)k : ~(uint32_t)k;
     const uint32_t px = (uint32_t)__shfl_up((int)kx, 1, 64);
     const bool head = !valid || (lane == 0u ? (!c.open || kx != c.x) : kx != px);
     const uint64_t H = __ballot(head);
     const uint32_t g = (uint32_t)__popcll(H & upto);   // runs starting at or below this lane
-    const uint64_t v = wave_prefix_min(((uint64_t)(64u - g) << 40) | ((uint64_t)ky << 6) | lane);
-    uint64_t s = ((uint64_t)(uint32_t)(v >> 6) << 32) | (i0 + (uint32_t)(v & 63u));
-    uint32_t sv = (uint32_t)__shfl((int)kv, (int)(v & 63u), 64);
+    const uint64_t runs = (uint64_t)(64u - g) << 40;
     const bool carried = g == 0u;   // this lane is in the run carried in
-    if (carried && c.best < s) {
-        s = c.best;
-        sv = c.val;
+    uint64_t sb[2];
+    uint32_t svb[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const uint32_t ky = side == 0 ? (uint32_t)k : ~(uint32_t)k;
+        const uint64_t v = wave_prefix_min(runs | ((uint64_t)ky << 6) | lane);
+        sb[side] = ((uint64_t)(uint32_t)(v >> 6) << 32) | (i0 + (uint32_t)(v & 63u));
+        svb[side] = (uint32_t)__shfl((int)kv, (int)(v & 63u), 64);
+        if (carried && c.best[side] < sb[side]) {
+            sb[side] = c.best[side];
+            svb[side] = c.val[side];
+        }
     }
     const bool own = carried ? c.own : (i0 < e);
     const bool end = valid && (lane < 63u ? ((H >> lane) & 2ull) != 0ull : i + 1u == m);
@@ -678,21 +688,26 @@ __device__ __forceinline__ bool run_step(uint64_t k, uint32_t kv, uint32_t i0, u
     const uint64_t E = __ballot(emit);
     const uint32_t base = len + (cemit ? 1u : 0u);
     if (cemit && lane == 0u) {
-        const uint32_t y = (uint32_t)(c.best >> 32);
-        rk[len] = ((uint64_t)c.x << 32) | (sign > 0 ? y : ~y);
-        rv[len] = c.val;
+        rk0[len] = ((uint64_t)c.x << 32) | (uint32_t)(c.best[0] >> 32);
+        rv0[len] = c.val[0];
+        rk1[len] = ((uint64_t)c.x << 32) | ~(uint32_t)(c.best[1] >> 32);
+        rv1[len] = c.val[1];
     }
     if (emit) {
         const uint32_t o = base + (uint32_t)__popcll(E & (upto >> 1));
-        const uint32_t y = (uint32_t)(s >> 32);
-        rk[o] = ((uint64_t)kx << 32) | (sign > 0 ? y : ~y);
-        rv[o] = sv;
+        rk0[o] = ((uint64_t)kx << 32) | (uint32_t)(sb[0] >> 32);
+        rv0[o] = svb[0];
+        rk1[o] = ((uint64_t)kx << 32) | ~(uint32_t)(sb[1] >> 32);
+        rv1[o] = svb[1];
     }
     len = base + (uint32_t)__popcll(E);
     if (i0 + 64u >= m) return false;
     c.x = (uint32_t)__shfl((int)kx, 63, 64);
-    c.best = __shfl(s, 63, 64);
-    c.val = (uint32_t)__shfl((int)sv, 63, 64);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        c.best[side] = __shfl(sb[side], 63, 64);
+        c.val[side] = (uint32_t)__shfl((int)svb[side], 63, 64);
+    }
     c.own = __shfl((int)own, 63, 64) != 0;
     c.open = true;
     return !(i0 + 64u >= e && !c.own);   // past the tile with no owned run open: done
@@ -703,8 +718,9 @@ __device__ __forceinline__ bool run_step(uint64_t k, uint32_t kv, uint32_t i0, u
 // most to its set's end (runs never cross sets), and a piece that starts a
 // set has no run open before it.
 __global__ __launch_bounds__(256) void k_runs(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                                              uint32_t m, int sign, SetSplit sp, uint64_t* __restrict__ rk,
-                                              uint32_t* __restrict__ rv, uint32_t* __restrict__ cnt) {
+                                              uint32_t m, SetSplit sp, uint64_t* __restrict__ rk0,
+                                              uint32_t* __restrict__ rv0, uint64_t* __restrict__ rk1,
+                                              uint32_t* __restrict__ rv1, uint32_t* __restrict__ cnt) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6);
     const uint32_t nt = sp.first ? sp.first[sp.S] : (m + kRunTile - 1u) / kRunTile;
@@ -732,21 +748,24 @@ __global__ __launch_bounds__(256) void k_runs(const uint64_t* __restrict__ keys,
         vr[u] = (i < se) ? vals[i] : 0u;
     }
     // a run open at b started in the previous tile: not this wave's
-    RunCarry c{!first, false, first ? 0u : (uint32_t)(keys[b - 1u] >> 32), ~0ull, 0u};
-    uint64_t* ok = rk + (uint64_t)w * kRunTile;   // tile w's slots
-    uint32_t* ov = rv + (uint64_t)w * kRunTile;
+    RunCarry c{!first, false, first ? 0u : (uint32_t)(keys[b - 1u] >> 32), {~0ull, ~0ull}, {0u, 0u}};
+    const uint64_t o0 = (uint64_t)w * kRunTile;   // tile w's slots
+    uint64_t* ok0 = rk0 + o0;
+    uint32_t* ov0 = rv0 + o0;
+    uint64_t* ok1 = rk1 + o0;
+    uint32_t* ov1 = rv1 + o0;
     uint32_t len = 0;
     bool more = true;
 #pragma unroll
     for (uint32_t u = 0; u < kRunSteps; ++u) {
-        more = run_step(kr[u], vr[u], b + 64u * u, se, e, sign, lane, upto, c, ok, ov, len);
+        more = run_step(kr[u], vr[u], b + 64u * u, se, e, lane, upto, c, ok0, ov0, ok1, ov1, len);
         if (!more) break;
     }
     // past the tile: the owned run still open
     for (uint32_t i0 = b + kRunTile; more; i0 += 64u) {
         const uint32_t i = i0 + lane;
-        more = run_step((i < se) ? keys[i] : 0ull, (i < se) ? vals[i] : 0u, i0, se, e, sign, lane, upto, c, ok, ov,
-                        len);
+        more = run_step((i < se) ? keys[i] : 0ull, (i < se) ? vals[i] : 0u, i0, se, e, lane, upto, c, ok0, ov0, ok1,
+                        ov1, len);
     }
     if (lane == 0u) cnt[w] = len;
 }
@@ -1075,11 +1094,13 @@ hipError_t launch_chain(const uint64_t* keys, uint32_t m, uint32_t C, int sign, 
     return hipGetLastError();
 }
 
-hipError_t launch_runs(const uint64_t* keys, const uint32_t* vals, uint32_t m, int sign, uint64_t* rk, uint32_t* rv,
-                       uint32_t* cnt, hipStream_t stream, const SetSplit& sp, uint32_t nsp) {
+hipError_t launch_runs(const uint64_t* keys, const uint32_t* vals, uint32_t m, uint64_t* rk0, uint32_t* rv0,
+                       uint64_t* rk1, uint32_t* rv1, uint32_t* cnt, hipStream_t stream, const SetSplit& sp,
+                       uint32_t nsp) {
     const uint32_t nt = sp.first ? nsp : (m + kRunTile - 1u) / kRunTile;
     if (nt == 0u) return hipSuccess;
-    hipLaunchKernelGGL(k_runs, dim3((nt + 3u) / 4u), dim3(256), 0, stream, keys, vals, m, sign, sp, rk, rv, cnt);
+    hipLaunchKernelGGL(k_runs, dim3((nt + 3u) / 4u), dim3(256), 0, stream, keys, vals, m, sp, rk0, rv0, rk1, rv1,
+                       cnt);
     return hipGetLastError();
 }
 

@@ -202,13 +202,15 @@ hipError_t launch_bfin_keys(const float2* pts, const uint64_t* off, const uint32
 hipError_t launch_finish_sort_sets(uint64_t* keys, uint32_t* vals, uint64_t* keys2, uint32_t* vals2, uint32_t m,
                                    const SetSplit& sp, uint32_t tiles, uint32_t* hist, uint32_t* rowend, uint32_t* sdp,
                                    hipStream_t stream);
-// Run representatives of keys sorted by x alone (see k_runs): their keys
-// and values into rk / rv (tile t's at t*kRunTile, cnt[t] of them), counts
-// per tile into cnt: ceil(m / kRunTile) tiles, or with a split sp (pieces
-// of kRunTile, a batch) its nsp pieces.
+// Run representatives of keys sorted by x alone (see k_runs), both sides:
+// their keys and values into rk0 / rv0 (lower side) and rk1 / rv1 (upper
+// side) (tile t's at t*kRunTile, cnt[t] of them on each side), counts per
+// tile into cnt: ceil(m / kRunTile) tiles, or with a split sp (pieces of
+// kRunTile, a batch) its nsp pieces.
 constexpr uint32_t kRunTile = 1024;
-hipError_t launch_runs(const uint64_t* keys, const uint32_t* vals, uint32_t m, int sign, uint64_t* rk, uint32_t* rv,
-                       uint32_t* cnt, hipStream_t stream, const SetSplit& sp = SetSplit{}, uint32_t nsp = 0);
+hipError_t launch_runs(const uint64_t* keys, const uint32_t* vals, uint32_t m, uint64_t* rk0, uint32_t* rv0,
+                       uint64_t* rk1, uint32_t* rv1, uint32_t* cnt, hipStream_t stream,
+                       const SetSplit& sp = SetSplit{}, uint32_t nsp = 0);
 // Chains of chunks of C sorted points (C at most 64): chain holds a slot
 // per point (chunk c's chain at c*C), cnt one word per chunk: ceil(m/C)
 // chunks, or with a split sp (pieces of C, never crossing a set) its nsp

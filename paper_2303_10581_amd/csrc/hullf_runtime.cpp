@@ -74,8 +74,10 @@ struct hullf_ctx {
     unsigned long long* part16 = nullptr;   // kPart16Words * kReduceMaxGrid
     Poly16* h_poly16 = nullptr;
     // hull finishing on the device (large survivor sets)
-    uint64_t* fk[3] = {nullptr, nullptr, nullptr};   // keys: sorted, then level outputs
-    uint32_t* fv[3] = {nullptr, nullptr, nullptr};   // point indices
+    // finishing keys and point indices: 0 sorted, 1 and 3 the two sides' run
+    // representatives, then level outputs (side 0: 1 <-> 2, side 1: 3 <-> 0)
+    uint64_t* fk[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint32_t* fv[4] = {nullptr, nullptr, nullptr, nullptr};
     uint32_t* fchain = nullptr;
     uint32_t* fcnt = nullptr;
     uint32_t* fblk = nullptr;
@@ -373,7 +375,7 @@ hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
     if (m > c->f_cap) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             ws_free(c, c->fk[k]);
             ws_free(c, c->fv[k]);
             c->fk[k] = nullptr;
@@ -387,7 +389,7 @@ hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
         c->fblk = nullptr;
         c->f_cap = 0;
         const uint64_t cap = m + m / 8 + 1024;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             if ((e = ws_alloc(c, &c->fk[k], cap)) != hipSuccess) return e;
             if ((e = ws_alloc(c, &c->fv[k], cap)) != hipSuccess) return e;
         }
@@ -434,25 +436,27 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
     std::vector<HostPt> lists[2];
     uint32_t* const off_b = c->fchain + c->f_cap / 2;   // second offset array of the merge rounds
     uint2* const br = reinterpret_cast<uint2*>(c->fchain);
+    // each side's representative of every run of equal x, in order
+    // (distinct points, sorted by (x, y)), per tile of the run pass: lower
+    // side into buffer 1, upper into 3; the first chunk level reads them
+    // through the scanned tile counts
+    uint32_t* const tcnt = c->fcnt + c->f_cap / kChainChunkMin + 2;
+    const uint32_t ntiles = (mm + kRunTile - 1) / kRunTile;
+    CHECK_HIP(launch_runs(c->fk[0], c->fv[0], mm, c->fk[1], c->fv[1], c->fk[3], c->fv[3], tcnt, s));
+    CHECK_HIP(launch_scan_counts(tcnt, ntiles, c->frow + 256, c->fblk, s));
+    CHECK_HIP(hipMemcpyAsync(c->h_total, c->frow + 256, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    const uint32_t reps = *c->h_total;
+    if (reps == 0 || reps > mm) return HULLF_EDEVICE;
     for (int side = 0; side < 2; ++side) {
         const int sign = side == 0 ? 1 : -1;
-        // the side's representative of every run of equal x, in order
-        // (distinct points, sorted by (x, y)), per tile of the run pass;
-        // the first chunk level reads them through the scanned tile counts
-        uint32_t* const tcnt = c->fcnt + c->f_cap / kChainChunkMin + 2;
-        const uint32_t ntiles = (mm + kRunTile - 1) / kRunTile;
-        CHECK_HIP(launch_runs(c->fk[0], c->fv[0], mm, sign, c->fk[1], c->fv[1], tcnt, s));
-        CHECK_HIP(launch_scan_counts(tcnt, ntiles, c->frow + 256, c->fblk, s));
-        CHECK_HIP(hipMemcpyAsync(c->h_total, c->frow + 256, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        CHECK_HIP(hipStreamSynchronize(s));
-        const uint32_t reps = *c->h_total;
-        if (reps == 0 || reps > mm) return HULLF_EDEVICE;
+        const int ba = side == 0 ? 1 : 3, bb = side == 0 ? 2 : 0;   // the side's two buffers
         const uint32_t* toff = tcnt;
-        int cur = 1;
+        int cur = ba;
         uint32_t cm = reps, nc = 0;
         // chunk levels while they shrink the set well
         for (;;) {
-            const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
+            const int nxt = (cur == ba) ? bb : ba;
             const uint32_t C = c->chain_chunk;
             const uint32_t nch = (cm + C - 1) / C;
             CHECK_HIP(launch_chain(c->fk[cur], cm, C, sign, toff, toff ? ntiles : 0u, c->fchain, c->fcnt, s));
@@ -480,7 +484,7 @@ hullf_status finish_on_device(hullf_ctx* c, const float2* pts, uint64_t n, const
         uint32_t* off_out = off_b;
         while (nc > 1) {
             const uint32_t np = (nc + 1) / 2;
-            const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
+            const int nxt = (cur == ba) ? bb : ba;
             const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((np + 3) / 4, (uint32_t)c->cus * 8));
             CHECK_HIP(launch_bridge(c->fk[cur], off_in, nc, sign, br, off_out, gg, s));
             CHECK_HIP(launch_scan_counts(off_out, np, off_out + np, c->fblk, s));
@@ -595,22 +599,26 @@ hullf_status finish_batch(hullf_ctx* c, const float2* pts, const uint64_t* d_off
     uint32_t* const tcnt = c->fcnt + c->f_cap / kChainChunkMin + 2;
     const uint32_t C = c->chain_chunk;
     std::vector<uint32_t> rng(S1), fcs(S1), rounds;
+    // run representatives of both sides per run tile (lower into buffer 1,
+    // upper into 3), then each set's range of them
+    const SetSplit sp_run{d_rft, d_ipos, S, kRunTile};
+    CHECK_HIP(launch_runs(c->fk[0], c->fv[0], mm, c->fk[1], c->fv[1], c->fk[3], c->fv[3], tcnt, s, sp_run,
+                          (uint32_t)NRT));
+    CHECK_HIP(launch_scan_counts(tcnt, (uint32_t)NRT, c->frow + 256, c->fblk, s));
+    CHECK_HIP(launch_copy_u32(tcnt + NRT, c->frow + 256, s));   // toff[NRT] = the total
+    CHECK_HIP(take(tcnt, d_rft));
+    const std::vector<uint32_t> reps = took;
+    if (reps[S] == 0 || reps[S] > mm) return HULLF_EDEVICE;
     for (int side = 0; side < 2; ++side) {
         const int sign = side == 0 ? 1 : -1;
-        // run representatives per run tile, then each set's range of them
-        const SetSplit sp_run{d_rft, d_ipos, S, kRunTile};
-        CHECK_HIP(launch_runs(c->fk[0], c->fv[0], mm, sign, c->fk[1], c->fv[1], tcnt, s, sp_run, (uint32_t)NRT));
-        CHECK_HIP(launch_scan_counts(tcnt, (uint32_t)NRT, c->frow + 256, c->fblk, s));
-        CHECK_HIP(launch_copy_u32(tcnt + NRT, c->frow + 256, s));   // toff[NRT] = the total
-        CHECK_HIP(take(tcnt, d_rft));
-        rng = took;
-        if (rng[S] == 0 || rng[S] > mm) return HULLF_EDEVICE;
+        const int ba = side == 0 ? 1 : 3, bb = side == 0 ? 2 : 0;   // the side's two buffers
+        rng = reps;
         // chunk levels
         const uint32_t* toff = tcnt;
-        int cur = 1;
+        int cur = ba;
         uint32_t cm = rng[S], nc = 0;
         for (;;) {
-            const int nxt = (cur == 1) ? 2 : 1;   // buffer 0 keeps the sorted keys for the other side
+            const int nxt = (cur == ba) ? bb : ba;
             uint64_t nct = 0;
             for (uint32_t k = 0; k < S; ++k) {
                 fcs[k] = (uint32_t)nct;
@@ -676,7 +684,7 @@ hullf_status finish_batch(hullf_ctx* c, const float2* pts, const uint64_t* d_off
         uint32_t ncur = nc;
         for (uint32_t r = 0; r < nr; ++r) {
             const uint32_t np = nps[r];
-            const int nxt = (cur == 1) ? 2 : 1;
+            const int nxt = (cur == ba) ? bb : ba;
             const SetSplit sp_pair{d_rounds + 2ull * r * S1, d_rounds + 2ull * r * S1 + S1, S, 2u};
             const int gg = (int)std::max<uint32_t>(1, std::min<uint32_t>((np + 3) / 4, (uint32_t)c->cus * 8));
             CHECK_HIP(launch_bridge(c->fk[cur], off_in, ncur, sign, br, off_out, gg, s, sp_pair, np));
@@ -1004,8 +1012,8 @@ void hullf_destroy(hullf_ctx_t c) {
                    c->b_sets, c->b_octs, c->b_tot, c->b_part, c->b_boxes, c->b_bits, c->b_blkcnt};
     for (void* p : dev)
         if (p) (void)hipFree(p);
-    void* fin[] = {c->fk[0], c->fk[1], c->fk[2], c->fv[0],   c->fv[1],
-                   c->fv[2], c->fchain, c->fcnt,  c->fblk,  c->fhist, c->frow};
+    void* fin[] = {c->fk[0], c->fk[1], c->fk[2],  c->fk[3], c->fv[0], c->fv[1],  c->fv[2],
+                   c->fv[3], c->fchain, c->fcnt, c->fblk,  c->fhist, c->frow};
     for (void* p : fin)
         if (p) (void)hipFree(p);
     void* host[] = {c->h_surv, c->h_xy,   c->h_count, c->h_oct,  c->h_fk,   c->h_fv,
