@@ -903,7 +903,7 @@ hullf_status enqueue_batched(hullf_ctx* c, const hullf_pt* d_pts, const uint64_t
 }
 
 hullf_status check_batch_args(hullf_ctx* c, const hullf_pt* d_pts, const uint64_t* d_off, uint32_t S,
-                              uint64_t n_total, uint32_t* d_surv, uint64_t* d_counts) {
+                              uint64_t n_total, const uint32_t* d_surv, const uint64_t* d_counts) {
     if (!c) return HULLF_EINVAL;
     if (S == 0) return HULLF_OK;
     if (!d_off || !d_counts) return HULLF_EINVAL;
@@ -1146,8 +1146,7 @@ hullf_status hull_from_survivors_batched(hullf_ctx_t c, const hullf_pt* d_pts, c
                                          uint64_t n_total, const uint32_t* d_surv, const uint64_t* d_counts,
                                          uint32_t* h_hull, uint64_t cap, uint64_t* h_hull_off, void* stream) {
     if (!h_hull_off || (cap > 0 && !h_hull)) return HULLF_EINVAL;
-    hullf_status st = check_batch_args(c, d_pts, d_off, S, n_total, const_cast<uint32_t*>(d_surv),
-                                       const_cast<uint64_t*>(d_counts));
+    hullf_status st = check_batch_args(c, d_pts, d_off, S, n_total, d_surv, d_counts);
     if (st != HULLF_OK) return st;
     if (S == 0) {
         h_hull_off[0] = 0;

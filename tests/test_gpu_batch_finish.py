@@ -119,6 +119,32 @@ def test_nonfinite_set_is_reported(ctx, torch_dev):
     assert e.value.status == hullf.ENONFINITE
 
 
+def test_capacity_and_bad_counts(ctx, torch_dev):
+    """Too small a host array: HULLF_ECAPACITY with every set's offset
+    written; a count above its set's size: HULLF_EINVAL."""
+    import torch
+    sets, off, pts = _batch([("circle", 3000), ("normal", 500), ("displaced", 2000)], 700)
+    tp = torch.from_numpy(pts).to(torch_dev)
+    to = torch.from_numpy(off).to(torch_dev)
+    surv, counts = ctx.hull_filter_batched(tp, to)
+    hulls, hoff = ctx.hulls_batched(tp, to, surv, counts)
+    lib = hullf._load()
+    S = len(sets)
+    out = np.zeros(4, np.uint32)
+    ho = np.zeros(S + 1, np.uint64)
+    st = lib.hull_from_survivors_batched(ctx.handle, tp.data_ptr(), to.data_ptr(), S, pts.shape[0],
+                                         surv.data_ptr(), counts.data_ptr(), out.ctypes.data, 4, ho.ctypes.data,
+                                         hullf._stream(None))
+    assert st == hullf.ECAPACITY
+    assert ho.astype(np.int64).tolist() == hoff.tolist()
+    assert (out == 0).all()
+    bad = counts.clone()
+    bad[1] = 501
+    with pytest.raises(hullf.HullfError) as e:
+        ctx.hulls_batched(tp, to, surv, bad)
+    assert e.value.status == hullf.EINVAL
+
+
 def _sha(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
