@@ -8,7 +8,8 @@
  *  1. admits requests in arrival order while a request slot and room in the
  *     device arena are free (admission by device memory);
  *  2. copies each admitted request's points into its arena region, on two
- *     copy streams (two copies in flight), while earlier batches run;
+ *     copy streams (two copies in flight; HULLF_SERVER_COPIERS=1..4 at
+ *     creation sets the number), while earlier batches run;
  *  3. whenever the device is idle, launches one batched filter over every
  *     request whose points are resident (hull_filter_segments in hullf.h:
  *     extremes, inside test and compaction per request, one launch set);

@@ -369,6 +369,7 @@ constexpr uint32_t kChainChunkMin = 16;        // least sorted points per chain 
 constexpr uint32_t kChainMaxChunk = 64;        // most sorted points per chain thread
 constexpr uint32_t kRsTileItems = 4096;        // items per radix-sort tile
 constexpr uint64_t kDeviceFinishMin = 1u << 14;   // survivors from which the device sorts and chains
+constexpr uint64_t kEagerHull = 4096;             // survivors convex_hull stages before it knows the count
 constexpr uint32_t kLevelStop = 1u << 16;         // chunk levels stop at this many candidates
 
 hipError_t ensure_finish(hullf_ctx* c, uint64_t m, hipStream_t s) {
@@ -759,6 +760,17 @@ hullf_status finish_batch(hullf_ctx* c, const float2* pts, const uint64_t* d_off
 
 // Hull of pts[d_surv[0..m)] (m indices below n, ascending): the host chain
 // for few survivors, the device sort and chains for many.
+// Host monotone chain of the m survivors staged in h_surv / h_xy.
+hullf_status host_hull(hullf_ctx* c, uint64_t n, uint64_t m, std::vector<uint32_t>& out) {
+    std::vector<HostPt> p(m);
+    for (uint64_t k = 0; k < m; ++k) {
+        if (c->h_surv[k] >= n) return HULLF_EINVAL;
+        p[k] = HostPt{c->h_xy[k].x, c->h_xy[k].y, c->h_surv[k]};
+    }
+    monotone_chain(p, out);
+    return HULLF_OK;
+}
+
 hullf_status hull_of(hullf_ctx* c, const float2* pts, uint64_t n, const uint32_t* d_surv, uint64_t m,
                      std::vector<uint32_t>& out, hipStream_t s) {
     out.clear();
@@ -773,13 +785,7 @@ hullf_status hull_of(hullf_ctx* c, const float2* pts, uint64_t n, const uint32_t
     CHECK_HIP(hipMemcpyAsync(c->h_surv, d_surv, m * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     CHECK_HIP(hipMemcpyAsync(c->h_xy, c->gather, m * sizeof(float2), hipMemcpyDeviceToHost, s));
     CHECK_HIP(hipStreamSynchronize(s));
-    std::vector<HostPt> p(m);
-    for (uint64_t k = 0; k < m; ++k) {
-        if (c->h_surv[k] >= n) return HULLF_EINVAL;
-        p[k] = HostPt{c->h_xy[k].x, c->h_xy[k].y, c->h_surv[k]};
-    }
-    monotone_chain(p, out);
-    return HULLF_OK;
+    return host_hull(c, n, m, out);
 }
 
 // Tune-cache key of a batch: floor(log2 S) and floor(log2(mean set size)).
@@ -1111,13 +1117,26 @@ hullf_status convex_hull(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint3
     CHECK_HIP(grow_device(c, &c->surv, &c->surv_cap, n, s));
     hullf_status st = enqueue_filter(c, d_pts, n, c->surv, n, c->count, s);
     if (st != HULLF_OK) return st;
+    // Few survivors (the usual case) are staged for the host chain right
+    // behind the filter, before the count is known (the gather reads it on
+    // the device and stages nothing above kEagerHull): one host round trip
+    // instead of two.
+    const float2* pts = reinterpret_cast<const float2*>(d_pts);
+    const uint64_t eager = std::min<uint64_t>(n, kEagerHull);
+    CHECK_HIP(grow_device(c, &c->gather, &c->gather_cap, eager, s));
+    CHECK_HIP(grow_host(&c->h_surv, &c->h_cap, eager));
+    CHECK_HIP(grow_host(&c->h_xy, &c->h_xy_cap, eager));
+    CHECK_HIP(launch_gather(pts, c->surv, c->count, eager, n, c->gather, 16, s));
     CHECK_HIP(hipMemcpyAsync(c->h_count, c->count, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipMemcpyAsync(c->h_surv, c->surv, eager * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipMemcpyAsync(c->h_xy, c->gather, eager * sizeof(float2), hipMemcpyDeviceToHost, s));
     CHECK_HIP(hipStreamSynchronize(s));
     const uint64_t m = *c->h_count;
     if (m == kCountNonFinite) return HULLF_ENONFINITE;
     if (m > n) return HULLF_EDEVICE;
     std::vector<uint32_t> out;
-    st = hull_of(c, reinterpret_cast<const float2*>(d_pts), n, c->surv, m, out, s);
+    if (m <= eager && (m < kDeviceFinishMin || c->host_finish)) st = host_hull(c, n, m, out);
+    else st = hull_of(c, pts, n, c->surv, m, out, s);
     if (st != HULLF_OK) return st;
     *h_count = out.size();
     if (out.size() > cap) return HULLF_ECAPACITY;

@@ -4,7 +4,7 @@
 // Threads and what each one owns:
 //  - scheduler: admission (arena regions, slots), residency checks, batch
 //    launches on the compute stream, batch completion;
-//  - copiers (kCopiers): host-to-device copies of admitted requests, each on
+//  - copiers (2 by default): host-to-device copies of admitted requests, each on
 //    its own copy stream (direct from page-locked memory, else through its
 //    pinned staging slots), so that several copies are in flight;
 //  - finishers: survivor copies back (one stream each), arena release, and
@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -37,7 +38,7 @@ using Clock = std::chrono::steady_clock;
 constexpr uint64_t kGranule = 64;               // arena allocation unit (points): 512-byte aligned regions
 constexpr uint64_t kStagePoints = 1ull << 20;   // pinned staging slot (8 MiB)
 constexpr int kStageSlots = 4;                  // per copier
-constexpr int kCopiers = 2;                     // copier threads, each with its own copy stream
+constexpr int kMaxCopiers = 4;                  // copier threads, each with its own copy stream
 constexpr uint64_t kCountNonFinite = UINT64_MAX;
 
 double us_between(Clock::time_point a, Clock::time_point b) {
@@ -122,10 +123,11 @@ struct hullf_server {
     // pinned host memory
     uint64_t* h_seg = nullptr;
     uint64_t* h_counts = nullptr;
-    hullf_pt* stage[kCopiers][kStageSlots] = {};
-    hipEvent_t stage_ev[kCopiers][kStageSlots] = {};
+    int copiers = 2;
+    hullf_pt* stage[kMaxCopiers][kStageSlots] = {};
+    hipEvent_t stage_ev[kMaxCopiers][kStageSlots] = {};
     // streams and events
-    hipStream_t compute = nullptr, copy[kCopiers] = {};
+    hipStream_t compute = nullptr, copy[kMaxCopiers] = {};
     hipEvent_t batch_ev = nullptr;
     std::vector<hipEvent_t> ev_pool;
 
@@ -141,7 +143,7 @@ struct hullf_server {
     Clock::time_point batch_t0;
     hullf_server_counters st{};
 
-    std::thread sched_th, copy_th[kCopiers];
+    std::thread sched_th, copy_th[kMaxCopiers];
     std::vector<std::thread> finish_th;
     std::vector<hullf_ctx_t> fctx;   // one context per finisher thread
 
@@ -371,7 +373,7 @@ struct hullf_server {
             if (q) (void)hipFree(q);
         if (h_seg) (void)hipHostFree(h_seg);
         if (h_counts) (void)hipHostFree(h_counts);
-        for (int i = 0; i < kCopiers; ++i)
+        for (int i = 0; i < kMaxCopiers; ++i)
             for (int k = 0; k < kStageSlots; ++k) {
                 if (stage[i][k]) (void)hipHostFree(stage[i][k]);
                 if (stage_ev[i][k]) (void)hipEventDestroy(stage_ev[i][k]);
@@ -419,13 +421,15 @@ hullf_status hullf_server_create(int device, const hullf_server_config* cfg, hul
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_counts, 8ull * M);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_seg, 16ull * M, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_counts, 8ull * M, hipHostMallocDefault);
-    for (int i = 0; i < kCopiers; ++i)
+    if (const char* v = std::getenv("HULLF_SERVER_COPIERS"))
+        s->copiers = std::min(kMaxCopiers, std::max(1, std::atoi(v)));
+    for (int i = 0; i < s->copiers; ++i)
         for (int k = 0; k < kStageSlots && e == hipSuccess; ++k) {
             e = hipHostMalloc((void**)&s->stage[i][k], kStagePoints * sizeof(hullf_pt), hipHostMallocDefault);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s->stage_ev[i][k], hipEventDisableTiming);
         }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking);
-    for (int i = 0; i < kCopiers && e == hipSuccess; ++i)
+    for (int i = 0; i < s->copiers && e == hipSuccess; ++i)
         e = hipStreamCreateWithFlags(&s->copy[i], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->batch_ev, hipEventDisableTiming);
     // one launch over max_inflight empty segments sizes the batched scratch
@@ -451,7 +455,7 @@ hullf_status hullf_server_create(int device, const hullf_server_config* cfg, hul
     s->arena.reset(new Arena(A));
     s->st.arena_points = A;
     s->sched_th = std::thread([s] { s->sched_loop(); });
-    for (int i = 0; i < kCopiers; ++i) s->copy_th[i] = std::thread([s, i] { s->copy_loop(i); });
+    for (int i = 0; i < s->copiers; ++i) s->copy_th[i] = std::thread([s, i] { s->copy_loop(i); });
     for (uint32_t k = 0; k < c.finish_threads; ++k) {
         hullf_ctx_t f = s->fctx[k];
         s->finish_th.emplace_back([s, f] { s->finish_loop(f); });
@@ -474,7 +478,8 @@ void hullf_server_destroy(hullf_server_t s) {
     }
     s->cv_copy.notify_all();
     s->cv_finish.notify_all();
-    for (std::thread& t : s->copy_th) t.join();
+    for (std::thread& t : s->copy_th)
+        if (t.joinable()) t.join();
     for (auto& t : s->finish_th) t.join();
     s->release_all();
     delete s;
