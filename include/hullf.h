@@ -226,7 +226,8 @@ hullf_status hull_filter_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
  * h_hull_off[s+1]); h_hull_off: S + 1 host words, written also when cap is
  * too small (then HULLF_ECAPACITY and h_hull untouched).  A set counted
  * HULLF_COUNT_NONFINITE gives HULLF_ENONFINITE; a count above its set's
- * size or a survivor index outside its set gives HULLF_EINVAL. */
+ * size, a survivor index outside its set, or more than 3.5e9 survivors in
+ * all (sorted positions are 32-bit) gives HULLF_EINVAL. */
 hullf_status hull_from_survivors_batched(hullf_ctx_t ctx, const hullf_pt *d_pts,
                                          const uint64_t *d_off, uint32_t S,
                                          uint64_t n_total, const uint32_t *d_surv,

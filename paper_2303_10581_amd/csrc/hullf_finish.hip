@@ -1004,6 +1004,26 @@ __global__ __launch_bounds__(256) void k_merge_gather(const uint64_t* __restrict
     }
 }
 
+// Few survivors for the host chain, in one block of (page-locked host)
+// memory: stage = [count (u64), pad, points (float2 x cap), indices (u32 x
+// cap)]; the points and indices only when count <= cap (the count read on
+// the device: the filter's, or an error code).
+__global__ __launch_bounds__(256) void k_stage_small(const float2* __restrict__ pts, uint64_t n,
+                                                     const uint32_t* __restrict__ surv,
+                                                     const uint64_t* __restrict__ count, uint32_t cap,
+                                                     unsigned char* __restrict__ stage) {
+    const uint64_t c = *count;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stage) = c;
+    if (c > cap) return;
+    float2* xy = reinterpret_cast<float2*>(stage + 16);
+    uint32_t* idx = reinterpret_cast<uint32_t*>(stage + 16 + 8ull * cap);
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < (uint32_t)c; i += gridDim.x * 256u) {
+        const uint32_t k = surv[i];
+        xy[i] = (k < n) ? pts[k] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+        idx[i] = k;
+    }
+}
+
 __global__ void k_copy_u32(uint32_t* dst, const uint32_t* src) { *dst = *src; }
 
 // dst[i] = src[idx[i]] for i < n.
@@ -1130,6 +1150,15 @@ hipError_t launch_chain_gather(const uint64_t* keys, const uint32_t* vals, uint3
 
 hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, hipStream_t stream) {
     hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, stream, dst, src);
+    return hipGetLastError();
+}
+
+uint64_t stage_small_bytes(uint32_t cap) { return 16ull + 12ull * cap; }
+
+hipError_t launch_stage_small(const float2* pts, uint64_t n, const uint32_t* surv, const uint64_t* count,
+                              uint32_t cap, unsigned char* stage, hipStream_t stream) {
+    hipLaunchKernelGGL(k_stage_small, dim3(std::max<uint32_t>(1u, std::min<uint32_t>((cap + 255u) / 256u, 16u))),
+                       dim3(256), 0, stream, pts, n, surv, count, cap, stage);
     return hipGetLastError();
 }
 

@@ -237,6 +237,12 @@ hipError_t launch_merge_gather(const uint64_t* keys, const uint32_t* vals, const
                                const uint2* br, const uint32_t* noff, uint64_t* kout, uint32_t* vout, int grid,
                                hipStream_t stream, const SetSplit& sp = SetSplit{}, uint32_t nsp = 0);
 hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, hipStream_t stream);
+// The filter's count and, when it is at most cap, the survivors' points and
+// indices, staged in one block of stage_small_bytes(cap) bytes: [u64 count,
+// 8 bytes pad, float2 points[cap], u32 indices[cap]].
+uint64_t stage_small_bytes(uint32_t cap);
+hipError_t launch_stage_small(const float2* pts, uint64_t n, const uint32_t* surv, const uint64_t* count,
+                              uint32_t cap, unsigned char* stage, hipStream_t stream);
 // dst[i] = src[idx[i]], i < n.
 hipError_t launch_take_u32(const uint32_t* src, const uint32_t* idx, uint32_t n, uint32_t* dst, hipStream_t stream);
 // The chain vertices of nch chunks (chunk c's at chain[c*C ...], off: the

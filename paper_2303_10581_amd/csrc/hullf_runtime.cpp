@@ -91,6 +91,8 @@ struct hullf_ctx {
     uint32_t* h_fv = nullptr;
     uint64_t h_f_cap = 0;
     uint64_t h_fv_cap = 0;
+    unsigned char* h_stage = nullptr;      // convex_hull: count + few survivors, written by the device
+    uint64_t h_stage_cap = 0;
     uint64_t* h_bk[2] = {nullptr, nullptr};   // batched finishing: each side's chains
     uint32_t* h_bv[2] = {nullptr, nullptr};
     uint64_t h_bk_cap[2] = {0, 0};
@@ -1022,8 +1024,8 @@ void hullf_destroy(hullf_ctx_t c) {
                    c->fv[3], c->fchain, c->fcnt, c->fblk,  c->fhist, c->frow};
     for (void* p : fin)
         if (p) (void)hipFree(p);
-    void* host[] = {c->h_surv, c->h_xy,   c->h_count, c->h_oct,  c->h_fk,   c->h_fv,
-                    c->h_total, c->h_poly16, c->h_bk[0], c->h_bk[1], c->h_bv[0], c->h_bv[1]};
+    void* host[] = {c->h_surv,   c->h_xy,     c->h_count,  c->h_oct,   c->h_fk,    c->h_fv,   c->h_total,
+                    c->h_poly16, c->h_bk[0], c->h_bk[1], c->h_bv[0], c->h_bv[1], c->h_stage};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     if (c->capture) (void)hipStreamDestroy(c->capture);
@@ -1122,21 +1124,31 @@ hullf_status convex_hull(hullf_ctx_t c, const hullf_pt* d_pts, uint64_t n, uint3
     // the device and stages nothing above kEagerHull): one host round trip
     // instead of two.
     const float2* pts = reinterpret_cast<const float2*>(d_pts);
-    const uint64_t eager = std::min<uint64_t>(n, kEagerHull);
-    CHECK_HIP(grow_device(c, &c->gather, &c->gather_cap, eager, s));
-    CHECK_HIP(grow_host(&c->h_surv, &c->h_cap, eager));
-    CHECK_HIP(grow_host(&c->h_xy, &c->h_xy_cap, eager));
-    CHECK_HIP(launch_gather(pts, c->surv, c->count, eager, n, c->gather, 16, s));
-    CHECK_HIP(hipMemcpyAsync(c->h_count, c->count, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    CHECK_HIP(hipMemcpyAsync(c->h_surv, c->surv, eager * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    CHECK_HIP(hipMemcpyAsync(c->h_xy, c->gather, eager * sizeof(float2), hipMemcpyDeviceToHost, s));
+    const uint32_t eager = (uint32_t)std::min<uint64_t>(n, kEagerHull);
+    // the stage is page-locked host memory the kernel writes through its
+    // device address: no copy back, only the synchronisation
+    CHECK_HIP(grow_host(&c->h_stage, &c->h_stage_cap, stage_small_bytes(eager)));
+    unsigned char* d_stage = nullptr;
+    CHECK_HIP(hipHostGetDevicePointer((void**)&d_stage, c->h_stage, 0));
+    CHECK_HIP(launch_stage_small(pts, n, c->surv, c->count, eager, d_stage, s));
     CHECK_HIP(hipStreamSynchronize(s));
-    const uint64_t m = *c->h_count;
+    uint64_t m = 0;
+    std::memcpy(&m, c->h_stage, sizeof m);
     if (m == kCountNonFinite) return HULLF_ENONFINITE;
     if (m > n) return HULLF_EDEVICE;
     std::vector<uint32_t> out;
-    if (m <= eager && (m < kDeviceFinishMin || c->host_finish)) st = host_hull(c, n, m, out);
-    else st = hull_of(c, pts, n, c->surv, m, out, s);
+    if (m <= eager && (m < kDeviceFinishMin || c->host_finish)) {
+        const float2* xy = reinterpret_cast<const float2*>(c->h_stage + 16);
+        const uint32_t* idx = reinterpret_cast<const uint32_t*>(c->h_stage + 16 + 8ull * eager);
+        std::vector<HostPt> p(m);
+        for (uint64_t k = 0; k < m; ++k) {
+            if (idx[k] >= n) return HULLF_EINVAL;
+            p[k] = HostPt{xy[k].x, xy[k].y, idx[k]};
+        }
+        monotone_chain(p, out);
+    } else {
+        st = hull_of(c, pts, n, c->surv, m, out, s);
+    }
     if (st != HULLF_OK) return st;
     *h_count = out.size();
     if (out.size() > cap) return HULLF_ECAPACITY;
