@@ -666,8 +666,11 @@ __device__ __forceinline__ int setup_octagon(const float2* __restrict__ pts, uin
 // ---------------------------------------------------------------------------
 
 // The binary64 rule: strictly inside every edge (mode == 1 implies m >= 3).
-template <int NV>
-__device__ __forceinline__ bool contract_inside(const Poly<NV>* __restrict__ o, float px, float py) {
+// P points to the polygon record in any address space; in the constant one
+// the edge data come in by scalar loads, whose wait does not also wait for
+// the vector loads in flight.
+template <int NV, typename P>
+__device__ __forceinline__ bool contract_inside(P o, float px, float py) {
 #pragma clang fp contract(off)
     const double x = px, y = py;
     bool in = true;
@@ -759,7 +762,7 @@ __device__ __forceinline__ bool keep_point(const Poly<NV>* __restrict__ o, const
         if (mn < -1.0f) return true;
         if (mn > 2.0f) return false;
     }
-    return !contract_inside(o, x, y);
+    return !contract_inside<NV>(o, x, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -808,78 +811,114 @@ __device__ __forceinline__ uint32_t load_sub(const float2* __restrict__ pts, uin
     return validm;
 }
 
-// Inside test of one loaded sub-tile; returns the keep mask (bit 2j+h).
-// Points in the uncertain band are re-read by index and take the binary64
-// rule itself.
-template <int BLOCK, int PPT, int NV>
-__device__ __forceinline__ uint32_t classify_sub(const Poly<NV>* __restrict__ o, const EdgeRegsN<NV>& ek,
-                                                 const float2* __restrict__ pts, uint64_t sb,
-                                                 const float4 (&q)[PPT / 2], uint32_t validm) {
-    constexpr int NP = PPT / 2;
-    const uint32_t t = threadIdx.x;
-    if (ek.mode == 0) return validm;
-    if (__ballot(validm != 0u) == 0ull) return 0u;   // every group of the wave skipped
-    uint32_t keepm = 0, pendm = 0;
-    const float bxl = ek.bxl, bxh = ek.bxh, byl = ek.byl, byh = ek.byh;
-    const bool fast = ek.fast != 0;
+// Inside test of NP loaded pair slots (lane l of slot j holds two
+// consecutive points of a 128-point group: q[j].xy the even one, q[j].zw the
+// odd one; bit 2j+h of validm marks point h valid, the same in every lane
+// when UNI; TEST = false: mode 0, every valid point is kept).  The
+// decisions are taken on wave masks: every comparison is balloted on its own
+// (a ballot of a comparison is the comparison's own lane mask) and the masks
+// are combined with scalar operations; the two masks left per slot are the
+// group's keep words (even points, odd points).  Lane j receives slot j's
+// words in (m0, m1) and `total` (uniform) gains the number of kept points.
+//
+// The scaled FP32 edge values come first; the quick-accept box and the
+// binary64 rule only for the points they leave undecided (rare).  The order
+// does not change a decision: a point inside the box has every scaled edge
+// value above -0.45, so the FP32 test never keeps it, and whatever it
+// discards the rule discards.  Testing the box first would only spare the
+// edge values of pair slots whose points all lie in the box, which the
+// region skip already spares on clouds, and costs a test per point on data
+// that mostly survives.
+template <int NP, int NV, bool UNI, bool TEST = true>
+__device__ __forceinline__ void keep_masks(const Poly<NV>* __restrict__ o, const EdgeRegsN<NV>& ek,
+                                           const float4 (&q)[NP], uint32_t validm, unsigned long long& m0,
+                                           unsigned long long& m1, uint32_t& total) {
+    const uint32_t lane = lane_id();
+    if (UNI) validm = uniform_u32(validm);
+    const unsigned long long live = __ballot(1);
+    uint32_t e0lo = 0, e0hi = 0, e1lo = 0, e1hi = 0;
+    if (__ballot(validm != 0u) != 0ull) {   // else every group of the wave was skipped
+        const bool fast = ek.fast != 0;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const bool ok0 = (validm >> (2 * j)) & 1u, ok1 = (validm >> (2 * j + 1)) & 1u;
-        const bool in0 = (bxl < q[j].x) & (q[j].x < bxh) & (byl < q[j].y) & (q[j].y < byh);
-        const bool in1 = (bxl < q[j].z) & (q[j].z < bxh) & (byl < q[j].w) & (q[j].w < byh);
-        const bool need0 = ok0 & !in0, need1 = ok1 & !in1;
-        // wave-uniform branch: skipped when every point of the pair slot is
-        // inside the quick-accept box (most of a normal cloud)
-        if (__ballot(need0 | need1) != 0ull) {
-            uint32_t k2 = 0, p2 = 0;
-            if (fast) {
-                const float mn0 = edge_min(ek, q[j].x, q[j].y);
-                const float mn1 = edge_min(ek, q[j].z, q[j].w);
-                k2 = ((need0 & (mn0 < -1.0f)) ? 1u : 0u) | ((need1 & (mn1 < -1.0f)) ? 2u : 0u);
-                p2 = ((need0 & !(mn0 < -1.0f) & !(mn0 > 2.0f)) ? 1u : 0u) |
-                     ((need1 & !(mn1 < -1.0f) & !(mn1 > 2.0f)) ? 2u : 0u);
+        for (int j = 0; j < NP; ++j) {
+            unsigned long long v0, v1;   // valid points
+            if (UNI) {
+                v0 = ((validm >> (2 * j)) & 1u) ? live : 0ull;
+                v1 = ((validm >> (2 * j + 1)) & 1u) ? live : 0ull;
             } else {
-                p2 = (need0 ? 1u : 0u) | (need1 ? 2u : 0u);
+                v0 = __ballot(((validm >> (2 * j)) & 1u) != 0u);
+                v1 = __ballot(((validm >> (2 * j + 1)) & 1u) != 0u);
             }
-            keepm |= k2 << (2 * j);
-            pendm |= p2 << (2 * j);
+            unsigned long long b0 = v0, b1 = v1;   // mode 0 keeps every point
+            if (TEST && (v0 | v1) != 0ull) {
+                unsigned long long u0 = v0, u1 = v1;   // undecided
+                b0 = 0ull;
+                b1 = 0ull;
+                if (fast) {
+                    const float mn0 = edge_min(ek, q[j].x, q[j].y);
+                    const float mn1 = edge_min(ek, q[j].z, q[j].w);
+                    const unsigned long long o0 = __ballot(mn0 < -1.0f), o1 = __ballot(mn1 < -1.0f);
+                    b0 = v0 & o0;
+                    b1 = v1 & o1;
+                    u0 = v0 & ~o0 & ~__ballot(mn0 > 2.0f);
+                    u1 = v1 & ~o1 & ~__ballot(mn1 > 2.0f);
+                }
+                if ((u0 | u1) != 0ull) {   // the quick-accept box, then the binary64 rule
+                    const float bxl = ek.bxl, bxh = ek.bxh, byl = ek.byl, byh = ek.byh;
+                    const bool in0 = (bxl < q[j].x) & (q[j].x < bxh) & (byl < q[j].y) & (q[j].y < byh);
+                    const bool in1 = (bxl < q[j].z) & (q[j].z < bxh) & (byl < q[j].w) & (q[j].w < byh);
+                    // an opaque copy of the pointer keeps the compiler from
+                    // hoisting the binary64 edge data into registers
+                    PolyK<NV>* oo = as_const(o);
+                    asm volatile("" : "+s"(oo));
+                    const bool p0 = ((u0 >> lane) & 1ull) && !in0, p1 = ((u1 >> lane) & 1ull) && !in1;
+                    b0 |= __ballot(p0 && !contract_inside<NV>(oo, q[j].x, q[j].y));
+                    b1 |= __ballot(p1 && !contract_inside<NV>(oo, q[j].z, q[j].w));
+                }
+            }
+            total += (uint32_t)(__popcll(b0) + __popcll(b1));
+            if (lane == (uint32_t)j) {
+                e0lo = (uint32_t)b0;
+                e0hi = (uint32_t)(b0 >> 32);
+                e1lo = (uint32_t)b1;
+                e1hi = (uint32_t)(b1 >> 32);
+            }
         }
     }
-    // uncertain band: one point per lane per round (rare)
-    const float2* __restrict__ tp = pts + sb;
-    while (__ballot(pendm != 0u) != 0ull) {
-        if (pendm) {
-            const int b = __ffs(pendm) - 1;
-            pendm &= pendm - 1u;
-            const float2 pt = *reinterpret_cast<const float2*>(
-                reinterpret_cast<const char*>(tp) + 16u * ((uint32_t)(b >> 1) * BLOCK + opaque_tid()) +
-                8u * (uint32_t)(b & 1));
-            // an opaque copy of the pointer keeps the compiler from hoisting
-            // the binary64 edge data into registers on the hot path
-            const Poly<NV>* oo = o;
-            asm volatile("" : "+s"(oo));
-            if (!contract_inside(oo, pt.x, pt.y)) keepm |= 1u << b;
-        }
-    }
-    return keepm;
+    m0 = ((unsigned long long)e0hi << 32) | e0lo;
+    m1 = ((unsigned long long)e1hi << 32) | e1lo;
 }
 
-// Keep words of a wave's NP pair slots: bit 2j+h of k (per lane) is point h
-// of slot j.  Lane j receives slot j's two ballots (word for the even points,
-// word for the odd ones); `total` (uniform) gains the number of kept points.
-template <int NP>
-__device__ __forceinline__ void keep_words(uint32_t k, unsigned long long& m0, unsigned long long& m1,
-                                           uint32_t& total) {
-    const uint32_t lane = lane_id();
+// Load and test one sub-tile of the range [lo, hi) (skipm: pair slots whose
+// groups the region skip discards, full sub-tiles only): the wave's keep
+// words in (m0, m1) as keep_masks gives them.  A full sub-tile with nothing
+// skipped (every sub-tile of circle-like data) is one straight run of loads
+// followed by the tests, so the test of slot j waits only for slot j's load
+// and not for the whole sub-tile.
+template <int BLOCK, int PPT, bool VEC4, int NV>
+__device__ __forceinline__ void classify_tile(const Poly<NV>* __restrict__ o, const EdgeRegsN<NV>& ek,
+                                              const float2* __restrict__ pts, uint64_t lo, uint64_t hi,
+                                              uint64_t sb, uint32_t skipm, unsigned long long& m0,
+                                              unsigned long long& m1, uint32_t& total) {
+    constexpr int NP = PPT / 2;
+    constexpr uint32_t ST = BLOCK * PPT;
+    float4 q[NP];
+    if (ek.mode == 0) {   // fewer than three distinct vertices: every point survives
+        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, sb, q, skipm);
+        keep_masks<NP, NV, false, false>(o, ek, q, validm, m0, m1, total);
+    } else if (sb >= lo && sb + ST <= hi) {
+        if (skipm == 0u) {
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + sb, ST * 8u);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const unsigned long long b0 = __ballot((k >> (2 * j)) & 1u);
-        const unsigned long long b1 = __ballot((k >> (2 * j + 1)) & 1u);
-        if (lane == (uint32_t)j) {
-            m0 = b0;
-            m1 = b1;
+            for (int j = 0; j < NP; ++j) q[j] = load_pair_buf<VEC4>(rs, 16u * threadIdx.x, 16u * j * BLOCK);
+            keep_masks<NP, NV, true>(o, ek, q, (NP == 16) ? 0xFFFFFFFFu : ((1u << (2 * NP)) - 1u), m0, m1, total);
+        } else {
+            const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, sb, q, skipm);
+            keep_masks<NP, NV, true>(o, ek, q, validm, m0, m1, total);   // the same in every lane
         }
-        total += (uint32_t)(__popcll(b0) + __popcll(b1));
+    } else {
+        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, sb, q, 0u);
+        keep_masks<NP, NV, false>(o, ek, q, validm, m0, m1, total);
     }
 }
 
@@ -1255,51 +1294,6 @@ __device__ __forceinline__ uint32_t load_groups(const float2* __restrict__ pts, 
     return validm;
 }
 
-// classify_sub for listed groups: the same decisions, with the uncertain
-// band re-read from the listed group's own base.
-template <int NP, int NV>
-__device__ __forceinline__ uint32_t classify_groups(const Poly<NV>* __restrict__ o, const EdgeRegsN<NV>& ek,
-                                                    const float2* __restrict__ pts, const uint32_t* list,
-                                                    const float4 (&q)[NP], uint32_t validm) {
-    if (ek.mode == 0) return validm;
-    uint32_t keepm = 0, pendm = 0;
-    const float bxl = ek.bxl, bxh = ek.bxh, byl = ek.byl, byh = ek.byh;
-    const bool fast = ek.fast != 0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const bool ok0 = (validm >> (2 * j)) & 1u, ok1 = (validm >> (2 * j + 1)) & 1u;
-        const bool in0 = (bxl < q[j].x) & (q[j].x < bxh) & (byl < q[j].y) & (q[j].y < byh);
-        const bool in1 = (bxl < q[j].z) & (q[j].z < bxh) & (byl < q[j].w) & (q[j].w < byh);
-        const bool need0 = ok0 & !in0, need1 = ok1 & !in1;
-        if (__ballot(need0 | need1) != 0ull) {
-            uint32_t k2 = 0, p2 = 0;
-            if (fast) {
-                const float mn0 = edge_min(ek, q[j].x, q[j].y);
-                const float mn1 = edge_min(ek, q[j].z, q[j].w);
-                k2 = ((need0 & (mn0 < -1.0f)) ? 1u : 0u) | ((need1 & (mn1 < -1.0f)) ? 2u : 0u);
-                p2 = ((need0 & !(mn0 < -1.0f) & !(mn0 > 2.0f)) ? 1u : 0u) |
-                     ((need1 & !(mn1 < -1.0f) & !(mn1 > 2.0f)) ? 2u : 0u);
-            } else {
-                p2 = (need0 ? 1u : 0u) | (need1 ? 2u : 0u);
-            }
-            keepm |= k2 << (2 * j);
-            pendm |= p2 << (2 * j);
-        }
-    }
-    while (__ballot(pendm != 0u) != 0ull) {
-        if (pendm) {
-            const int b = __ffs(pendm) - 1;
-            pendm &= pendm - 1u;
-            const uint64_t g = list[b >> 1];
-            const uint32_t ln = opaque_tid() & 63u;
-            const float2 pt = pts[128ull * g + 2u * ln + (uint32_t)(b & 1)];
-            const Poly<NV>* oo = o;
-            asm volatile("" : "+s"(oo));
-            if (!contract_inside(oo, pt.x, pt.y)) keepm |= 1u << b;
-        }
-    }
-    return keepm;
-}
 
 template <int BLOCK, int PPT, bool VEC4, int NV>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_classify(
@@ -1329,22 +1323,36 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     const bool skipon = box != nullptr && ok->mode == 1 && ok->skip != 0;
     const uint64_t w0 = r0 >> 15;
     const uint32_t nw = (uint32_t)min<uint64_t>(((r1 + 32767u) >> 15) - w0, kSkipWords);
+    const EdgeRegsN<NV> ek = load_edges(oct);
+    // any skip bit set in the block's words (else no group is skipped)
+    bool anyskip = false;
     if (skipon) {
         for (uint32_t i = threadIdx.x; i < nw * 64u; i += BLOCK) {
             const uint64_t bi = (w0 << 6) + i;
-            const bool pass = bi < nbox && box_inside<NV>(box[bi], ok);
+            bool pass = false;
+            if (bi < nbox) {
+                const float4 b = box[bi];
+                // FP32 screen: a corner with a scaled edge value below -1 lies
+                // outside that edge (the rule keeps it), so the box fails;
+                // only the others take the binary64 corner test
+                const bool outside = ek.fast != 0 && min(min(edge_min(ek, b.x, b.z), edge_min(ek, b.y, b.z)),
+                                                         min(edge_min(ek, b.x, b.w), edge_min(ek, b.y, b.w))) < -1.0f;
+                pass = !outside && box_inside<NV>(b, ok);
+            }
             const unsigned long long m = __ballot(pass);
             if (lane == 0) sh_skip[i >> 6] = m;
         }
         __syncthreads();
+        unsigned long long any = 0ull;
+        for (uint32_t i = 0; i < nw; ++i) any |= sh_skip[i];
+        anyskip = any != 0ull;
     }
-    const EdgeRegsN<NV> ek = load_edges(oct);
     uint32_t total = 0, groups = 0;
     // Sparse inside test: list the groups to read (lane per group) and
     // decide whether the block takes the listed path.
     bool sparse = false;
     const uint64_t g0 = r0 >> 7, g1 = (r1 + 127) >> 7;
-    if (skipon) {
+    if (anyskip) {
         if (threadIdx.x == 0) sh_nlist = 0u;
         __syncthreads();
         for (uint64_t gb = g0 + (uint64_t)wave * 64u; gb < g1; gb += (uint64_t)NW * 64u) {
@@ -1368,9 +1376,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
             const uint32_t cnt = min((uint32_t)NP, nl - b);
             float4 q[NP];
             const uint32_t validm = load_groups<NP, VEC4>(pts, n, sh_list + b, cnt, q);
-            const uint32_t k = classify_groups<NP, NV>(oct, ek, pts, sh_list + b, q, validm);
-            unsigned long long m0 = 0ull, m1 = 0ull;
-            if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);
+            unsigned long long m0, m1;
+            keep_masks<NP, NV, false>(oct, ek, q, validm, m0, m1, total);
             if (lane < cnt) {
                 const uint64_t g = sh_list[b + lane];
                 *reinterpret_cast<ulonglong2*>(bits + 2 * g) = make_ulonglong2(m0, m1);
@@ -1393,10 +1400,46 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
             }
         }
     }
-    for (uint64_t sb = r0; !sparse && sb < r1; sb += ST) {
+    // Dense blocks (no group of the range skipped: every block of circle-like
+    // data): the loads of sub-tile i+1 are issued before sub-tile i is
+    // tested, so a wave keeps a sub-tile of loads in flight while it
+    // computes (two register buffers, used in turn).
+    const bool dense = !anyskip && NP <= 4;   // two buffers of 8 slots would not fit the register budget
+    uint64_t rs0 = r0;   // where the sub-tile loop below starts
+    if (dense) {
+        constexpr uint32_t allv = (NP == 16) ? 0xFFFFFFFFu : ((1u << (2 * NP)) - 1u);
+        const uint64_t rf = r0 + ((r1 - r0) / ST) * ST;   // end of the full sub-tiles
+        // past rf the descriptor is empty: the loads return zeros and read nothing
+        auto load = [&](uint64_t sb, float4(&q)[NP]) {
+            const bool in = sb < rf;
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + (in ? sb : 0), in ? ST * 8u : 0u);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) q[j] = load_pair_buf<VEC4>(rs, 16u * threadIdx.x, 16u * j * BLOCK);
+        };
+        auto test_store = [&](uint64_t sb, const float4(&q)[NP]) {
+            unsigned long long m0, m1;
+            keep_masks<NP, NV, true>(oct, ek, q, allv, m0, m1, total);
+            const uint64_t g = (sb >> 7) + (uint64_t)(lane * NW + wave);
+            if (lane < (uint32_t)NP) *reinterpret_cast<ulonglong2*>(bits + 2 * g) = make_ulonglong2(m0, m1);
+            groups += (uint32_t)NP;
+        };
+        if (NP <= 4 && rf > r0) {
+            float4 qa[NP], qb[NP];
+            load(r0, qa);
+            for (uint64_t sb = r0; sb < rf; sb += 2ull * ST) {
+                load(sb + ST, qb);
+                test_store(sb, qa);
+                if (sb + ST >= rf) break;
+                load(sb + 2ull * ST, qa);
+                test_store(sb + ST, qb);
+            }
+        }
+        rs0 = rf;   // the partial sub-tile, if any
+    }
+    for (uint64_t sb = rs0; !sparse && sb < r1; sb += ST) {
         uint32_t skipm = 0;
         const uint64_t rel = (sb >> 15) - w0;
-        if (skipon && sb + ST <= n && rel < nw) {
+        if (anyskip && sb + ST <= n && rel < nw) {
             // this sub-tile's boxes are 4*ST/2048 consecutive bits of one word
             const uint64_t word = sh_skip[rel];
 #pragma unroll
@@ -1407,13 +1450,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
             }
         }
         groups += (uint32_t)(NP - __popc(skipm));
-        float4 q[NP];
-        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q, skipm);
-        const uint32_t k = classify_sub<BLOCK, PPT, NV>(oct, ek, pts, sb, q, validm);
-        // lane j keeps the two ballots of pair slot j, then all NP groups
+        // lane j holds the two keep words of pair slot j, then all NP groups
         // of this wave are stored by one instruction
-        unsigned long long m0 = 0ull, m1 = 0ull;
-        if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);   // else the wave kept nothing
+        unsigned long long m0, m1;
+        classify_tile<BLOCK, PPT, VEC4, NV>(oct, ek, pts, 0, n, sb, skipm, m0, m1, total);
         const uint64_t g = (sb >> 7) + (uint64_t)(lane * NW + wave);
         if (lane < (uint32_t)NP && g < ngroups) {
             ulonglong2 v;
@@ -1727,11 +1767,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
     uint32_t total = 0;
     unsigned long long m0 = 0ull, m1 = 0ull;
     if (tskip != 0xFFFFu) {
-        float4 q[NP];
-        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, 0, n, sb, q, full ? skipm : 0u);
         const EdgeRegsN<NV> ek = load_edges(oct);
-        const uint32_t k = classify_sub<BLOCK, PPT, NV>(oct, ek, pts, sb, q, validm);
-        if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);
+        classify_tile<BLOCK, PPT, VEC4, NV>(oct, ek, pts, 0, n, sb, full ? skipm : 0u, m0, m1, total);
     }
     if (lane < (uint32_t)NP) {
         const uint32_t g = lane * NW + wave;
@@ -2037,11 +2074,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
                         skipm |= (uint32_t)((word >> ((gg >> 4) * 4u + (gg & 3u))) & 1ull) << j;
                     }
                 }
-                float4 q[NP];
-                const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, b, hi, sb, q, skipm);
-                const uint32_t k = classify_sub<BLOCK, PPT, 8>(o, ek, pts, sb, q, validm);
-                unsigned long long m0 = 0ull, m1 = 0ull;
-                if (__ballot(k != 0u) != 0ull) keep_words<NP>(k, m0, m1, total);   // else the wave kept nothing
+                unsigned long long m0, m1;
+                classify_tile<BLOCK, PPT, VEC4, 8>(o, ek, pts, b, hi, sb, skipm, m0, m1, total);
                 const uint32_t g = (uint32_t)((sb - r0) >> 7) + lane * NW + wave;
                 if (lane < (uint32_t)NP) {
                     ulonglong2 v;
