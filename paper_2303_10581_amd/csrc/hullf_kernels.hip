@@ -863,7 +863,7 @@ __device__ __forceinline__ void keep_masks(const Poly<NV>* __restrict__ o, const
                     u0 = v0 & ~o0 & ~__ballot(mn0 > 2.0f);
                     u1 = v1 & ~o1 & ~__ballot(mn1 > 2.0f);
                 }
-                if ((u0 | u1) != 0ull) {   // the quick-accept box, then the binary64 rule
+                if (__builtin_expect((u0 | u1) != 0ull, 0)) {   // the quick-accept box, then the binary64 rule
                     const float bxl = ek.bxl, bxh = ek.bxh, byl = ek.byl, byh = ek.byh;
                     const bool in0 = (bxl < q[j].x) & (q[j].x < bxh) & (byl < q[j].y) & (q[j].y < byh);
                     const bool in1 = (bxl < q[j].z) & (q[j].z < bxh) & (byl < q[j].w) & (q[j].w < byh);
@@ -889,6 +889,42 @@ __device__ __forceinline__ void keep_masks(const Poly<NV>* __restrict__ o, const
     m1 = ((unsigned long long)e1hi << 32) | e1lo;
 }
 
+// Keep words of one sub-tile, as keep_masks gives them: (m0, m1) per lane,
+// total (uniform) the number of kept points.
+struct TileOut {
+    unsigned long long m0, m1;
+    uint32_t total;
+};
+
+// The sub-tiles that are not a full run of unskipped groups of a polygon in
+// mode 1 (a partial last sub-tile, skipped groups, mode 0): out of line, so
+// the kernel's hot loop stays a short run of code (a copy of the unrolled
+// test per sub-tile kind had made the kernel ~10 000 instructions, beyond
+// the instruction cache).
+template <int BLOCK, int PPT, bool VEC4, int NV>
+__device__ __attribute__((noinline)) TileOut classify_tile_cold(const Poly<NV>* __restrict__ o,
+                                                               const float2* __restrict__ pts, uint64_t lo,
+                                                               uint64_t hi, uint64_t sb, uint32_t skipm) {
+    constexpr int NP = PPT / 2;
+    constexpr uint32_t ST = BLOCK * PPT;
+    // the arguments of a call arrive in vector registers: the uniform ones
+    // go back to scalar registers (buffer descriptors and scalar loads)
+    o = reinterpret_cast<const Poly<NV>*>(uniform_u64(reinterpret_cast<uint64_t>(o)));
+    pts = reinterpret_cast<const float2*>(uniform_u64(reinterpret_cast<uint64_t>(pts)));
+    lo = uniform_u64(lo);
+    hi = uniform_u64(hi);
+    sb = uniform_u64(sb);
+    skipm = uniform_u32(skipm);
+    const EdgeRegsN<NV> ek = load_edges(o);
+    float4 q[NP];
+    TileOut r{0ull, 0ull, 0u};
+    const bool full = sb >= lo && sb + ST <= hi;
+    const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, sb, q, full ? skipm : 0u);
+    if (ek.mode == 0) keep_masks<NP, NV, false, false>(o, ek, q, validm, r.m0, r.m1, r.total);
+    else keep_masks<NP, NV, false>(o, ek, q, validm, r.m0, r.m1, r.total);
+    return r;
+}
+
 // Load and test one sub-tile of the range [lo, hi) (skipm: pair slots whose
 // groups the region skip discards, full sub-tiles only): the wave's keep
 // words in (m0, m1) as keep_masks gives them.  A full sub-tile with nothing
@@ -902,23 +938,17 @@ __device__ __forceinline__ void classify_tile(const Poly<NV>* __restrict__ o, co
                                               unsigned long long& m1, uint32_t& total) {
     constexpr int NP = PPT / 2;
     constexpr uint32_t ST = BLOCK * PPT;
-    float4 q[NP];
-    if (ek.mode == 0) {   // fewer than three distinct vertices: every point survives
-        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, sb, q, skipm);
-        keep_masks<NP, NV, false, false>(o, ek, q, validm, m0, m1, total);
-    } else if (sb >= lo && sb + ST <= hi) {
-        if (skipm == 0u) {
-            const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + sb, ST * 8u);
+    if (ek.mode != 0 && skipm == 0u && sb >= lo && sb + ST <= hi) {
+        float4 q[NP];
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + sb, ST * 8u);
 #pragma unroll
-            for (int j = 0; j < NP; ++j) q[j] = load_pair_buf<VEC4>(rs, 16u * threadIdx.x, 16u * j * BLOCK);
-            keep_masks<NP, NV, true>(o, ek, q, (NP == 16) ? 0xFFFFFFFFu : ((1u << (2 * NP)) - 1u), m0, m1, total);
-        } else {
-            const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, sb, q, skipm);
-            keep_masks<NP, NV, true>(o, ek, q, validm, m0, m1, total);   // the same in every lane
-        }
+        for (int j = 0; j < NP; ++j) q[j] = load_pair_buf<VEC4>(rs, 16u * threadIdx.x, 16u * j * BLOCK);
+        keep_masks<NP, NV, true>(o, ek, q, (NP == 16) ? 0xFFFFFFFFu : ((1u << (2 * NP)) - 1u), m0, m1, total);
     } else {
-        const uint32_t validm = load_sub<BLOCK, PPT, VEC4>(pts, lo, hi, sb, q, 0u);
-        keep_masks<NP, NV, false>(o, ek, q, validm, m0, m1, total);
+        const TileOut r = classify_tile_cold<BLOCK, PPT, VEC4, NV>(o, pts, lo, hi, sb, skipm);
+        m0 = r.m0;
+        m1 = r.m1;
+        total += uniform_u32(r.total);
     }
 }
 
@@ -1371,13 +1401,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     }
     if (sparse) {
         const uint32_t nl = sh_nlist;
-        // the listed groups, NP per wave at a time
-        for (uint32_t b = wave * (uint32_t)NP; b < nl; b += (uint32_t)(NW * NP)) {
-            const uint32_t cnt = min((uint32_t)NP, nl - b);
-            float4 q[NP];
-            const uint32_t validm = load_groups<NP, VEC4>(pts, n, sh_list + b, cnt, q);
+        // the listed groups, NPL per wave at a time (8 whatever the sub-tile
+        // shape: the list is short, and a round of loads is a memory round trip)
+        constexpr int NPL = 8;
+        for (uint32_t b = wave * (uint32_t)NPL; b < nl; b += (uint32_t)(NW * NPL)) {
+            const uint32_t cnt = min((uint32_t)NPL, nl - b);
+            float4 q[NPL];
+            const uint32_t validm = load_groups<NPL, VEC4>(pts, n, sh_list + b, cnt, q);
             unsigned long long m0, m1;
-            keep_masks<NP, NV, false>(oct, ek, q, validm, m0, m1, total);
+            keep_masks<NPL, NV, false>(oct, ek, q, validm, m0, m1, total);
             if (lane < cnt) {
                 const uint64_t g = sh_list[b + lane];
                 *reinterpret_cast<ulonglong2*>(bits + 2 * g) = make_ulonglong2(m0, m1);
