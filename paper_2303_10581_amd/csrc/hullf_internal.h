@@ -56,7 +56,8 @@ struct alignas(16) SetInfo {
 struct alignas(16) BatchTotals {
     uint32_t r_tiles;
     uint32_t f_tiles;
-    uint32_t pad[2];
+    uint32_t r_next;   // reduction-tile tickets handed out (reset by the plan)
+    uint32_t pad;
 };
 
 constexpr uint64_t kCountNonFinite = ~0ull;

@@ -275,8 +275,8 @@ __device__ __forceinline__ uint32_t opaque_tid() {
 }
 
 // Reduction of points [lo, hi) over chunks c = c0, c0+cstep, ... < nch of
-// CH = BLOCK*G*2 points starting at the pair-aligned base al (lo - 1 <= al
-// <= lo).  On return (all threads), rec[j] (j < 8) holds the block's packed
+// CH = BLOCK*G*2 points starting at the even base al <= lo (with DEFER,
+// lo - 1 <= al: the recorded position must not be negative).  On return (all threads), rec[j] (j < 8) holds the block's packed
 // (key, position) for direction j, or 0 if the block saw no point, and
 // rec[8] is 1 if a NaN was seen.  The position is the lowest index relative
 // to lo attaining the key (DEFER false), or, with DEFER, the chunk holding
@@ -359,15 +359,23 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
                 const float qn = __builtin_nanf("");
                 put_box(c, make_float4(qn, qn, qn, qn));
             }
+            // a partial chunk: all 2G loads issued before any is used (one
+            // memory round trip); the descriptor ends at the range's end, so
+            // loads past it read nothing, and points before lo are masked
             const RangeView rv = range_view(pts, cb, CH, lo, hi);
             const uint32_t tt = opaque_tid();
-#pragma unroll 1
+            float2 pq[2 * G];
+#pragma unroll
             for (uint32_t k = 0; k < 2 * G; ++k) {
-                bool ok;
                 const uint32_t p = 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
-                const float2 q = load_point_checked(rv.r, p, rv.lo_rel, rv.hi_rel, ok);
-                if (!ok) continue;
-                const float x = q.x, y = q.y;
+                const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(rv.r, (int)(8u * p), 0, 0);
+                pq[k] = make_float2(__uint_as_float(a.x), __uint_as_float(a.y));
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < 2 * G; ++k) {
+                const uint32_t p = 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
+                if (p < rv.lo_rel || p >= rv.hi_rel) continue;
+                const float x = pq[k].x, y = pq[k].y;
                 const float s = x + y, d = x - y;
                 bad |= __builtin_isnan(s);
                 if (x > v[0]) { v[0] = x; grp[0] = c; }
@@ -1866,7 +1874,7 @@ __global__ __launch_bounds__(256) void k_gather(const float2* __restrict__ pts,
 // Sets are CSR ranges of one point array (or a list of (begin, count)
 // segments).  Launch 1 (plan, one block) cuts every set into reduction tiles
 // of kBatchRT points and work items of kBatchItem points (both counted from
-// the set's pair-aligned start) and computes their prefix counts.  Launch 2
+// the set's start rounded down to 16 points) and computes their prefix counts.  Launch 2
 // streams all reduction tiles and writes one partial record per tile (and
 // the tiles' region-skip boxes); launch 3 merges each set's records and
 // builds its octagon (one wave per set); launch 4 runs the inside test on
@@ -1874,7 +1882,13 @@ __global__ __launch_bounds__(256) void k_gather(const float2* __restrict__ pts,
 // every item at its offset inside its set.  Cross-block results only flow
 // across launch boundaries, so no kernel needs a device-wide fence.
 
-constexpr uint32_t kBatchRChunks = 4;
+// A set's tiles and work items are counted from its first point rounded
+// down to a multiple of 16 points (128 bytes), so that every full chunk a
+// wave loads is line-aligned (measured on one 1e8 set: 16-byte-aligned
+// chunks that straddle lines cost up to 8 % in the reduction); the points
+// before the set's start are masked like any point outside the set.
+constexpr uint64_t kBatchAlign = 15;
+constexpr uint32_t kBatchRChunks = 16;
 constexpr uint32_t kBatchRT = kRBlock * kRG * 2 * kBatchRChunks;   // reduction tile (points)
 constexpr uint32_t kBatchTileBoxes = 4 * kBatchRChunks;             // region-skip boxes per tile
 
@@ -1888,6 +1902,22 @@ __device__ __forceinline__ uint32_t set_of(const SetInfo* __restrict__ sets, uin
         else hi = mid - 1;
     }
     return lo;
+}
+
+// The sets of a block's next kAhead tiles (or work items) r0, r0 + step, ...
+// (those below lim), looked up by kAhead lanes at once: one round of binary
+// searches, all in flight together, instead of one dependent search per
+// tile.  sh[k] holds the set of tile r0 + k * step.
+constexpr uint32_t kAhead = 64;
+constexpr uint32_t kTicketTiles = 2;   // reduction tiles per ticket (at most kAhead)
+__device__ __forceinline__ void sets_ahead(const SetInfo* __restrict__ sets, uint32_t S, uint32_t r0, uint32_t step,
+                                           uint32_t lim, bool f, uint32_t* sh) {
+    __syncthreads();   // the previous round's readers of sh are done
+    if (threadIdx.x < kAhead) {
+        const uint64_t r = (uint64_t)r0 + (uint64_t)threadIdx.x * step;
+        sh[threadIdx.x] = (r < lim) ? set_of(sets, S, (uint32_t)r, f) : 0u;
+    }
+    __syncthreads();
 }
 
 // Exclusive scan of one value per thread over a block of 1024 threads;
@@ -1958,6 +1988,7 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
         if (t == 0) {
             tot->r_tiles = 0u;
             tot->f_tiles = 0u;
+            tot->r_next = 0u;
         }
         return;
     }
@@ -1969,7 +2000,7 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
             uint64_t e;
             set_span<SEG>(off, s, b, e);
             n = e - b;
-            const uint64_t al = b & ~1ull;
+            const uint64_t al = b & ~kBatchAlign;
             rt = n ? (uint32_t)((b + n - al + kBatchRT - 1) / kBatchRT) : 0u;
             fc = n ? (uint32_t)((b + n - al + ft - 1) / ft) : 0u;
         }
@@ -1990,22 +2021,38 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
     if (t == 0) {
         tot->r_tiles = fits ? rtiles : 0u;
         tot->f_tiles = fits ? ftiles : 0u;
+        tot->r_next = 0u;
     }
 }
 
 template <bool VEC4>
 __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_batch_reduce(
     const float2* __restrict__ pts, uint32_t S, const SetInfo* __restrict__ sets,
-    const BatchTotals* __restrict__ tot, unsigned long long* __restrict__ part, float4* __restrict__ box) {
+    BatchTotals* __restrict__ tot, unsigned long long* __restrict__ part, float4* __restrict__ box) {
+    // Tiles are handed out by ticket, kTicketTiles consecutive ones at a
+    // time, so blocks that drew small tiles (the last tile of a set) draw
+    // again instead of the grid waiting on a fixed share per block.  The
+    // next ticket is drawn before the current tiles are streamed.
     const uint32_t rtiles = tot->r_tiles;
-    for (uint32_t r = blockIdx.x; r < rtiles; r += gridDim.x) {
-        const uint32_t s = set_of(sets, S, r, false);
-        const uint64_t b = sets[s].begin, n = sets[s].n;
-        const uint64_t tb = (b & ~1ull) + (uint64_t)(r - sets[s].r_tile0) * kBatchRT;
-        __shared__ unsigned long long rec[9];
-        reduce_points<kRBlock, kRG, VEC4, false>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec,
-                                                 box ? box + (uint64_t)r * kBatchTileBoxes : nullptr);
-        if (threadIdx.x < 9) part[(uint64_t)r * 9 + threadIdx.x] = rec[threadIdx.x];
+    __shared__ uint32_t sh_set[kAhead];
+    __shared__ uint32_t sh_tk[2];
+    __shared__ unsigned long long rec[9];
+    if (threadIdx.x == 0) sh_tk[0] = atomicAdd(&tot->r_next, kTicketTiles);
+    for (uint32_t round = 0;; ++round) {
+        __syncthreads();   // this round's ticket is visible
+        const uint32_t r0 = sh_tk[round & 1u];
+        if (r0 >= rtiles) break;
+        if (threadIdx.x == 0) sh_tk[(round + 1) & 1u] = atomicAdd(&tot->r_next, kTicketTiles);
+        sets_ahead(sets, S, r0, 1u, rtiles, false, sh_set);
+        for (uint32_t k = 0; k < kTicketTiles && r0 + k < rtiles; ++k) {
+            const uint32_t r = r0 + k;
+            const uint32_t s = uniform_u32(sh_set[k]);
+            const uint64_t b = sets[s].begin, n = sets[s].n;
+            const uint64_t tb = (b & ~kBatchAlign) + (uint64_t)(r - sets[s].r_tile0) * kBatchRT;
+            reduce_points<kRBlock, kRG, VEC4, false>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec,
+                                                     box ? box + (uint64_t)r * kBatchTileBoxes : nullptr);
+            if (threadIdx.x < 9) part[(uint64_t)r * 9 + threadIdx.x] = rec[threadIdx.x];
+        }
     }
 }
 
@@ -2050,7 +2097,7 @@ __global__ __launch_bounds__(256) void k_batch_setup(const float2* __restrict__ 
 }
 
 // Two-pass compaction of a batch.  Every set is cut into work items of
-// kBatchItem points counted from its pair-aligned start al = begin & ~1
+// kBatchItem points counted from its start rounded down to 16 points
 // (SetInfo f_tiles / f_tile0 count items).  Item i owns kBatchItem/64 words
 // of keep bits (same layout as the single-set pass, groups counted from the
 // item's first point) and one survivor count.
@@ -2069,15 +2116,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     __shared__ uint32_t sh_w[NW];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint32_t items = tot->f_tiles;
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const uint32_t s = set_of(sets, S, it, true);
+    __shared__ uint32_t sh_set[kAhead];
+    for (uint64_t i0 = blockIdx.x; i0 < items; i0 += (uint64_t)gridDim.x * kAhead)
+    for (uint32_t k = 0; k < kAhead; ++k) {
+        if (k == 0) sets_ahead(sets, S, (uint32_t)i0, gridDim.x, items, true, sh_set);
+        const uint64_t ii = i0 + (uint64_t)k * gridDim.x;
+        if (ii >= items) break;
+        const uint32_t it = (uint32_t)ii;
+        const uint32_t s = uniform_u32(sh_set[k]);
         const Octagon* o = &octs[s];
         const EdgeRegs ek = load_edges(o);
         uint32_t total = 0;
         if (o->status == 0) {
             const uint64_t b = sets[s].begin, hi = b + sets[s].n;
             const uint32_t li = it - sets[s].f_tile0;
-            const uint64_t r0 = (b & ~1ull) + (uint64_t)li * kBatchItem;
+            const uint64_t r0 = (b & ~kBatchAlign) + (uint64_t)li * kBatchItem;
             const uint64_t r1 = min<uint64_t>(hi, r0 + kBatchItem);
             uint64_t* ib = bits + (uint64_t)it * (kBatchItem / 64);
             // Region skip: the item's 64 groups of 512 points have the 64
@@ -2145,8 +2198,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(uint32_t S, const SetIn
     __shared__ uint32_t sh_tot[NW];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint32_t items = tot->f_tiles;
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const uint32_t s = set_of(sets, S, it, true);
+    __shared__ uint32_t sh_set[kAhead];
+    for (uint64_t i0 = blockIdx.x; i0 < items; i0 += (uint64_t)gridDim.x * kAhead)
+    for (uint32_t k = 0; k < kAhead; ++k) {
+        if (k == 0) sets_ahead(sets, S, (uint32_t)i0, gridDim.x, items, true, sh_set);
+        const uint64_t ii = i0 + (uint64_t)k * gridDim.x;
+        if (ii >= items) break;
+        const uint32_t it = (uint32_t)ii;
+        const uint32_t s = uniform_u32(sh_set[k]);
         const uint32_t first = sets[s].f_tile0, li = it - first;
         const int ost = octs[s].status;
         if (ost != 0) {
@@ -2154,7 +2213,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(uint32_t S, const SetIn
             continue;
         }
         const uint64_t b = sets[s].begin, n = sets[s].n;
-        const uint64_t r0 = (b & ~1ull) + (uint64_t)li * kBatchItem;
+        const uint64_t r0 = (b & ~kBatchAlign) + (uint64_t)li * kBatchItem;
         const uint64_t r1 = min<uint64_t>(b + n, r0 + kBatchItem);
         const uint64_t sb = r0 + (uint64_t)wave * kSpan;
         // this wave's span words (issued before the offset sums below)
