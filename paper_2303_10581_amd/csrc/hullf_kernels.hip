@@ -1370,12 +1370,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
             bool pass = false;
             if (bi < nbox) {
                 const float4 b = box[bi];
-                // FP32 screen: a corner with a scaled edge value below -1 lies
-                // outside that edge (the rule keeps it), so the box fails;
-                // only the others take the binary64 corner test
-                const bool outside = ek.fast != 0 && min(min(edge_min(ek, b.x, b.z), edge_min(ek, b.y, b.z)),
-                                                         min(edge_min(ek, b.x, b.w), edge_min(ek, b.y, b.w))) < -1.0f;
-                pass = !outside && box_inside<NV>(b, ok);
+                // FP32 screen of the corners: a scaled edge value below -1 at a
+                // corner means D < 0 there (the box fails); above 2 at all four
+                // corners on every edge means D > 24 u M_e > sm[e] there (the box
+                // passes, NaN never does); only the others take the binary64
+                // corner test
+                bool decided = false;
+                if (ek.fast != 0) {
+                    const float mn = min(min(edge_min(ek, b.x, b.z), edge_min(ek, b.y, b.z)),
+                                         min(edge_min(ek, b.x, b.w), edge_min(ek, b.y, b.w)));
+                    decided = (mn < -1.0f) || (mn > 2.0f);
+                    pass = mn > 2.0f;
+                }
+                if (!decided) pass = box_inside<NV>(b, ok);
             }
             const unsigned long long m = __ballot(pass);
             if (lane == 0) sh_skip[i >> 6] = m;
