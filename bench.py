@@ -779,6 +779,7 @@ def _serve(srv, pool, times, order):
     th.join()
     wall = time.perf_counter() - t0
     lat = np.array([late[k] * 1e3 + res[k][1]["done_us"] * 1e-3 for k in range(n)])
+    _serve.late_ms = late * 1e3   # submission lateness of the open-loop driver itself
     return lat, res, wall
 
 
@@ -845,6 +846,10 @@ def bench_serving(args):
                         "p50_ms": round(float(np.percentile(lat, 50)), 2),
                         "p99_ms": round(float(np.percentile(lat, 99)), 2)}
         log(f"[bench] serving capacity {cap:.1f} hulls/s (burst of {len(pool)})")
+        # one short open-loop run first, not recorded: the first run of the
+        # submitting loop (Python, timers) and of the server's paced path
+        wt, _, _, _ = workloads.arrivals(200, seed=9, qps=0.25 * cap)
+        _serve(srv, pool, wt, [k % len(pool) for k in range(200)])
         runs = []
         for frac in args.serve_fracs:
             qps = frac * cap
@@ -861,6 +866,8 @@ def bench_serving(args):
                 "qps": round(qps, 1), "load": frac, "requests": m,
                 "p50_ms": round(float(np.percentile(lat, 50)), 2),
                 "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "submit_late_ms": {"p50": round(float(np.percentile(_serve.late_ms, 50)), 3),
+                                   "p99": round(float(np.percentile(_serve.late_ms, 99)), 3)},
                 "hulls_per_s": round(m / wall, 1),
                 "mean_batch_requests": round((st1["batched_requests"] - st0["batched_requests"]) / max(nb, 1), 2),
                 "gpu_busy_frac": round((st1["batch_ms"] - st0["batch_ms"]) / 1e3 / wall, 4),
