@@ -2033,7 +2033,10 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
 }
 
 template <bool VEC4>
-__global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_batch_reduce(
+// Four waves per SIMD: with the ticket and look-up state the kernel does not
+// fit 64 registers (at 8 waves per SIMD it spilled 52-68 bytes per lane
+// inside the streaming loop; 745-800 us against 640-750 us now).
+__global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_reduce(
     const float2* __restrict__ pts, uint32_t S, const SetInfo* __restrict__ sets,
     BatchTotals* __restrict__ tot, unsigned long long* __restrict__ part, float4* __restrict__ box) {
     // Tiles are handed out by ticket, kTicketTiles consecutive ones at a
@@ -2468,7 +2471,7 @@ hipError_t launch_batch(const float2* pts, const uint64_t* off, bool seg, uint32
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const bool v = is_vec4(pts);
-    const int rgrid = cus * (reduce_per_cu > 0 ? reduce_per_cu : 8);
+    const int rgrid = cus * (reduce_per_cu > 0 ? reduce_per_cu : 4);   // the occupancy k_batch_reduce allows
     if (v)
         hipLaunchKernelGGL(k_batch_reduce<true>, dim3(rgrid), dim3(kRBlock), 0, stream, pts, S, sets, tot, part,
                            box);
