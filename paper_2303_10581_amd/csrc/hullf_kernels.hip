@@ -1451,7 +1451,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     // data): the loads of sub-tile i+1 are issued before sub-tile i is
     // tested, so a wave keeps a sub-tile of loads in flight while it
     // computes (two register buffers, used in turn).
-    const bool dense = !anyskip && NP <= 4;   // two buffers of 8 slots would not fit the register budget
+    // (two buffers of 8 slots would not fit the register budget; mode 0 keeps
+    // every point and takes the out-of-line path)
+    const bool dense = !anyskip && NP <= 4 && ek.mode != 0;
     uint64_t rs0 = r0;   // where the sub-tile loop below starts
     if (dense) {
         constexpr uint32_t allv = (NP == 16) ? 0xFFFFFFFFu : ((1u << (2 * NP)) - 1u);
