@@ -285,7 +285,10 @@ __device__ __forceinline__ uint32_t opaque_tid() {
 // box (optional): box[c*NW + w] = (min x, max x, min y, max y) of the
 // points wave w read in chunk c -- groups 4k+w (k < G) of 128 points of the
 // chunk; NaN for a partial chunk.
-template <int BLOCK, int G, bool VEC4, bool DEFER>
+// PF: full chunks are loaded one chunk ahead (two register sets), so a wave
+// keeps two chunks of loads in flight; for callers that run at low
+// occupancy and have the registers to spare.
+template <int BLOCK, int G, bool VEC4, bool DEFER, bool PF = false>
 __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, uint64_t lo, uint64_t hi, uint64_t al,
                                               uint32_t c0, uint32_t cstep, uint32_t nch,
                                               unsigned long long* rec, float4* __restrict__ box) {
@@ -315,78 +318,180 @@ __device__ __forceinline__ void reduce_points(const float2* __restrict__ pts, ui
         }
     };
 
-    for (uint32_t c = c0; c < nch; c += cstep) {
+    auto full_at = [&](uint32_t c) {
         const uint64_t cb = al + (uint64_t)c * CH;
-        if (cb >= lo && cb + CH <= hi) {
-            static_assert(G == 4, "the hot loop folds 8 points per group");
-            const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + cb, CH * 8u);
-            float4 q[G];
+        return c < nch && cb >= lo && cb + CH <= hi;
+    };
+    auto fold_full = [&](uint32_t c, const float4* q) {
+        static_assert(G == 4, "the hot loop folds 8 points per group");
+        float xs[8], ys[8], ss[8], ds[8];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            xs[2 * k] = q[k].x;
+            ys[2 * k] = q[k].y;
+            xs[2 * k + 1] = q[k].z;
+            ys[2 * k + 1] = q[k].w;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            ss[i] = xs[i] + ys[i];
+            ds[i] = xs[i] - ys[i];
+        }
+        const float m0 = max8(xs), m1 = max8(ss), m2 = max8(ys), m3 = min8(ds);
+        const float m4 = min8(xs), m5 = min8(ss), m6 = min8(ys), m7 = max8(ds);
+        // maximum() propagates NaN: one test on the x+y maximum covers
+        // every NaN coordinate of the group
+        bad |= __builtin_isnan(m1);
+        if (m0 > v[0]) { v[0] = m0; grp[0] = c; }
+        if (m1 > v[1]) { v[1] = m1; grp[1] = c; }
+        if (m2 > v[2]) { v[2] = m2; grp[2] = c; }
+        if (m3 < v[3]) { v[3] = m3; grp[3] = c; }
+        if (m4 < v[4]) { v[4] = m4; grp[4] = c; }
+        if (m5 < v[5]) { v[5] = m5; grp[5] = c; }
+        if (m6 < v[6]) { v[6] = m6; grp[6] = c; }
+        if (m7 > v[7]) { v[7] = m7; grp[7] = c; }
+        if (box) {
+            const float b0 = wave_minmax_dpp<false>(m4), b1 = wave_minmax_dpp<true>(m0);
+            const float b2 = wave_minmax_dpp<false>(m6), b3 = wave_minmax_dpp<true>(m2);
+            put_box(c, make_float4(b0, b1, b2, b3));
+        }
+    };
+    auto fold_partial = [&](uint32_t c) {
+        const uint64_t cb = al + (uint64_t)c * CH;
+        if (box) {
+            const float qn = __builtin_nanf("");
+            put_box(c, make_float4(qn, qn, qn, qn));
+        }
+        // a partial chunk: all 2G loads issued before any is used (one
+        // memory round trip); the descriptor ends at the range's end, so
+        // loads past it read nothing, and points before lo are masked
+        const RangeView rv = range_view(pts, cb, CH, lo, hi);
+        const uint32_t tt = opaque_tid();
+        float2 pq[2 * G];
+#pragma unroll
+        for (uint32_t k = 0; k < 2 * G; ++k) {
+            const uint32_t p = 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
+            const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(rv.r, (int)(8u * p), 0, 0);
+            pq[k] = make_float2(__uint_as_float(a.x), __uint_as_float(a.y));
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 2 * G; ++k) {
+            const uint32_t p = 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
+            if (p < rv.lo_rel || p >= rv.hi_rel) continue;
+            const float x = pq[k].x, y = pq[k].y;
+            const float s = x + y, d = x - y;
+            bad |= __builtin_isnan(s);
+            if (x > v[0]) { v[0] = x; grp[0] = c; }
+            if (s > v[1]) { v[1] = s; grp[1] = c; }
+            if (y > v[2]) { v[2] = y; grp[2] = c; }
+            if (d < v[3]) { v[3] = d; grp[3] = c; }
+            if (x < v[4]) { v[4] = x; grp[4] = c; }
+            if (s < v[5]) { v[5] = s; grp[5] = c; }
+            if (y < v[6]) { v[6] = y; grp[6] = c; }
+            if (d > v[7]) { v[7] = d; grp[7] = c; }
+        }
+    };
+
+    if constexpr (!PF) {
+        // (the single-set pass keeps the folds written out here: with them as
+        // the shared lambdas above its 64-register build spills)
+        for (uint32_t c = c0; c < nch; c += cstep) {
+            const uint64_t cb = al + (uint64_t)c * CH;
+            if (cb >= lo && cb + CH <= hi) {
+                static_assert(G == 4, "the hot loop folds 8 points per group");
+                const __amdgpu_buffer_rsrc_t rs = make_rsrc(pts + cb, CH * 8u);
+                float4 q[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) q[k] = load_pair_buf<VEC4>(rs, 16u * t, 16u * k * BLOCK);
+                float xs[8], ys[8], ss[8], ds[8];
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    xs[2 * k] = q[k].x;
+                    ys[2 * k] = q[k].y;
+                    xs[2 * k + 1] = q[k].z;
+                    ys[2 * k + 1] = q[k].w;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    ss[i] = xs[i] + ys[i];
+                    ds[i] = xs[i] - ys[i];
+                }
+                const float m0 = max8(xs), m1 = max8(ss), m2 = max8(ys), m3 = min8(ds);
+                const float m4 = min8(xs), m5 = min8(ss), m6 = min8(ys), m7 = max8(ds);
+                // maximum() propagates NaN: one test on the x+y maximum covers
+                // every NaN coordinate of the group
+                bad |= __builtin_isnan(m1);
+                if (m0 > v[0]) { v[0] = m0; grp[0] = c; }
+                if (m1 > v[1]) { v[1] = m1; grp[1] = c; }
+                if (m2 > v[2]) { v[2] = m2; grp[2] = c; }
+                if (m3 < v[3]) { v[3] = m3; grp[3] = c; }
+                if (m4 < v[4]) { v[4] = m4; grp[4] = c; }
+                if (m5 < v[5]) { v[5] = m5; grp[5] = c; }
+                if (m6 < v[6]) { v[6] = m6; grp[6] = c; }
+                if (m7 > v[7]) { v[7] = m7; grp[7] = c; }
+                if (box) {
+                    const float b0 = wave_minmax_dpp<false>(m4), b1 = wave_minmax_dpp<true>(m0);
+                    const float b2 = wave_minmax_dpp<false>(m6), b3 = wave_minmax_dpp<true>(m2);
+                    put_box(c, make_float4(b0, b1, b2, b3));
+                }
+            } else {
+                if (box) {
+                    const float qn = __builtin_nanf("");
+                    put_box(c, make_float4(qn, qn, qn, qn));
+                }
+                // a partial chunk: all 2G loads issued before any is used (one
+                // memory round trip); the descriptor ends at the range's end, so
+                // loads past it read nothing, and points before lo are masked
+                const RangeView rv = range_view(pts, cb, CH, lo, hi);
+                const uint32_t tt = opaque_tid();
+                float2 pq[2 * G];
+#pragma unroll
+                for (uint32_t k = 0; k < 2 * G; ++k) {
+                    const uint32_t p = 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
+                    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(rv.r, (int)(8u * p), 0, 0);
+                    pq[k] = make_float2(__uint_as_float(a.x), __uint_as_float(a.y));
+                }
+#pragma unroll
+                for (uint32_t k = 0; k < 2 * G; ++k) {
+                    const uint32_t p = 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
+                    if (p < rv.lo_rel || p >= rv.hi_rel) continue;
+                    const float x = pq[k].x, y = pq[k].y;
+                    const float s = x + y, d = x - y;
+                    bad |= __builtin_isnan(s);
+                    if (x > v[0]) { v[0] = x; grp[0] = c; }
+                    if (s > v[1]) { v[1] = s; grp[1] = c; }
+                    if (y > v[2]) { v[2] = y; grp[2] = c; }
+                    if (d < v[3]) { v[3] = d; grp[3] = c; }
+                    if (x < v[4]) { v[4] = x; grp[4] = c; }
+                    if (s < v[5]) { v[5] = s; grp[5] = c; }
+                    if (y < v[6]) { v[6] = y; grp[6] = c; }
+                    if (d > v[7]) { v[7] = d; grp[7] = c; }
+                }
+            }
+        }
+    } else {
+        // Loads of chunk c are issued unconditionally, through a descriptor
+        // of zero records unless c is a full chunk (such loads read nothing
+        // and return zero): the loop stays straight-line, so each fold waits
+        // only for its own chunk's loads.
+        auto issue = [&](uint32_t c, float4* q) {
+            const bool f = full_at(c);
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(f ? (const void*)(pts + al + (uint64_t)c * CH) : (const void*)pts,
+                                                        f ? CH * 8u : 0u);
 #pragma unroll
             for (int k = 0; k < G; ++k) q[k] = load_pair_buf<VEC4>(rs, 16u * t, 16u * k * BLOCK);
-            float xs[8], ys[8], ss[8], ds[8];
-#pragma unroll
-            for (int k = 0; k < G; ++k) {
-                xs[2 * k] = q[k].x;
-                ys[2 * k] = q[k].y;
-                xs[2 * k + 1] = q[k].z;
-                ys[2 * k + 1] = q[k].w;
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                ss[i] = xs[i] + ys[i];
-                ds[i] = xs[i] - ys[i];
-            }
-            const float m0 = max8(xs), m1 = max8(ss), m2 = max8(ys), m3 = min8(ds);
-            const float m4 = min8(xs), m5 = min8(ss), m6 = min8(ys), m7 = max8(ds);
-            // maximum() propagates NaN: one test on the x+y maximum covers
-            // every NaN coordinate of the group
-            bad |= __builtin_isnan(m1);
-            if (m0 > v[0]) { v[0] = m0; grp[0] = c; }
-            if (m1 > v[1]) { v[1] = m1; grp[1] = c; }
-            if (m2 > v[2]) { v[2] = m2; grp[2] = c; }
-            if (m3 < v[3]) { v[3] = m3; grp[3] = c; }
-            if (m4 < v[4]) { v[4] = m4; grp[4] = c; }
-            if (m5 < v[5]) { v[5] = m5; grp[5] = c; }
-            if (m6 < v[6]) { v[6] = m6; grp[6] = c; }
-            if (m7 > v[7]) { v[7] = m7; grp[7] = c; }
-            if (box) {
-                const float b0 = wave_minmax_dpp<false>(m4), b1 = wave_minmax_dpp<true>(m0);
-                const float b2 = wave_minmax_dpp<false>(m6), b3 = wave_minmax_dpp<true>(m2);
-                put_box(c, make_float4(b0, b1, b2, b3));
-            }
-        } else {
-            if (box) {
-                const float qn = __builtin_nanf("");
-                put_box(c, make_float4(qn, qn, qn, qn));
-            }
-            // a partial chunk: all 2G loads issued before any is used (one
-            // memory round trip); the descriptor ends at the range's end, so
-            // loads past it read nothing, and points before lo are masked
-            const RangeView rv = range_view(pts, cb, CH, lo, hi);
-            const uint32_t tt = opaque_tid();
-            float2 pq[2 * G];
-#pragma unroll
-            for (uint32_t k = 0; k < 2 * G; ++k) {
-                const uint32_t p = 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
-                const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(rv.r, (int)(8u * p), 0, 0);
-                pq[k] = make_float2(__uint_as_float(a.x), __uint_as_float(a.y));
-            }
-#pragma unroll
-            for (uint32_t k = 0; k < 2 * G; ++k) {
-                const uint32_t p = 2u * ((k >> 1) * BLOCK + tt) + (k & 1u);
-                if (p < rv.lo_rel || p >= rv.hi_rel) continue;
-                const float x = pq[k].x, y = pq[k].y;
-                const float s = x + y, d = x - y;
-                bad |= __builtin_isnan(s);
-                if (x > v[0]) { v[0] = x; grp[0] = c; }
-                if (s > v[1]) { v[1] = s; grp[1] = c; }
-                if (y > v[2]) { v[2] = y; grp[2] = c; }
-                if (d < v[3]) { v[3] = d; grp[3] = c; }
-                if (x < v[4]) { v[4] = x; grp[4] = c; }
-                if (s < v[5]) { v[5] = s; grp[5] = c; }
-                if (y < v[6]) { v[6] = y; grp[6] = c; }
-                if (d > v[7]) { v[7] = d; grp[7] = c; }
-            }
+        };
+        float4 qa[G], qb[G];
+        issue(c0, qa);
+        for (uint32_t c = c0; c < nch; c += 2u * cstep) {
+            const uint32_t c1 = c + cstep;
+            issue(c1, qb);
+            if (full_at(c)) fold_full(c, qa);
+            else fold_partial(c);
+            if (c1 >= nch) break;
+            issue(c1 + cstep, qa);
+            if (full_at(c1)) fold_full(c1, qb);
+            else fold_partial(c1);
         }
     }
 
@@ -1918,7 +2023,7 @@ __device__ __forceinline__ uint32_t set_of(const SetInfo* __restrict__ sets, uin
 // searches, all in flight together, instead of one dependent search per
 // tile.  sh[k] holds the set of tile r0 + k * step.
 constexpr uint32_t kAhead = 64;
-constexpr uint32_t kTicketTiles = 2;   // reduction tiles per ticket (at most kAhead)
+constexpr uint32_t kTicketTiles = 2;   // reduction tiles per ticket
 __device__ __forceinline__ void sets_ahead(const SetInfo* __restrict__ sets, uint32_t S, uint32_t r0, uint32_t step,
                                            uint32_t lim, bool f, uint32_t* sh) {
     __syncthreads();   // the previous round's readers of sh are done
@@ -1927,6 +2032,24 @@ __device__ __forceinline__ void sets_ahead(const SetInfo* __restrict__ sets, uin
         sh[threadIdx.x] = (r < lim) ? set_of(sets, S, (uint32_t)r, f) : 0u;
     }
     __syncthreads();
+}
+
+// Last set s with start[s] <= k, found by one wave: each round cuts the
+// remaining range into 64 parts, one lane reads the first start of each, and
+// the last part that starts at or before k holds the answer (two rounds of
+// loads for up to 4096 sets, three up to 2^18).  Every lane returns it.
+__device__ __forceinline__ uint32_t set_of_wave(const SetInfo* __restrict__ sets, uint32_t S, uint32_t k, bool f) {
+    uint32_t lo = 0, span = S;
+    while (span > 1u) {
+        const uint32_t step = (span + 63u) >> 6;
+        const uint32_t idx = lo + lane_id() * step;
+        const bool ok = (idx < lo + span) && (f ? sets[idx].f_tile0 : sets[idx].r_tile0) <= k;
+        const uint64_t m = __ballot(ok);   // lane 0 always holds: start[lo] <= k
+        const uint32_t j = 63u - (uint32_t)__builtin_clzll(m);
+        lo += j * step;
+        span = min(step, span - j * step);
+    }
+    return lo;
 }
 
 // Exclusive scan of one value per thread over a block of 1024 threads;
@@ -2035,9 +2158,10 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict_
 }
 
 template <bool VEC4>
-// Four waves per SIMD: with the ticket and look-up state the kernel does not
-// fit 64 registers (at 8 waves per SIMD it spilled 52-68 bytes per lane
-// inside the streaming loop; 745-800 us against 640-750 us now).
+// Four waves per SIMD, 128 registers: the streaming loop keeps two chunks of
+// loads in flight per wave (two register sets) to make up for the low
+// occupancy.  At 5 or 6 waves per SIMD the kernel spills (54-124 registers),
+// and at 8 it spilled inside the streaming loop even with one chunk in flight.
 __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_reduce(
     const float2* __restrict__ pts, uint32_t S, const SetInfo* __restrict__ sets,
     BatchTotals* __restrict__ tot, unsigned long long* __restrict__ part, float4* __restrict__ box) {
@@ -2046,7 +2170,7 @@ __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
     // again instead of the grid waiting on a fixed share per block.  The
     // next ticket is drawn before the current tiles are streamed.
     const uint32_t rtiles = tot->r_tiles;
-    __shared__ uint32_t sh_set[kAhead];
+    __shared__ uint32_t sh_set[kTicketTiles];
     __shared__ uint32_t sh_tk[2];
     __shared__ unsigned long long rec[9];
     if (threadIdx.x == 0) sh_tk[0] = atomicAdd(&tot->r_next, kTicketTiles);
@@ -2055,13 +2179,23 @@ __global__ __launch_bounds__(kRBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
         const uint32_t r0 = sh_tk[round & 1u];
         if (r0 >= rtiles) break;
         if (threadIdx.x == 0) sh_tk[(round + 1) & 1u] = atomicAdd(&tot->r_next, kTicketTiles);
-        sets_ahead(sets, S, r0, 1u, rtiles, false, sh_set);
+        // the sets of this ticket's tiles, one wave per tile
+        static_assert(kTicketTiles <= kRBlock / 64, "one wave per tile of a ticket");
+        __syncthreads();   // the previous round's readers of sh_set are done
+        {
+            const uint32_t w = threadIdx.x >> 6;
+            if (w < kTicketTiles && r0 + w < rtiles) {
+                const uint32_t s = set_of_wave(sets, S, r0 + w, false);
+                if (lane_id() == 0) sh_set[w] = s;
+            }
+        }
+        __syncthreads();
         for (uint32_t k = 0; k < kTicketTiles && r0 + k < rtiles; ++k) {
             const uint32_t r = r0 + k;
             const uint32_t s = uniform_u32(sh_set[k]);
             const uint64_t b = sets[s].begin, n = sets[s].n;
             const uint64_t tb = (b & ~kBatchAlign) + (uint64_t)(r - sets[s].r_tile0) * kBatchRT;
-            reduce_points<kRBlock, kRG, VEC4, false>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec,
+            reduce_points<kRBlock, kRG, VEC4, false, true>(pts, b, b + n, tb, 0u, 1u, kBatchRChunks, rec,
                                                      box ? box + (uint64_t)r * kBatchTileBoxes : nullptr);
             if (threadIdx.x < 9) part[(uint64_t)r * 9 + threadIdx.x] = rec[threadIdx.x];
         }
