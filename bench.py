@@ -906,6 +906,26 @@ def profile_pass(args):
     ctx.close()
 
 
+def profile_batched(args):
+    """Short run for rocprofv3 counters on the batched path: the 4096-set
+    batch through hull_filter_batched, `steps` calls, each followed by a
+    synchronize (no per-set launches, so the dispatch queue stays short)."""
+    import torch
+    from paper_2303_10581_amd import hullf, workloads
+    dev = torch.device("cuda:0")
+    pts, off, _ = workloads.batch(S=4096, seed=6)
+    tp = torch.from_numpy(pts).to(dev)
+    to = torch.from_numpy(off.astype(np.int64)).to(dev)
+    surv = torch.empty(pts.shape[0], dtype=torch.int32, device=dev)
+    counts = torch.empty(off.size - 1, dtype=torch.int64, device=dev)
+    ctx = hullf.Context(0)
+    for i in range(args.steps):
+        ctx.hull_filter_batched(tp, to, surv=surv, counts=counts)
+        torch.cuda.synchronize()
+        log(f"[profile] batched call {i}: survivors {int(counts.sum().item())}")
+    ctx.close()
+
+
 def parse_pmc(directory):
     """Print FETCH_SIZE / WRITE_SIZE (bytes) per kernel dispatch from
     rocprofv3 counter_collection CSV files under `directory`."""
@@ -1042,6 +1062,8 @@ def main():
     ap.add_argument("--serve-arena", type=int, default=1 << 30)
     ap.add_argument("--serve-finish", type=int, default=4)
     ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="a few synchronized hull_filter_batched calls on the 4096-set batch (for rocprofv3)")
     ap.add_argument("--only-e2e", action="store_true",
                     help="convex_hull of each set only (hull finishing traces; not a bench line)")
     ap.add_argument("--p-sweep", action="store_true",
@@ -1063,6 +1085,9 @@ def main():
         return 2
     if args.profile_pass:
         profile_pass(args)
+        return 0
+    if args.profile_batched:
+        profile_batched(args)
         return 0
     if args.p_sweep:
         print(json.dumps(p_sweep(args)), flush=True)
